@@ -1,0 +1,189 @@
+"""Benchmark of the sampled TR-ALS hot path on one MI355X.
+
+A step is one sweep of Algorithm 2 (every core updated once: sample, sketch,
+gather, normal equations, solve, new leverage table) over the default
+workload, a 500 x 500 x 500 FP32 tensor built from random rank-(10,10,10)
+TR cores plus 1% Gaussian noise, with J = 8192 samples per update (the
+paper's synthetic-tensor experiment shape, Section 4.1.1).
+
+Prints one JSON line: sampled rows/s (J * N rows per sweep), sweeps/s,
+per-update latency percentiles, the dominant kernel's roofline (HIP events on
+the library's stream) and the FP64 oracle's rate on a bounded sample of the
+same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
+PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_2010_08581_amd", "csrc"))):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(ROOT, "paper_2010_08581_amd", "csrc", fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "contract_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("workload") != workload:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(X, init, cfg, budget_s):
+    """FP64 oracle (test infrastructure) on a bounded number of updates."""
+    from oracle import als as oals
+    from oracle.leverage import core_table
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = None
+    X64 = X.astype(np.float64)
+    N = X.ndim
+    J = cfg["samples"]
+    cores = [np.array(c, dtype=np.float64) for c in init]
+    tables = [None] + [core_table(cores[m]) for m in range(1, N)]
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        n = done % N
+        cores[n], _, _ = oals.sampled_update(X64, cores, tables, n, J, cfg["seed"], 0, done)
+        tables[n] = core_table(cores[n])
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cores_used = len(os.sched_getaffinity(0))
+    return {
+        "value": J * done / dt, "unit": "rows/s", "cores": blas_threads or cores_used, "kind": "oracle",
+        "sample": f"{done} core updates (J={J}) of the same workload from the same initial cores, "
+                  f"numpy FP64, {dt:.1f} s; host has {cores_used} usable cores",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--latency-updates", type=int, default=60)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the method runs on one GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2010_08581_amd import TRALS
+
+    cfg = dict(synth.CONFIGS[args.config])
+    dims, ranks, J, prec = cfg["dims"], cfg["ranks"], cfg["samples"], cfg["precision"]
+    N = len(dims)
+    log(f"generating {cfg['name']} {dims} ranks {ranks}")
+    t = time.perf_counter()
+    X, _, init = synth.make_config(args.config, dtype=np.float64 if prec == "f64" else np.float32)
+    log(f"generated in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    Xt = torch.from_numpy(X).to(dev)
+    h = TRALS(Xt, ranks, J, seed=cfg["seed"], precision=prec, init_cores=init)
+    del Xt
+    torch.cuda.synchronize()
+    log("handle created")
+    if args.warmup:
+        h.sweep(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} sweeps done")
+
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.sweep(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    kern = {}
+    for k in ("sample", "sketch", "contract", "reduce", "solve", "table"):
+        ms, cnt = h.profile_read(k)
+        kern[k] = {"ms_per_launch": ms / max(cnt, 1), "launches": cnt}
+    h.profile(False)
+    log(f"timed {args.steps} sweeps in {elapsed:.3f} s")
+
+    # per-update latency (one core update = sample + sketch + normal equations + solve + table)
+    lat = []
+    for _ in range(args.latency_updates):
+        a = time.perf_counter()
+        h.step(1)
+        lat.append(time.perf_counter() - a)
+    lat_us = np.array(lat) * 1e6
+    fit = h.fit_error()
+    log(f"latency done, fit {fit:.4e}")
+
+    rows = J * N * args.steps
+    value = rows / elapsed
+    esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+    P = [ranks[(n - 1) % N] * ranks[n] for n in range(N)]
+    # dominant kernel: fused fiber gather + A^T X~ (all modes of this workload have the same shape)
+    avg_s = kern["contract"]["ms_per_launch"] * 1e-3
+    flops = np.mean([2.0 * J * P[n] * dims[n] for n in range(N)])
+    gbytes = np.mean([J * dims[n] * esz for n in range(N)])
+    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[prec]
+    achieved = flops / avg_s / 1e12
+    traffic = measured_traffic(cfg["name"])
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic, "kernel": "contract (gather + A^T X~)",
+                "gather_GBps": gbytes / avg_s / 1e9}
+    bytes_sweep = J * sum(dims) * esz
+    out = {
+        "metric": "sampled ALS rows/s", "value": value, "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "dims": list(dims), "ranks": list(ranks), "samples": J,
+                   "noise": f"{cfg['noise'][0]} {cfg['noise'][1]}", "seed": cfg["seed"],
+                   "step": "one sweep (N core updates)"},
+        "sweeps_per_s": args.steps / elapsed,
+        "hbm_frac": bytes_sweep / (elapsed / args.steps) / (PEAK_HBM_GBS * 1e9),
+        "update_latency_us": {"p50": float(np.percentile(lat_us, 50)), "p99": float(np.percentile(lat_us, 99))},
+        "fit_error": fit,
+        "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in kern.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(X, init, cfg, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

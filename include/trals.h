@@ -1,0 +1,150 @@
+/*
+ * trals.h -- C ABI of the MI355X (gfx950) sampled tensor-ring ALS library.
+ *
+ * The library fits a tensor ring (TR) decomposition X ~ TR(G^(0..N-1)) to a
+ * dense N-way tensor by leverage-score-sampled alternating least squares
+ * (Malik & Becker, ICML 2021, Algorithm 2 "TR-ALS-Sampled").  Per core update
+ * n it draws J index tuples from the product of the other cores' leverage
+ * distributions (Algorithm 3, eqs. (3)-(4)), forms the J sampled rows of the
+ * design matrix from lateral-slice products (Algorithm 4, eq. (5)), gathers
+ * the J sampled mode-n fibers of X (Algorithm 2, "sample X"), solves the
+ * sampled least-squares problem (Algorithm 2, LS step) and recomputes the
+ * leverage distribution of the new core (eq. (3)).
+ *
+ * Conventions
+ *  - Indices are 0-based.  X is a C-order array X[i_0, ..., i_{N-1}] (last
+ *    index fastest), which differs from the paper's first-index-fastest
+ *    linearisation (Section 2); only the row order of the sampled systems
+ *    depends on it, not their solution.
+ *  - Core n has shape (R[(n+N-1)%N], I[n], R[n]) (Section 2.1: ring closure
+ *    R_0 = R_N).  The cores exchanged through this ABI are stored one after
+ *    the other, each in C order.
+ *  - All pointers named *_dev are device pointers on the current HIP device.
+ *    Host arrays are read during the call only.
+ *  - Every call returns a trals_status (0 on success) and never throws.
+ *  - Asynchrony: trals_create, trals_sweep and trals_step enqueue work on the
+ *    caller's stream.  trals_sweep/trals_step synchronise that stream once at
+ *    the end to report a failed solve; trals_fit_error, trals_get_cores and
+ *    trals_get_last_samples synchronise it as well.
+ *  - A handle must not be used from two threads at once.
+ *  - The workspace is owned by the caller, must stay allocated until
+ *    trals_destroy, and is used for everything the handle keeps on the GPU
+ *    (data panels, cores, sampling tables, samples, partial sums).  The
+ *    library itself allocates no device memory.
+ */
+#ifndef TRALS_H
+#define TRALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct trals_ctx* trals_handle;
+
+typedef enum {
+  TRALS_OK = 0,
+  TRALS_EINVAL = -1,     /* bad argument: shape, rank, J, dtype, NaN/Inf in X, small workspace */
+  TRALS_ENOMEM = -2,     /* host allocation failed */
+  TRALS_ESINGULAR = -3,  /* sampled normal equations or a core's Gram not positive definite;
+                            the core being updated is left unchanged */
+  TRALS_EHIP = -4,       /* a HIP runtime call failed */
+  TRALS_ESTATE = -5      /* handle is in a failed state (reset it with trals_set_cores) */
+} trals_status;
+
+typedef enum {
+  TRALS_F64 = 0,   /* IEEE double */
+  TRALS_F32 = 1,   /* IEEE single */
+  TRALS_BF16 = 2   /* bfloat16 (precision TRALS_BF16 selects the BF16 form: BF16 data panels
+                      and sketch on matrix cores with FP32 accumulation, FP64 Gram/Cholesky) */
+} trals_dtype;
+
+/* Problem description (Algorithm 2 inputs: X, target ranks; J per update; seed). */
+typedef struct {
+  int32_t order;           /* N, 2 <= N <= 16 */
+  const int64_t* dims;     /* host array I[0..N-1], each in [1, 2^21] */
+  const int32_t* ranks;    /* host array R[0..N-1], each in [1, 32]; core n is R[n-1] x I[n] x R[n] */
+  int64_t samples;         /* J in [max_n R[n-1]*R[n], 2^24] (fewer rows cannot give a full-rank system) */
+  uint64_t seed;           /* Philox4x64-10 key word 0 */
+  uint64_t stream_id;      /* Philox4x64-10 key word 1 (independent problems use distinct ids) */
+  int32_t precision;       /* TRALS_F64, TRALS_F32 or TRALS_BF16 */
+  const void* init_cores;  /* optional device pointer to all N cores (layout above), element type
+                              init_dtype; NULL draws every entry iid N(0,1) (Section 3) from the seed */
+  int32_t init_dtype;      /* TRALS_F64 or TRALS_F32 */
+} trals_desc;
+
+/* Bytes of device workspace trals_create needs for this description.
+ * Pure host computation.  Returns TRALS_EINVAL for an invalid description. */
+int trals_workspace_bytes(const trals_desc* desc, size_t* bytes);
+
+/* Build a handle: validates desc, copies X into per-mode data panels inside the
+ * workspace (X may be freed afterwards), loads or draws the initial cores and
+ * computes the sampling tables of cores 1..N-1 (Algorithm 2, first two steps).
+ * X_dev: device pointer to prod(I) elements of type x_dtype (TRALS_F64 or TRALS_F32).
+ * stream: a hipStream_t (NULL = default stream), borrowed for the handle's lifetime.
+ * Fails with TRALS_EINVAL on NaN/Inf in X or a workspace smaller than
+ * trals_workspace_bytes(desc). */
+int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, void* ws_dev,
+                 size_t ws_bytes, void* stream, trals_handle* out);
+
+/* Run n_sweeps outer iterations of Algorithm 2 (each updates cores 0..N-1 in
+ * order), continuing from the handle's update counter. */
+int trals_sweep(trals_handle h, int32_t n_sweeps);
+
+/* Run n_updates single core updates (inner iterations of Algorithm 2),
+ * continuing from the update counter; core n = counter mod N is updated next. */
+int trals_step(trals_handle h, int32_t n_updates);
+
+/* Relative error ||TR(G) - X||_F / ||X||_F (Section 4.1) over every entry of X,
+ * with FP64 accumulation.  Synchronises the stream. */
+int trals_fit_error(trals_handle h, double* rel_err);
+
+/* Release the handle (not the workspace).  NULL is a no-op. */
+int trals_destroy(trals_handle h);
+
+/* Copy all cores out to / in from dst_dev / src_dev (layout above, element type
+ * dtype = TRALS_F64 or TRALS_F32).  trals_set_cores recomputes every sampling
+ * table and clears a failed state; it does not change the update counter. */
+int trals_get_cores(trals_handle h, void* dst_dev, int32_t dtype);
+int trals_set_cores(trals_handle h, const void* src_dev, int32_t dtype);
+
+/* Samples of the most recent update (host arrays): idx_host[j*(N-1)+k] is the
+ * index drawn in mode (n+1+k) mod N for sample j, w_host[j] the Definition 5
+ * rescaling 1/sqrt(J q_j).  Either pointer may be NULL.  TRALS_ESTATE before
+ * the first update. */
+int trals_get_last_samples(trals_handle h, int32_t* idx_host, double* w_host);
+
+/* Number of core updates run so far (sweeps * N + position in the sweep). */
+int64_t trals_update_counter(trals_handle h);
+
+/* Set the update counter (used to resume a run from saved cores); the next
+ * update is core counter mod N and draws from that counter's Philox stream. */
+int trals_set_update_counter(trals_handle h, int64_t counter);
+
+/* Kernel timing with HIP events, recorded on the handle's stream around each
+ * launch of the kernel groups below (for measurement; off by default).
+ * trals_profile_read synchronises the stream and returns the summed duration
+ * and launch count of one group since profiling was enabled, then keeps
+ * accumulating. */
+typedef enum {
+  TRALS_K_SAMPLE = 0,    /* Algorithm 3 sampler */
+  TRALS_K_SKETCH = 1,    /* Algorithm 4 sketched design rows */
+  TRALS_K_REDUCE = 2,    /* fixed-order reduction of the split-K partials of H and B */
+  TRALS_K_CONTRACT = 3,  /* fused fiber gather + [A^T A | A^T X~] partials (matrix cores) */
+  TRALS_K_SOLVE = 4,     /* SPD inverse of H, Z = H^{-1} B, core write */
+  TRALS_K_TABLE = 5,     /* new core's leverage table */
+  TRALS_K_COUNT = 6
+} trals_kernel;
+int trals_profile(trals_handle h, int32_t enable);
+int trals_profile_read(trals_handle h, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* trals_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRALS_H */

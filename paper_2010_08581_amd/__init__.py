@@ -1,0 +1,133 @@
+"""Leverage-score-sampled tensor-ring ALS on MI355X (gfx950).
+
+``TRALS`` wraps one handle of the C ABI (``include/trals.h``).  PyTorch
+supplies the device memory (the caller-owned workspace, the data tensor,
+core buffers) and the stream; every step of the method runs in the library's
+HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import TRALS_F32, TRALS_F64, TRALS_BF16, TralsError  # noqa: F401
+
+_PREC = {"f64": TRALS_F64, "f32": TRALS_F32, "bf16": TRALS_BF16}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class TRALS:
+    """One sampled TR-ALS problem held on the GPU.
+
+    X: CUDA tensor (float32 or float64), C order.  ranks: R[0..N-1] (core n is
+    R[n-1] x I[n] x R[n]).  samples: J per core update.  precision: "f64",
+    "f32" or "bf16".  init_cores: optional list of N tensors (any device) of
+    shapes (R[n-1], I[n], R[n]); None draws N(0,1) entries on the GPU.
+    """
+
+    def __init__(self, X, ranks, samples, seed=0, stream_id=0, precision="f32", init_cores=None,
+                 stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        if not X.is_cuda:
+            raise ValueError("X must be a CUDA tensor")
+        X = X.contiguous()
+        self.dims = tuple(int(v) for v in X.shape)
+        self.ranks = tuple(int(v) for v in ranks)
+        self.N = len(self.dims)
+        self.J = int(samples)
+        self.precision = precision
+        self.device = X.device
+        self.stream = torch.cuda.current_stream(X.device) if stream is None else stream
+        xdt = {torch.float64: TRALS_F64, torch.float32: TRALS_F32}[X.dtype]
+        init_ptr, init_dt, init_buf = None, TRALS_F64, None
+        if init_cores is not None:
+            init_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+                                  .to(device=X.device, dtype=torch.float64).reshape(-1) for c in init_cores])
+            init_ptr = init_buf.data_ptr()
+        desc, self._keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
+                                          init_ptr, init_dt)
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.trals_workspace_bytes(C.byref(desc), C.byref(nbytes)), "trals_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=X.device)
+        h = C.c_void_p(0)
+        _lib.check(self.lib.trals_create(C.byref(desc), C.c_void_p(X.data_ptr()), xdt,
+                                         C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)), "trals_create")
+        self.h = h
+        self.core_shapes = [(self.ranks[(n - 1) % self.N], self.dims[n], self.ranks[n]) for n in range(self.N)]
+
+    # -- driving the iteration --
+    def sweep(self, n=1):
+        _lib.check(self.lib.trals_sweep(self.h, int(n)), "trals_sweep")
+
+    def step(self, n=1):
+        _lib.check(self.lib.trals_step(self.h, int(n)), "trals_step")
+
+    def fit_error(self) -> float:
+        out = C.c_double(0.0)
+        _lib.check(self.lib.trals_fit_error(self.h, C.byref(out)), "trals_fit_error")
+        return float(out.value)
+
+    @property
+    def update_counter(self) -> int:
+        return int(self.lib.trals_update_counter(self.h))
+
+    @update_counter.setter
+    def update_counter(self, v):
+        _lib.check(self.lib.trals_set_update_counter(self.h, int(v)), "trals_set_update_counter")
+
+    # -- state --
+    def get_cores(self, dtype=None):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        total = sum(a * b * c for a, b, c in self.core_shapes)
+        buf = torch.empty(total, dtype=dtype, device=self.device)
+        code = TRALS_F64 if dtype == torch.float64 else TRALS_F32
+        _lib.check(self.lib.trals_get_cores(self.h, C.c_void_p(buf.data_ptr()), code), "trals_get_cores")
+        out, off = [], 0
+        for s in self.core_shapes:
+            cnt = s[0] * s[1] * s[2]
+            out.append(buf[off:off + cnt].reshape(s))
+            off += cnt
+        return out
+
+    def set_cores(self, cores):
+        torch = _torch()
+        buf = torch.cat([torch.as_tensor(c).to(device=self.device, dtype=torch.float64).reshape(-1) for c in cores])
+        _lib.check(self.lib.trals_set_cores(self.h, C.c_void_p(buf.data_ptr()), TRALS_F64), "trals_set_cores")
+
+    def last_samples(self):
+        idx = np.empty((self.J, self.N - 1), dtype=np.int32)
+        w = np.empty(self.J, dtype=np.float64)
+        _lib.check(self.lib.trals_get_last_samples(self.h, idx.ctypes.data_as(C.c_void_p),
+                                                   w.ctypes.data_as(C.c_void_p)), "trals_get_last_samples")
+        return idx, w
+
+    def profile(self, enable=True):
+        """Time every kernel group with HIP events on the handle's stream."""
+        _lib.check(self.lib.trals_profile(self.h, int(bool(enable))), "trals_profile")
+
+    def profile_read(self, kernel):
+        """(total ms, launches) of a kernel group since profiling was enabled."""
+        ms, cnt = C.c_double(0.0), C.c_int64(0)
+        _lib.check(self.lib.trals_profile_read(self.h, _lib.KERNELS[kernel], C.byref(ms), C.byref(cnt)),
+                   "trals_profile_read")
+        return float(ms.value), int(cnt.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.trals_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

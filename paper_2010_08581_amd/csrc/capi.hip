@@ -1,0 +1,545 @@
+// Host runtime behind the C ABI declared in include/trals.h: argument validation, workspace
+// carving, and the per-update launch sequence of Algorithm 2 (sample -> sketch -> normal
+// equations -> solve -> new sampling table).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/trals.h"
+#include "kernels.h"
+
+using namespace trals;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t panel[kMaxOrder];
+  size_t core[kMaxOrder];
+  size_t cdf[kMaxOrder];
+  size_t idx, w, A, Hpart, Bpart, Bred, M, W, partial, scal, total;
+  int64_t partial_count;
+};
+
+struct Problem {
+  int N;
+  int64_t dims[kMaxOrder];
+  int32_t ranks[kMaxOrder];
+  int64_t J;
+  uint64_t seed, stream_id;
+  int prec;
+  int real_dt, panel_dt;
+  size_t real_sz, panel_sz;
+  int64_t E;     // prod dims
+  int Pmax;
+  int64_t Imax;
+};
+
+int P_of(const Problem& p, int n) { return p.ranks[(n + p.N - 1) % p.N] * p.ranks[n]; }
+
+int validate(const trals_desc* d, Problem* p) {
+  if (!d || !d->dims || !d->ranks) return TRALS_EINVAL;
+  if (d->order < 2 || d->order > kMaxOrder) return TRALS_EINVAL;
+  if (d->precision != TRALS_F64 && d->precision != TRALS_F32) return TRALS_EINVAL;
+  memset(p, 0, sizeof(*p));
+  p->N = d->order;
+  p->E = 1;
+  for (int n = 0; n < p->N; ++n) {
+    if (d->dims[n] < 1 || d->dims[n] > (int64_t)1 << 21) return TRALS_EINVAL;  // grid-y limit of the contraction
+    if (d->ranks[n] < 1 || d->ranks[n] > kMaxRank) return TRALS_EINVAL;
+    p->dims[n] = d->dims[n];
+    p->ranks[n] = d->ranks[n];
+    if (p->E > ((int64_t)1 << 40) / d->dims[n]) return TRALS_EINVAL;
+    p->E *= d->dims[n];
+  }
+  p->J = d->samples;
+  p->Pmax = 0;
+  p->Imax = 0;
+  for (int n = 0; n < p->N; ++n) {
+    p->Pmax = P_of(*p, n) > p->Pmax ? P_of(*p, n) : p->Pmax;
+    p->Imax = p->dims[n] > p->Imax ? p->dims[n] : p->Imax;
+  }
+  if (p->J < p->Pmax || p->J > ((int64_t)1 << 24)) return TRALS_EINVAL;  // grid-z limit of the split-K partials
+  p->seed = d->seed;
+  p->stream_id = d->stream_id;
+  p->prec = d->precision;
+  p->real_dt = p->prec == TRALS_F64 ? 0 : 1;
+  p->panel_dt = p->real_dt;
+  p->real_sz = p->real_dt == 0 ? 8 : 4;
+  p->panel_sz = p->real_sz;
+  if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
+  return TRALS_OK;
+}
+
+constexpr int kFitRows = 8;  // rows per block of the fit kernel
+constexpr int kScanBlocks = 1024;
+
+void plan(const Problem& p, Layout* L) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  for (int n = 0; n < p.N; ++n) L->panel[n] = take((size_t)p.E * p.panel_sz);
+  for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * p.real_sz);
+  for (int n = 0; n < p.N; ++n) L->cdf[n] = take((size_t)p.dims[n] * 8);
+  size_t hpart = 0, bpart = 0;
+  for (int n = 0; n < p.N; ++n) {
+    const int P = P_of(p, n);
+    const NormalEqPlan pl = plan_normal_eq(P, (int)p.dims[n], p.J, (int)p.panel_sz, kPlanCUs);
+    const size_t h = (size_t)pl.splits * P * P, b = (size_t)pl.splits * P * p.dims[n];
+    hpart = h > hpart ? h : hpart;
+    bpart = b > bpart ? b : bpart;
+  }
+  L->idx = take((size_t)p.J * (p.N - 1) * 4);
+  L->w = take((size_t)p.J * 8);
+  L->A = take((size_t)p.J * p.Pmax * p.real_sz);
+  L->Hpart = take(hpart * 8);  // FP64 split-K partials
+  L->Bpart = take(bpart * 8);
+  L->Bred = take((size_t)p.Pmax * p.Imax * 8);
+  L->M = take((size_t)p.Pmax * p.Pmax * 8);
+  L->W = take((size_t)p.Pmax * p.Pmax * 8);
+  const int64_t fit_rows = p.E / p.dims[p.N - 1];
+  const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
+  L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
+  L->partial = take((size_t)L->partial_count * 8);
+  L->scal = take(64);  // [0] double result, [1] u64 nonfinite, [2] int status
+  L->total = off;
+}
+
+}  // namespace
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev[TRALS_K_COUNT];
+  size_t used[TRALS_K_COUNT] = {};
+  double ms[TRALS_K_COUNT] = {};
+  int64_t count[TRALS_K_COUNT] = {};
+};
+
+struct trals_ctx {
+  Prof prof;
+  Problem p;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t upd = 0;
+  bool failed = false;
+  bool table_valid[kMaxOrder] = {};
+  bool have_last = false;
+  double xnorm2 = 0.0;
+  hipError_t last_hip = hipSuccess;
+
+  template <typename T>
+  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+  int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
+  double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
+  unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
+};
+
+#define HIPTRY(expr)                      \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) {               \
+      h->last_hip = e_;                   \
+      return TRALS_EHIP;                  \
+    }                                     \
+  } while (0)
+
+namespace {
+
+hipError_t prof_mark(trals_ctx* h, int k, int which) {
+  if (!h->prof.on) return hipSuccess;
+  Prof& pr = h->prof;
+  const size_t slot = 2 * pr.used[k] + which;
+  while (pr.ev[k].size() <= slot) {
+    hipEvent_t e;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pr.ev[k].push_back(e);
+  }
+  const hipError_t r = hipEventRecord(pr.ev[k][slot], h->stream);
+  if (which == 1) pr.used[k] += 1;
+  return r;
+}
+
+#define PROF_BEGIN(k) HIPTRY(prof_mark(h, (k), 0))
+#define PROF_END(k) HIPTRY(prof_mark(h, (k), 1))
+
+Ring make_ring(const Problem& p) {
+  Ring g;
+  memset(&g, 0, sizeof(g));
+  g.N = p.N;
+  for (int n = 0; n < p.N; ++n) {
+    g.dims[n] = (int)p.dims[n];
+    g.ranks[n] = p.ranks[n];
+  }
+  return g;
+}
+
+int compute_table(trals_ctx* h, int m) {
+  const Problem& p = h->p;
+  const int P = P_of(p, m);
+  const int I = (int)p.dims[m];
+  uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
+  void* core = h->at<void>(h->L.core[m]);
+  PROF_BEGIN(TRALS_K_TABLE);
+  if (I > P) {
+    double* M = h->at<double>(h->L.M);
+    double* W = h->at<double>(h->L.W);
+    HIPTRY(launch_lev_gram(core, p.real_dt, I, P, M, h->status(), h->stream));
+    HIPTRY(launch_spd_inverse(nullptr, 0, P, M, W, h->status(), h->stream));
+    HIPTRY(launch_lev_rows(core, p.real_dt, I, P, M, Q, h->status(), h->stream));
+  } else {
+    HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
+  }
+  HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
+  PROF_END(TRALS_K_TABLE);
+  h->table_valid[m] = true;
+  return TRALS_OK;
+}
+
+int run_update(trals_ctx* h) {
+  const Problem& p = h->p;
+  const int N = p.N;
+  const int n = (int)(h->upd % N);
+  for (int m = 0; m < N; ++m)
+    if (m != n && !h->table_valid[m]) {
+      const int rc = compute_table(h, m);
+      if (rc) return rc;
+    }
+  const Ring ring = make_ring(p);
+  const int P = P_of(p, n);
+  const int In = (int)p.dims[n];
+
+  SampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.ring = ring;
+  sa.n = n;
+  sa.J = p.J;
+  sa.seed = p.seed;
+  sa.stream_id = p.stream_id;
+  sa.u = (uint64_t)h->upd;
+  for (int m = 0; m < N; ++m) sa.cdf.p[m] = h->at<const uint64_t>(h->L.cdf[m]);
+  sa.idx = h->at<int32_t>(h->L.idx);
+  sa.w = h->at<double>(h->L.w);
+  sa.status = h->status();
+  PROF_BEGIN(TRALS_K_SAMPLE);
+  HIPTRY(launch_sample(sa, h->stream));
+  PROF_END(TRALS_K_SAMPLE);
+
+  SketchArgs ka;
+  memset(&ka, 0, sizeof(ka));
+  ka.ring = ring;
+  ka.n = n;
+  ka.J = p.J;
+  for (int m = 0; m < N; ++m) ka.cores.p[m] = h->at<const void>(h->L.core[m]);
+  ka.idx = sa.idx;
+  ka.w = sa.w;
+  ka.A = h->at<void>(h->L.A);
+  ka.status = h->status();
+  PROF_BEGIN(TRALS_K_SKETCH);
+  HIPTRY(launch_sketch(ka, p.real_dt, h->stream));
+  PROF_END(TRALS_K_SKETCH);
+
+  const NormalEqPlan pl = plan_normal_eq(P, In, p.J, (int)p.panel_sz, kPlanCUs);
+  NormalEqArgs na;
+  memset(&na, 0, sizeof(na));
+  na.A = ka.A;
+  na.panel = h->at<const void>(h->L.panel[n]);
+  na.idx = sa.idx;
+  na.w = sa.w;
+  // panel rows are the other modes in C order: stride of mode m = prod_{m' > m, m' != n} I_m'
+  for (int k = 0; k < N - 1; ++k) {
+    const int m = (n + 1 + k) % N;
+    int64_t st = 1;
+    for (int m2 = m + 1; m2 < N; ++m2)
+      if (m2 != n) st *= p.dims[m2];
+    na.stride[k] = st;
+  }
+  na.K = N - 1;
+  na.J = p.J;
+  na.chunk = pl.chunk;
+  na.P = P;
+  na.In = In;
+  na.gram_tiles = pl.gram_tiles;
+  na.Hpart = h->at<double>(h->L.Hpart);
+  na.Bpart = h->at<double>(h->L.Bpart);
+  na.status = h->status();
+  PROF_BEGIN(TRALS_K_CONTRACT);
+  HIPTRY(launch_normal_eq(na, pl, p.real_dt, h->stream));
+  PROF_END(TRALS_K_CONTRACT);
+
+  double* M = h->at<double>(h->L.M);
+  double* W = h->at<double>(h->L.W);
+  double* Bred = h->at<double>(h->L.Bred);
+  PROF_BEGIN(TRALS_K_REDUCE);
+  HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
+  HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 0, Bred, h->status(), h->stream));
+  PROF_END(TRALS_K_REDUCE);
+  PROF_BEGIN(TRALS_K_SOLVE);
+  HIPTRY(launch_spd_inverse(nullptr, 0, P, M, W, h->status(), h->stream));
+  HIPTRY(launch_solve(M, Bred, 1, P, In, h->at<void>(h->L.core[n]), p.real_dt, h->status(), h->stream));
+  PROF_END(TRALS_K_SOLVE);
+  h->table_valid[n] = false;
+  const int rc = compute_table(h, n);
+  if (rc) return rc;
+  h->upd += 1;
+  h->have_last = true;
+  return TRALS_OK;
+}
+
+int sync_status(trals_ctx* h) {
+  int st = 0;
+  HIPTRY(hipMemcpyAsync(&st, h->status(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  if (st != kDevOk) {
+    h->failed = true;
+    return TRALS_ESINGULAR;
+  }
+  return TRALS_OK;
+}
+
+int load_cores(trals_ctx* h, const void* src, int dtype) {
+  const Problem& p = h->p;
+  const size_t esz = dtype == TRALS_F64 ? 8 : 4;
+  size_t off = 0;
+  for (int n = 0; n < p.N; ++n) {
+    const int Rp = p.ranks[(n + p.N - 1) % p.N], Rn = p.ranks[n];
+    const int I = (int)p.dims[n];
+    HIPTRY(launch_core_import((const char*)src + off, dtype == TRALS_F64 ? 0 : 1, h->at<void>(h->L.core[n]),
+                              p.real_dt, Rp, I, Rn, h->stream));
+    off += (size_t)Rp * I * Rn * esz;
+  }
+  return TRALS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* trals_strerror(int code) {
+  switch (code) {
+    case TRALS_OK: return "ok";
+    case TRALS_EINVAL: return "invalid argument";
+    case TRALS_ENOMEM: return "out of host memory";
+    case TRALS_ESINGULAR: return "sampled normal equations or core Gram not positive definite";
+    case TRALS_EHIP: return "HIP runtime error";
+    case TRALS_ESTATE: return "handle in a failed or incomplete state";
+    default: return "unknown status";
+  }
+}
+
+int trals_workspace_bytes(const trals_desc* desc, size_t* bytes) {
+  if (!bytes) return TRALS_EINVAL;
+  Problem p;
+  const int rc = validate(desc, &p);
+  if (rc) return rc;
+  Layout L;
+  plan(p, &L);
+  *bytes = L.total;
+  return TRALS_OK;
+}
+
+int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, void* ws_dev, size_t ws_bytes,
+                 void* stream, trals_handle* out) {
+  if (!out) return TRALS_EINVAL;
+  *out = nullptr;
+  Problem p;
+  int rc = validate(desc, &p);
+  if (rc) return rc;
+  if (!X_dev || !ws_dev || (x_dtype != TRALS_F64 && x_dtype != TRALS_F32)) return TRALS_EINVAL;
+  if (((uintptr_t)ws_dev) % kAlign) return TRALS_EINVAL;
+  Layout L;
+  plan(p, &L);
+  if (ws_bytes < L.total) return TRALS_EINVAL;
+  trals_ctx* h = new (std::nothrow) trals_ctx();
+  if (!h) return TRALS_ENOMEM;
+  h->p = p;
+  h->L = L;
+  h->ws = (char*)ws_dev;
+  h->stream = (hipStream_t)stream;
+  rc = [&]() -> int {
+    HIPTRY(hipMemsetAsync(h->ws + L.scal, 0, 64, h->stream));
+    // norm and finiteness of X
+    HIPTRY(launch_scan_x(X_dev, x_dtype, p.E, h->at<double>(L.partial), kScanBlocks, h->nonfinite(), h->stream));
+    HIPTRY(launch_sum_partials(h->at<double>(L.partial), kScanBlocks, h->scal_d(), h->stream));
+    double x2 = 0.0;
+    unsigned long long bad = 0;
+    HIPTRY(hipMemcpyAsync(&x2, h->scal_d(), 8, hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipMemcpyAsync(&bad, h->nonfinite(), 8, hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if (bad) return TRALS_EINVAL;
+    if (!(x2 > 0.0)) return TRALS_EINVAL;
+    h->xnorm2 = x2;
+    // per-mode panels (mode n contiguous)
+    for (int n = 0; n < p.N; ++n) {
+      int64_t A = 1, B = 1;
+      for (int k = 0; k < n; ++k) A *= p.dims[k];
+      for (int k = n + 1; k < p.N; ++k) B *= p.dims[k];
+      HIPTRY(launch_panel(X_dev, x_dtype, h->at<void>(L.panel[n]), p.panel_dt, A, p.dims[n], B, h->stream));
+    }
+    if (desc->init_cores) {
+      const int r2 = load_cores(h, desc->init_cores, desc->init_dtype);
+      if (r2) return r2;
+    } else {
+      for (int n = 0; n < p.N; ++n) {
+        const int64_t cnt = (int64_t)p.dims[n] * P_of(p, n);
+        HIPTRY(launch_core_normal(h->at<void>(L.core[n]), p.real_dt, cnt, p.seed, p.stream_id, n, h->stream));
+      }
+    }
+    for (int m = 1; m < p.N; ++m) {
+      const int r3 = compute_table(h, m);
+      if (r3) return r3;
+    }
+    return sync_status(h);
+  }();
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return TRALS_OK;
+}
+
+static int run_updates(trals_ctx* h, int64_t count) {
+  if (!h) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  if (count < 0) return TRALS_EINVAL;
+  for (int64_t u = 0; u < count; ++u) {
+    const int rc = run_update(h);
+    if (rc) {
+      h->failed = true;
+      return rc;
+    }
+  }
+  return sync_status(h);
+}
+
+int trals_sweep(trals_handle h, int32_t n_sweeps) {
+  if (!h) return TRALS_EINVAL;
+  return run_updates(h, (int64_t)n_sweeps * h->p.N);
+}
+
+int trals_step(trals_handle h, int32_t n_updates) { return run_updates(h, n_updates); }
+
+int trals_fit_error(trals_handle h, double* rel_err) {
+  if (!h || !rel_err) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  const Problem& p = h->p;
+  FitArgs fa;
+  memset(&fa, 0, sizeof(fa));
+  fa.ring = make_ring(p);
+  for (int m = 0; m < p.N; ++m) fa.cores.p[m] = h->at<const void>(h->L.core[m]);
+  fa.X = h->at<const void>(h->L.panel[p.N - 1]);
+  fa.rows = p.E / p.dims[p.N - 1];
+  fa.partial = h->at<double>(h->L.partial);
+  int nb = 0;
+  HIPTRY(launch_fit(fa, p.real_dt, p.panel_dt, &nb, h->stream));
+  HIPTRY(launch_sum_partials(fa.partial, nb, h->scal_d(), h->stream));
+  double r2 = 0.0;
+  HIPTRY(hipMemcpyAsync(&r2, h->scal_d(), 8, hipMemcpyDeviceToHost, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  *rel_err = sqrt(r2 / h->xnorm2);
+  return TRALS_OK;
+}
+
+int trals_destroy(trals_handle h) {
+  if (!h) return TRALS_OK;
+  for (auto& v : h->prof.ev)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  delete h;
+  return TRALS_OK;
+}
+
+int trals_profile(trals_handle h, int32_t enable) {
+  if (!h) return TRALS_EINVAL;
+  HIPTRY(hipStreamSynchronize(h->stream));
+  h->prof.on = enable != 0;
+  for (int k = 0; k < TRALS_K_COUNT; ++k) {
+    h->prof.used[k] = 0;
+    h->prof.ms[k] = 0.0;
+    h->prof.count[k] = 0;
+  }
+  return TRALS_OK;
+}
+
+int trals_profile_read(trals_handle h, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!h || kernel < 0 || kernel >= TRALS_K_COUNT) return TRALS_EINVAL;
+  HIPTRY(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < TRALS_K_COUNT; ++k) {
+    Prof& pr = h->prof;
+    for (size_t i = 0; i < pr.used[k]; ++i) {
+      float ms = 0.f;
+      HIPTRY(hipEventElapsedTime(&ms, pr.ev[k][2 * i], pr.ev[k][2 * i + 1]));
+      pr.ms[k] += ms;
+      pr.count[k] += 1;
+    }
+    pr.used[k] = 0;
+  }
+  if (total_ms) *total_ms = h->prof.ms[kernel];
+  if (launches) *launches = h->prof.count[kernel];
+  return TRALS_OK;
+}
+
+int trals_get_cores(trals_handle h, void* dst_dev, int32_t dtype) {
+  if (!h || !dst_dev || (dtype != TRALS_F64 && dtype != TRALS_F32)) return TRALS_EINVAL;
+  const Problem& p = h->p;
+  const size_t esz = dtype == TRALS_F64 ? 8 : 4;
+  size_t off = 0;
+  for (int n = 0; n < p.N; ++n) {
+    const int Rp = p.ranks[(n + p.N - 1) % p.N], Rn = p.ranks[n];
+    const int I = (int)p.dims[n];
+    HIPTRY(launch_core_export(h->at<const void>(h->L.core[n]), p.real_dt, (char*)dst_dev + off,
+                              dtype == TRALS_F64 ? 0 : 1, Rp, I, Rn, h->stream));
+    off += (size_t)Rp * I * Rn * esz;
+  }
+  HIPTRY(hipStreamSynchronize(h->stream));
+  return TRALS_OK;
+}
+
+int trals_set_cores(trals_handle h, const void* src_dev, int32_t dtype) {
+  if (!h || !src_dev || (dtype != TRALS_F64 && dtype != TRALS_F32)) return TRALS_EINVAL;
+  HIPTRY(hipMemsetAsync(h->ws + h->L.scal + 16, 0, sizeof(int), h->stream));
+  h->failed = false;
+  int rc = load_cores(h, src_dev, dtype);
+  if (rc) return rc;
+  for (int m = 0; m < h->p.N; ++m) h->table_valid[m] = false;
+  const int nxt = (int)(h->upd % h->p.N);
+  for (int m = 0; m < h->p.N; ++m)
+    if (m != nxt) {
+      rc = compute_table(h, m);
+      if (rc) return rc;
+    }
+  return sync_status(h);
+}
+
+int trals_get_last_samples(trals_handle h, int32_t* idx_host, double* w_host) {
+  if (!h) return TRALS_EINVAL;
+  if (!h->have_last) return TRALS_ESTATE;
+  const Problem& p = h->p;
+  if (idx_host)
+    HIPTRY(hipMemcpyAsync(idx_host, h->at<void>(h->L.idx), (size_t)p.J * (p.N - 1) * 4, hipMemcpyDeviceToHost,
+                          h->stream));
+  if (w_host)
+    HIPTRY(hipMemcpyAsync(w_host, h->at<void>(h->L.w), (size_t)p.J * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  return TRALS_OK;
+}
+
+int64_t trals_update_counter(trals_handle h) { return h ? h->upd : -1; }
+
+int trals_set_update_counter(trals_handle h, int64_t counter) {
+  if (!h || counter < 0) return TRALS_EINVAL;
+  h->upd = counter;
+  h->have_last = false;
+  return TRALS_OK;
+}
+
+}  // extern "C"

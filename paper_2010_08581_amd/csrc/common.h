@@ -1,0 +1,56 @@
+// Internal definitions shared by the gfx950 kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trals {
+
+constexpr int kMaxOrder = 16;   // N
+constexpr int kMaxRank = 32;    // R_n
+
+// Status word kept in device memory; kernels raise it, the host reads it at sync points.
+enum DevStatus : int { kDevOk = 0, kDevSingular = 1 };
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): multipliers and Weyl key increments.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+__device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = kPhiloxM0 * x[0];
+    const uint64_t hi0 = __umul64hi(kPhiloxM0, x[0]);
+    const uint64_t lo1 = kPhiloxM1 * x[2];
+    const uint64_t hi1 = __umul64hi(kPhiloxM1, x[2]);
+    const uint64_t y0 = hi1 ^ x[1] ^ k0;
+    const uint64_t y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+}
+
+// Per-mode view of the ring passed by value to kernels.
+struct Ring {
+  int N;
+  int dims[kMaxOrder];
+  int ranks[kMaxOrder];  // bond after core n; core n is ranks[n-1] x dims[n] x ranks[n]
+};
+
+__host__ __device__ __forceinline__ int rank_before(const Ring& g, int n) {
+  return g.ranks[(n + g.N - 1) % g.N];
+}
+
+// Pointers to per-mode device arrays.
+template <typename T>
+struct PerMode {
+  T* p[kMaxOrder];
+};
+
+}  // namespace trals

@@ -1,0 +1,79 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+symbol, and validates descriptions on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2010_08581_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(trals_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    decl = declared_symbols()
+    assert decl, "no declarations found"
+    assert decl == set(_lib.EXPORTS)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    assert _lib.strerror(0) == "ok"
+    assert "invalid" in _lib.strerror(-1)
+    assert "unknown" in _lib.strerror(123)
+
+
+def ws(dims, ranks, J, prec=_lib.TRALS_F32, **kw):
+    desc, keep = _lib.make_desc(dims, ranks, J, precision=prec, **kw)
+    out = C.c_size_t(0)
+    rc = _lib.load().trals_workspace_bytes(C.byref(desc), C.byref(out))
+    return rc, out.value
+
+
+def test_workspace_size_covers_panels():
+    rc, b = ws((60, 60, 60), (3, 3, 3), 2000, _lib.TRALS_F64)
+    assert rc == 0 and b >= 3 * 60 ** 3 * 8
+    rc, b32 = ws((60, 60, 60), (3, 3, 3), 2000, _lib.TRALS_F32)
+    assert rc == 0 and 3 * 60 ** 3 * 4 <= b32 < b
+
+
+@pytest.mark.parametrize("dims,ranks,J,prec", [
+    ((60, 60, 60), (3, 3, 3), 8, _lib.TRALS_F32),          # J < R_{n-1} R_n
+    ((60,), (3,), 100, _lib.TRALS_F32),                    # order 1
+    ((6, 6, 6), (3, 33, 3), 5000, _lib.TRALS_F32),         # rank above 32
+    ((6, 0, 6), (3, 3, 3), 100, _lib.TRALS_F32),           # empty mode
+    ((6, 6, 6), (3, 0, 3), 100, _lib.TRALS_F32),           # zero rank
+    ((6, 6, 6), (3, 3, 3), 100, 7),                        # unknown precision
+])
+def test_invalid_descriptions_rejected(dims, ranks, J, prec):
+    rc, _ = ws(dims, ranks, J, prec)
+    assert rc == _lib.TRALS_EINVAL
+
+
+def test_null_arguments(lib):
+    assert lib.trals_workspace_bytes(None, None) == _lib.TRALS_EINVAL
+    assert lib.trals_destroy(None) == 0
+    assert lib.trals_sweep(None, 1) == _lib.TRALS_EINVAL
+    assert lib.trals_update_counter(None) == -1
+    h = C.c_void_p(0)
+    desc, keep = _lib.make_desc((6, 6, 6), (2, 2, 2), 100)
+    # NULL data / workspace pointers are rejected before any device call
+    assert lib.trals_create(C.byref(desc), None, 1, None, 0, None, C.byref(h)) == _lib.TRALS_EINVAL
+    assert h.value is None

@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar: sampled indices bit-exact; FP64 cores within 1e-9 relative (free-running),
+FP32 cores within 1e-4 relative per update (lockstep: before every update the
+oracle starts from the GPU's current cores, so both sides draw from the same
+tables).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import als as oals  # noqa: E402
+from synth import make_config, random_cores, rng_for, video_tensor  # noqa: E402
+from tests.gpu_helpers import lockstep, rel, say, to_np  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2010_08581_amd import _lib
+    _lib.load()
+
+
+def TR(*a, **k):
+    from paper_2010_08581_amd import TRALS
+    return TRALS(*a, **k)
+
+
+def test_c1_free_running_fp64_full_config():
+    say("case: c1 60^3 R=3 J=2000 fp64, 10 sweeps free-running")
+    X, _, init = make_config("c1", dtype=np.float64)
+    rec = []
+    ref = oals.tr_als_sampled(X, init, 2000, 10, seed=0, record=rec)
+    t = TR(torch.tensor(X, device="cuda"), (3, 3, 3), 2000, seed=0, precision="f64", init_cores=init)
+    for u, n, idx_o, w_o in rec:
+        t.step(1)
+        idx_g, w_g = t.last_samples()
+        assert np.array_equal(idx_g, idx_o), f"update {u}: indices differ"
+        np.testing.assert_allclose(w_g, w_o, rtol=1e-10)
+    got = to_np(t.get_cores())
+    for n in range(3):
+        assert rel(got[n], ref[n]) < 1e-9
+    fg = t.fit_error()
+    fo = oals.fit_error(ref, X)
+    say(f"c1 fit gpu={fg:.9e} oracle={fo:.9e}")
+    assert abs(fg - fo) <= 1e-9 * fo
+
+
+def test_fp32_lockstep_3way_ragged():
+    say("case: fp32 120x136x150 R=10 J=1000 lockstep 6 updates")
+    X, _, init = make_config("c2", dims=(120, 136, 150), dtype=np.float32)
+    t = TR(torch.tensor(X, device="cuda"), (10, 10, 10), 1000, precision="f32", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 6, 1000)
+    say(f"worst core rel diff {worst:.3e}")
+
+
+def test_fp32_lockstep_5way():
+    say("case: fp32 5-way 21x22x20x23x19 R=5 J=4096 lockstep 5 updates")
+    X, _, init = make_config("c3", dims=(21, 22, 20, 23, 19), dtype=np.float32)
+    t = TR(torch.tensor(X, device="cuda"), (5,) * 5, 4096, precision="f32", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 5, 4096)
+    say(f"worst core rel diff {worst:.3e}")
+
+
+def test_fp32_lockstep_video_shape_small():
+    say("case: fp32 video 24x32x3x200 R=4 J=700 lockstep 8 updates")
+    X = video_tensor(24, 32, 3, 200, K=4, seed=0)
+    init = random_cores(X.shape, (4, 4, 4, 4), rng_for(0, 3))
+    t = TR(torch.tensor(X, device="cuda"), (4, 4, 4, 4), 700, precision="f32", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 8, 700)
+    say(f"worst core rel diff {worst:.3e}")
+
+
+def test_order2_rank1_fp64():
+    say("case: fp64 order 2, ranks (1,3), J=40")
+    rng = rng_for(61, 0)
+    X = rng.standard_normal((50, 70))
+    init = random_cores(X.shape, (1, 3), rng_for(61, 3))
+    t = TR(torch.tensor(X, device="cuda"), (1, 3), 40, precision="f64", init_cores=init)
+    lockstep(t, X, 4, 40, core_tol=1e-10)
+
+
+def test_wide_and_square_cores_fp64():
+    # I_n < P_n and I_n == P_n take the uniform table, I_n > P_n the Cholesky path
+    say("case: fp64 8x9x10 R=3 J=64")
+    X = rng_for(62, 0).standard_normal((8, 9, 10))
+    init = random_cores(X.shape, (3, 3, 3), rng_for(62, 3))
+    t = TR(torch.tensor(X, device="cuda"), (3, 3, 3), 64, precision="f64", init_cores=init)
+    lockstep(t, X, 6, 64, core_tol=1e-10)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_fit_error_matches_oracle(prec, tol):
+    say(f"case: fit error {prec}")
+    dims, ranks = (33, 41, 29, 7), (3, 4, 2, 5)
+    X = rng_for(63, 0).standard_normal(dims).astype(np.float32 if prec == "f32" else np.float64)
+    cores = random_cores(dims, ranks, rng_for(63, 1))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 200, precision=prec, init_cores=cores)
+    got = to_np(t.get_cores())
+    want = oals.fit_error(got, X.astype(np.float64))
+    assert abs(t.fit_error() - want) <= tol * want
+
+
+def test_nan_in_x_rejected():
+    say("case: NaN in X")
+    from paper_2010_08581_amd import TralsError
+    X = np.ones((10, 11, 12), dtype=np.float32)
+    X[3, 4, 5] = np.nan
+    with pytest.raises(TralsError) as e:
+        TR(torch.tensor(X, device="cuda"), (2, 2, 2), 50, precision="f32")
+    assert e.value.code == -1
+
+
+def test_zero_core_is_singular_and_recoverable():
+    say("case: all-zero core")
+    from paper_2010_08581_amd import TralsError
+    X = rng_for(64, 0).standard_normal((20, 21, 22))
+    init = random_cores(X.shape, (2, 2, 2), rng_for(64, 3))
+    t = TR(torch.tensor(X, device="cuda"), (2, 2, 2), 100, precision="f64", init_cores=init)
+    bad = [c.copy() for c in init]
+    bad[1][:] = 0.0
+    with pytest.raises(TralsError) as e:
+        t.set_cores(bad)
+    assert e.value.code == -3
+    with pytest.raises(TralsError):
+        t.step(1)  # failed state
+    t.set_cores(init)  # reset
+    t.step(3)
+
+
+def test_resume_and_determinism_bit_identical():
+    say("case: resume 2+2 sweeps vs 4 sweeps")
+    X, _, init = make_config("c1", dims=(30, 31, 32), dtype=np.float64)
+    Xt = torch.tensor(X, device="cuda")
+    a = TR(Xt, (3, 3, 3), 300, precision="f64", init_cores=init)
+    a.sweep(4)
+    ca = to_np(a.get_cores())
+    b = TR(Xt, (3, 3, 3), 300, precision="f64", init_cores=init)
+    b.sweep(2)
+    mid = to_np(b.get_cores())
+    c = TR(Xt, (3, 3, 3), 300, precision="f64", init_cores=mid)
+    c.update_counter = 2 * 3
+    c.sweep(2)
+    cc = to_np(c.get_cores())
+    for n in range(3):
+        assert np.array_equal(ca[n], cc[n])
+    d = TR(Xt, (3, 3, 3), 300, precision="f64", init_cores=init)
+    d.sweep(4)
+    for n, cd in enumerate(to_np(d.get_cores())):
+        assert np.array_equal(ca[n], cd)
+
+
+def test_c2_full_size_lockstep():
+    say("case: c2 full size 500^3 R=10 J=8192 fp32 lockstep 3 updates")
+    X, _, init = make_config("c2", dtype=np.float32)
+    t = TR(torch.tensor(X, device="cuda"), (10, 10, 10), 8192, precision="f32", init_cores=init)
+    X64 = X.astype(np.float64)
+    del X
+    worst = lockstep(t, X64, 3, 8192)
+    say(f"c2 worst core rel diff {worst:.3e}")
