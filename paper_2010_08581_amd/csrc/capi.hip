@@ -96,6 +96,10 @@ void plan(const Problem& p, Layout* L) {
     const size_t h = (size_t)pl.splits * P * P, b = (size_t)pl.splits * P * p.dims[n];
     hpart = h > hpart ? h : hpart;
     bpart = b > bpart ? b : bpart;
+    // Gram of the core itself for its leverage table
+    const NormalEqPlan pk = plan_normal_eq(P, 0, p.dims[n], (int)p.real_sz, kPlanCUs);
+    const size_t hk = (size_t)pk.splits * P * P;
+    hpart = hk > hpart ? hk : hpart;
   }
   L->idx = take((size_t)p.J * (p.N - 1) * 4);
   L->w = take((size_t)p.J * 8);
@@ -193,8 +197,20 @@ int compute_table(trals_ctx* h, int m) {
   if (I > P) {
     double* M = h->at<double>(h->L.M);
     double* W = h->at<double>(h->L.W);
-    HIPTRY(launch_lev_gram(core, p.real_dt, I, P, M, h->status(), h->stream));
-    HIPTRY(launch_spd_inverse(nullptr, 0, P, M, W, h->status(), h->stream));
+    // K = G_(2)^T G_(2): the Gram-only form of the normal-equation kernel over the I rows
+    const NormalEqPlan pl = plan_normal_eq(P, 0, I, (int)p.real_sz, kPlanCUs);
+    NormalEqArgs na;
+    memset(&na, 0, sizeof(na));
+    na.A = core;
+    na.J = I;
+    na.chunk = pl.chunk;
+    na.P = P;
+    na.gram_tiles = pl.gram_tiles;
+    na.Hpart = h->at<double>(h->L.Hpart);
+    na.status = h->status();
+    HIPTRY(launch_normal_eq(na, pl, p.real_dt, h->stream));
+    HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
+    HIPTRY(launch_spd_inverse(P, M, W, h->status(), h->stream));
     HIPTRY(launch_lev_rows(core, p.real_dt, I, P, M, Q, h->status(), h->stream));
   } else {
     HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
@@ -284,8 +300,8 @@ int run_update(trals_ctx* h) {
   HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 0, Bred, h->status(), h->stream));
   PROF_END(TRALS_K_REDUCE);
   PROF_BEGIN(TRALS_K_SOLVE);
-  HIPTRY(launch_spd_inverse(nullptr, 0, P, M, W, h->status(), h->stream));
-  HIPTRY(launch_solve(M, Bred, 1, P, In, h->at<void>(h->L.core[n]), p.real_dt, h->status(), h->stream));
+  HIPTRY(launch_spd_inverse(P, M, W, h->status(), h->stream));
+  HIPTRY(launch_solve(M, Bred, P, In, h->at<void>(h->L.core[n]), p.real_dt, h->status(), h->stream));
   PROF_END(TRALS_K_SOLVE);
   h->table_valid[n] = false;
   const int rc = compute_table(h, n);

@@ -77,20 +77,13 @@ hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int r
 hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int lower, double* out,
                                const int* status, hipStream_t s);
 
-// Reduce nparts partial P x P matrices (or use M as is when nparts == 0), Cholesky-factor
-// in FP64.  want == 0: M <- (L L^T)^{-1};  want == 1: W <- L^{-1} (lower).
-// On a non-positive pivot sets *status = kDevSingular.
-hipError_t launch_chol(const double* parts, int nparts, int P, double* M, double* W, int want, int* status,
-                       hipStream_t s);
+// In-place FP64 inverse of the SPD P x P matrix M (full storage).  scratch (P x P) is used for
+// P > 160.  A non-positive pivot sets *status = kDevSingular.
+hipError_t launch_spd_inverse(int P, double* M, double* scratch, int* status, hipStream_t s);
 
-// Full inverse of an SPD P x P matrix into work (FP64): input is the fixed-order sum of nparts
-// partial matrices, or work itself when nparts == 0.  scratch (P x P) is used for P > 144.
-hipError_t launch_spd_inverse(const double* parts, int nparts, int P, double* work, double* scratch, int* status,
-                              hipStream_t s);
-
-// Z = Hinv * sum_s Bpart[s]; core n slice i <- Z[:, i] (compute type).
-hipError_t launch_solve(const double* Hinv, const void* Bpart, int nparts, int P, int In, void* core,
-                        int real_dtype, const int* status, hipStream_t s);
+// Z = Hinv * B (P x I_n, FP64); core n slice i <- Z[:, i] (compute type).
+hipError_t launch_solve(const double* Hinv, const double* B, int P, int In, void* core, int real_dtype,
+                        const int* status, hipStream_t s);
 
 // ---- leverage tables (eq. (3)) ----
 hipError_t launch_lev_gram(const void* core, int real_dtype, int In, int P, double* K, const int* status,

@@ -19,15 +19,18 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kColTile = 64;
-constexpr int kKB = 16;  // sample rows per LDS stage (4 MFMA k-steps)
+constexpr int kKB = 32;         // sample rows per LDS stage (8 MFMA k-steps)
+constexpr int kMaxChunk = 512;  // sample rows per split (row offsets and weights cached in LDS)
 
 template <typename Real, int MB>
 __global__ __launch_bounds__(256) void k_normal_eq(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
-  __shared__ double As[kKB][RT + 1];
-  __shared__ double Bs[kKB][kColTile + 1];
-  __shared__ int64_t s_roff[kKB];
-  __shared__ double s_w[kKB];
+  constexpr int NA = (kKB * RT + 255) / 256;        // A elements per thread per stage
+  constexpr int NB = (kKB * kColTile + 255) / 256;  // B elements per thread per stage
+  __shared__ Real As[2][kKB][RT + 1];
+  __shared__ Real Bs[2][kKB][kColTile + 1];
+  __shared__ int64_t s_roff[kMaxChunk];
+  __shared__ double s_w[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
   const int ct = blockIdx.x, rt = blockIdx.y, s = blockIdx.z;
@@ -37,58 +40,77 @@ __global__ __launch_bounds__(256) void k_normal_eq(NormalEqArgs a) {
   if (gram && col0 >= row0 + RT) return;  // strictly upper Gram tile
   const int64_t r0 = (int64_t)s * a.chunk;
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
+  const int nrows = (int)(r1 - r0);
   const Real* A = (const Real*)a.A;
   const Real* X = (const Real*)a.panel;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // weights and panel-row offsets of the whole chunk (data tiles)
+  if (!gram) {
+    for (int r = threadIdx.x; r < nrows; r += 256) {
+      const int32_t* ij = a.idx + (r0 + r) * a.K;
+      int64_t off = 0;
+      for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      s_roff[r] = off * In;
+      s_w[r] = a.w[r0 + r];
+    }
+    __syncthreads();
+  }
+  Real ra[NA], rb[NB];
+  auto load_stage = [&](int base) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int r = e / RT, c = e % RT;
+      ra[q] = (e < kKB * RT && base + r < nrows && row0 + c < P) ? A[(r0 + base + r) * P + row0 + c] : Real(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int r = e / kColTile, c = e % kColTile;
+      Real v = Real(0);
+      if (base + r < nrows) {
+        if (gram) {
+          if (col0 + c < P) v = A[(r0 + base + r) * P + col0 + c];
+        } else {
+          if (col0 + c < In) v = X[s_roff[base + r] + col0 + c];
+        }
+      }
+      rb[q] = v;
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < kKB * RT) As[buf][e / RT][e % RT] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      Bs[buf][e / kColTile][e % kColTile] = rb[q];
+    }
+  };
   d4 acc[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t rb = r0; rb < r1; rb += kKB) {
-    if (!gram && threadIdx.x < kKB) {
-      const int64_t row = rb + threadIdx.x;
-      int64_t off = 0;
-      double wj = 0.0;
-      if (row < r1) {
-        const int32_t* ij = a.idx + row * a.K;
-        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
-        wj = a.w[row];
-      }
-      s_roff[threadIdx.x] = off * In;
-      s_w[threadIdx.x] = wj;
-    }
-    for (int e = threadIdx.x; e < kKB * RT; e += 256) {
-      const int r = e / RT, c = e % RT;
-      const int64_t row = rb + r;
-      As[r][c] = (row < r1 && row0 + c < P) ? (double)A[row * P + row0 + c] : 0.0;
-    }
-    if (gram) {
-      for (int e = threadIdx.x; e < kKB * kColTile; e += 256) {
-        const int r = e / kColTile, c = e % kColTile;
-        const int64_t row = rb + r;
-        Bs[r][c] = (row < r1 && col0 + c < P) ? (double)A[row * P + col0 + c] : 0.0;
-      }
-    }
+  const int stages = (nrows + kKB - 1) / kKB;
+  load_stage(0);
+  for (int t = 0; t < stages; ++t) {
+    const int buf = t & 1;
+    store_stage(buf);
     __syncthreads();
-    if (!gram) {
-      for (int e = threadIdx.x; e < kKB * kColTile; e += 256) {
-        const int r = e / kColTile, c = e % kColTile;
-        const int64_t row = rb + r;
-        Bs[r][c] = (row < r1 && col0 + c < In) ? s_w[r] * (double)X[s_roff[r] + col0 + c] : 0.0;
-      }
-      __syncthreads();
-    }
+    if (t + 1 < stages) load_stage((t + 1) * kKB);
 #pragma unroll
     for (int ks = 0; ks < kKB / 4; ++ks) {
       const int kr = ks * 4 + (lane >> 4);
-      const double b = Bs[kr][wave * 16 + (lane & 15)];
+      double b = (double)Bs[buf][kr][wave * 16 + (lane & 15)];
+      if (!gram) b *= s_w[t * kKB + kr < nrows ? t * kKB + kr : 0];
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        const double av = As[kr][m * 16 + (lane & 15)];
+        const double av = (double)As[buf][kr][m * 16 + (lane & 15)];
         acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[m], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
   // D(i, j) of each 16 x 16 block sits in lane j + 16 (i % 4), register i / 4
   const int col = col0 + wave * 16 + (lane & 15);
@@ -176,9 +198,12 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int panel_bytes, int num_c
   // split the samples so that the launch holds ~3 workgroups per CU, but keep the FP64 partial
   // traffic below the gathered bytes and every chunk at least one LDS stage long
   int64_t S = (3 * (int64_t)num_cu + tiles - 1) / tiles;
-  const int64_t cap_bytes = (J * In * panel_bytes) / (8 * (int64_t)P * (P + In)) + 1;
-  if (S > cap_bytes) S = cap_bytes;
+  if (In > 0) {
+    const int64_t cap_bytes = (2 * J * In * panel_bytes) / (8 * (int64_t)P * (P + In)) + 1;
+    if (S > cap_bytes) S = cap_bytes;
+  }
   if (S > J / kKB) S = J / kKB;
+  if (S < (J + kMaxChunk - 1) / kMaxChunk) S = (J + kMaxChunk - 1) / kMaxChunk;
   if (S < 1) S = 1;
   if (S > 65535) S = 65535;
   int64_t chunk = (J + S - 1) / S;
