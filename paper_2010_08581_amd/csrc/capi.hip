@@ -22,7 +22,7 @@ struct Layout {
   size_t panel[kMaxOrder];
   size_t core[kMaxOrder];
   size_t cdf[kMaxOrder];
-  size_t idx, w, A, Hpart, Bpart, Bred, M, W, partial, scal, total;
+  size_t idx, w, A, Hpart, Bpart, Bred, M, F, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -108,7 +108,7 @@ void plan(const Problem& p, Layout* L) {
   L->Bpart = take(bpart * 8);
   L->Bred = take((size_t)p.Pmax * p.Imax * 8);
   L->M = take((size_t)p.Pmax * p.Pmax * 8);
-  L->W = take((size_t)p.Pmax * p.Pmax * 8);
+  L->F = take(chol_factor_doubles(p.Pmax) * 8);
   const int64_t fit_rows = p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
@@ -196,7 +196,7 @@ int compute_table(trals_ctx* h, int m) {
   PROF_BEGIN(TRALS_K_TABLE);
   if (I > P) {
     double* M = h->at<double>(h->L.M);
-    double* W = h->at<double>(h->L.W);
+    double* F = h->at<double>(h->L.F);
     // K = G_(2)^T G_(2): the Gram-only form of the normal-equation kernel over the I rows
     const NormalEqPlan pl = plan_normal_eq(P, 0, I, (int)p.real_sz, kPlanCUs);
     NormalEqArgs na;
@@ -210,8 +210,8 @@ int compute_table(trals_ctx* h, int m) {
     na.status = h->status();
     HIPTRY(launch_normal_eq(na, pl, p.real_dt, h->stream));
     HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
-    HIPTRY(launch_spd_inverse(P, M, W, h->status(), h->stream));
-    HIPTRY(launch_lev_rows(core, p.real_dt, I, P, M, Q, h->status(), h->stream));
+    HIPTRY(launch_chol_factor(P, M, F, h->status(), h->stream));
+    HIPTRY(launch_chol_solve(P, I, F, nullptr, core, p.real_dt, Q, 1, h->status(), h->stream));
   } else {
     HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
   }
@@ -293,15 +293,16 @@ int run_update(trals_ctx* h) {
   PROF_END(TRALS_K_CONTRACT);
 
   double* M = h->at<double>(h->L.M);
-  double* W = h->at<double>(h->L.W);
+  double* F = h->at<double>(h->L.F);
   double* Bred = h->at<double>(h->L.Bred);
   PROF_BEGIN(TRALS_K_REDUCE);
   HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
   HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 0, Bred, h->status(), h->stream));
   PROF_END(TRALS_K_REDUCE);
   PROF_BEGIN(TRALS_K_SOLVE);
-  HIPTRY(launch_spd_inverse(P, M, W, h->status(), h->stream));
-  HIPTRY(launch_solve(M, Bred, P, In, h->at<void>(h->L.core[n]), p.real_dt, h->status(), h->stream));
+  HIPTRY(launch_chol_factor(P, M, F, h->status(), h->stream));
+  HIPTRY(launch_chol_solve(P, In, F, Bred, h->at<void>(h->L.core[n]), p.real_dt, nullptr, 0, h->status(),
+                           h->stream));
   PROF_END(TRALS_K_SOLVE);
   h->table_valid[n] = false;
   const int rc = compute_table(h, n);

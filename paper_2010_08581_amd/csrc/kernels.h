@@ -77,19 +77,17 @@ hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int r
 hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int lower, double* out,
                                const int* status, hipStream_t s);
 
-// In-place FP64 inverse of the SPD P x P matrix M (full storage).  scratch (P x P) is used for
-// P > 160.  A non-positive pivot sets *status = kDevSingular.
-hipError_t launch_spd_inverse(int P, double* M, double* scratch, int* status, hipStream_t s);
-
-// Z = Hinv * B (P x I_n, FP64); core n slice i <- Z[:, i] (compute type).
-hipError_t launch_solve(const double* Hinv, const double* B, int P, int In, void* core, int real_dtype,
-                        const int* status, hipStream_t s);
+// Blocked FP64 Cholesky of the SPD P x P matrix H (full storage, P <= 1024) into the factor
+// buffer F (chol_factor_doubles(P) doubles).  A non-positive pivot sets *status = kDevSingular.
+size_t chol_factor_doubles(int P);
+hipError_t launch_chol_factor(int P, const double* H, double* F, int* status, hipStream_t s);
+// With the factor F of H: mode 0 solves H Z = B (P x I_n) and writes lateral slice i of the
+// core as column i of Z (compute type); mode 1 writes the leverage weights
+// Q_i = floor(||L^{-1} g_i||^2 / P * 2^52) of the rows g_i of the core (B unused).
+hipError_t launch_chol_solve(int P, int In, const double* F, const double* B, void* core, int real_dtype,
+                             uint64_t* Q, int mode, const int* status, hipStream_t s);
 
 // ---- leverage tables (eq. (3)) ----
-hipError_t launch_lev_gram(const void* core, int real_dtype, int In, int P, double* K, const int* status,
-                           hipStream_t s);
-hipError_t launch_lev_rows(const void* core, int real_dtype, int In, int P, const double* Linv,
-                           uint64_t* Q, const int* status, hipStream_t s);
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s);
 hipError_t launch_scan_u64(uint64_t* Q, int In, const int* status, hipStream_t s);
 

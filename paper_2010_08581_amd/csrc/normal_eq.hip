@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__
       src = i >= j ? e : (int64_t)j * P + i;
     }
     double acc = 0.0;
+#pragma unroll 8
     for (int s = 0; s < nparts; ++s) acc += parts[s * count + src];
     out[e] = acc;
   }

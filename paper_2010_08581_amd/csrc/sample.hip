@@ -6,18 +6,39 @@
 // t = floor(r T / 2^64) (high word of the 128-bit product) and i = min{i : t < C_i}, found by
 // binary search; zero-weight entries are never drawn.  The rescaling is w = 1/sqrt(J q) with
 // q = prod_k Q_{i_k} / T_k the exact probability of the tuple, multiplied in FP64 in k order.
+//
+// The tables of the N-1 sampled modes are staged in LDS when they fit (kLdsTableBytes), so
+// the dependent loads of the binary searches stay on chip.
 #include "kernels.h"
 
 namespace trals {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+constexpr int kThreads = 256;
+constexpr size_t kLdsTableBytes = 48 * 1024;
+
+template <bool kLds>
+__global__ __launch_bounds__(kThreads) void k_sample(SampleArgs a) {
+  extern __shared__ uint64_t tab[];
   if (*a.status != kDevOk) return;
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= a.J) return;
   const int N = a.ring.N;
   const int K = N - 1;
+  int off[kMaxOrder];
+  if (kLds) {
+    int o = 0;
+    for (int k = 0; k < K; ++k) {
+      int m = a.n + 1 + k;
+      if (m >= N) m -= N;
+      off[k] = o;
+      const int I = a.ring.dims[m];
+      for (int i = threadIdx.x; i < I; i += kThreads) tab[o + i] = a.cdf.p[m][i];
+      o += I;
+    }
+    __syncthreads();
+  }
+  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= a.J) return;
   uint64_t x[4] = {0, 0, 0, 0};
   double q = 1.0;
   for (int k = 0; k < K; ++k) {
@@ -32,7 +53,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     const uint64_t r = word == 0 ? x[0] : word == 1 ? x[1] : word == 2 ? x[2] : x[3];
     int m = a.n + 1 + k;
     if (m >= N) m -= N;
-    const uint64_t* C = a.cdf.p[m];
+    const uint64_t* C = kLds ? tab + off[k] : a.cdf.p[m];
     const int I = a.ring.dims[m];
     const uint64_t T = C[I - 1];
     const uint64_t t = __umul64hi(r, T);
@@ -52,8 +73,11 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
 }  // namespace
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.J + 255) / 256;
-  k_sample<<<(unsigned)blocks, 256, 0, s>>>(a);
+  const int64_t blocks = (a.J + kThreads - 1) / kThreads;
+  size_t bytes = 0;
+  for (int k = 0; k < a.ring.N - 1; ++k) bytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
+  if (bytes <= kLdsTableBytes) k_sample<true><<<(unsigned)blocks, kThreads, bytes, s>>>(a);
+  else k_sample<false><<<(unsigned)blocks, kThreads, 0, s>>>(a);
   return hipGetLastError();
 }
 
