@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--latency-updates", type=int, default=60)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16-form", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -153,16 +154,19 @@ def main():
     value = rows / elapsed
     esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
     P = [ranks[(n - 1) % N] * ranks[n] for n in range(N)]
-    # dominant kernel: fused fiber gather + A^T X~ (all modes of this workload have the same shape)
+    # the method's contraction: fused fiber gather + [A^T A | A^T X~] (algorithmic FLOPs: B plus
+    # the lower triangle of H); the FP32 path accumulates in FP64 on the FP64 matrix cores
     avg_s = kern["contract"]["ms_per_launch"] * 1e-3
-    flops = np.mean([2.0 * J * P[n] * dims[n] for n in range(N)])
+    flops = np.mean([2.0 * J * P[n] * dims[n] + J * P[n] * (P[n] + 1.0) for n in range(N)])
     gbytes = np.mean([J * dims[n] * esz for n in range(N)])
-    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[prec]
+    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[prec]
     achieved = flops / avg_s / 1e12
     traffic = measured_traffic(cfg["name"])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": traffic, "kernel": "contract (gather + A^T X~)",
-                "gather_GBps": gbytes / avg_s / 1e9}
+                "frac": achieved / peak, "traffic": traffic,
+                "kernel": "k_normal_eq (fiber gather + [A^T A | A^T X~], FP64 matrix cores)",
+                "gather_GBps": gbytes / avg_s / 1e9,
+                "gather_hbm_frac": gbytes / avg_s / 1e9 / PEAK_HBM_GBS}
     bytes_sweep = J * sum(dims) * esz
     out = {
         "metric": "sampled ALS rows/s", "value": value, "unit": "rows/s", "n_gpus": 1,
@@ -179,6 +183,32 @@ def main():
         "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in kern.items()},
         "roofline": roofline,
     }
+    if prec == "f32" and not args.no_bf16_form:
+        # the BF16 form on the same input, initial cores and number of sweeps
+        del h
+        torch.cuda.empty_cache()
+        Xt = torch.from_numpy(X).to(dev)
+        hb = TRALS(Xt, ranks, J, seed=cfg["seed"], precision="bf16", init_cores=init)
+        del Xt
+        if args.warmup:
+            hb.sweep(args.warmup)
+        hb.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hb.sweep(args.steps)
+        torch.cuda.synchronize()
+        eb = time.perf_counter() - t0
+        ms, cnt = hb.profile_read("contract")
+        hb.profile(False)
+        hb.step(args.latency_updates)
+        fb = hb.fit_error()
+        out["forms"] = {"bf16": {
+            "value": J * N * args.steps / eb, "unit": "rows/s", "ms_per_step": eb / args.steps * 1e3,
+            "speedup_vs_f32": elapsed / eb, "fit_error": fb, "fit_rel_diff_vs_f32": abs(fb - fit) / fit,
+            "contract_ms_per_launch": ms / max(cnt, 1),
+            "contract_gather_GBps": np.mean([J * dims[n] * 2 for n in range(N)]) / (ms / max(cnt, 1) * 1e-3) / 1e9,
+        }}
+        log(f"bf16 form: {eb / args.steps * 1e3:.3f} ms/sweep, fit {fb:.4e}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(X, init, cfg, args.cpu_budget)

@@ -22,6 +22,7 @@ struct Layout {
   size_t panel[kMaxOrder];
   size_t core[kMaxOrder];
   size_t cdf[kMaxOrder];
+  size_t fitx;
   size_t idx, w, A, Hpart, Bpart, Bred, M, F, partial, scal, total;
   int64_t partial_count;
 };
@@ -33,7 +34,7 @@ struct Problem {
   int64_t J;
   uint64_t seed, stream_id;
   int prec;
-  int real_dt, panel_dt;
+  int real_dt, panel_dt, ne_dt;
   size_t real_sz, panel_sz;
   int64_t E;     // prod dims
   int Pmax;
@@ -45,7 +46,7 @@ int P_of(const Problem& p, int n) { return p.ranks[(n + p.N - 1) % p.N] * p.rank
 int validate(const trals_desc* d, Problem* p) {
   if (!d || !d->dims || !d->ranks) return TRALS_EINVAL;
   if (d->order < 2 || d->order > kMaxOrder) return TRALS_EINVAL;
-  if (d->precision != TRALS_F64 && d->precision != TRALS_F32) return TRALS_EINVAL;
+  if (d->precision != TRALS_F64 && d->precision != TRALS_F32 && d->precision != TRALS_BF16) return TRALS_EINVAL;
   memset(p, 0, sizeof(*p));
   p->N = d->order;
   p->E = 1;
@@ -68,10 +69,13 @@ int validate(const trals_desc* d, Problem* p) {
   p->seed = d->seed;
   p->stream_id = d->stream_id;
   p->prec = d->precision;
+  // storage of cores and sketch (FP64 or FP32), of the data panels (FP64, FP32 or BF16), and
+  // the arithmetic of the normal-equation products (FP64 matrix cores, or BF16 ones)
   p->real_dt = p->prec == TRALS_F64 ? 0 : 1;
-  p->panel_dt = p->real_dt;
   p->real_sz = p->real_dt == 0 ? 8 : 4;
-  p->panel_sz = p->real_sz;
+  p->panel_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
+  p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
+  p->ne_dt = p->panel_dt;
   if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
   return TRALS_OK;
 }
@@ -87,6 +91,8 @@ void plan(const Problem& p, Layout* L) {
     return o;
   };
   for (int n = 0; n < p.N; ++n) L->panel[n] = take((size_t)p.E * p.panel_sz);
+  // the fit error reads X in C order: the last panel, or an FP32 copy in the BF16 form
+  L->fitx = p.panel_dt == 2 ? take((size_t)p.E * 4) : L->panel[p.N - 1];
   for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * p.real_sz);
   for (int n = 0; n < p.N; ++n) L->cdf[n] = take((size_t)p.dims[n] * 8);
   size_t hpart = 0, bpart = 0;
@@ -289,7 +295,7 @@ int run_update(trals_ctx* h) {
   na.Bpart = h->at<double>(h->L.Bpart);
   na.status = h->status();
   PROF_BEGIN(TRALS_K_CONTRACT);
-  HIPTRY(launch_normal_eq(na, pl, p.real_dt, h->stream));
+  HIPTRY(launch_normal_eq(na, pl, p.ne_dt, h->stream));
   PROF_END(TRALS_K_CONTRACT);
 
   double* M = h->at<double>(h->L.M);
@@ -402,6 +408,9 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
       for (int k = n + 1; k < p.N; ++k) B *= p.dims[k];
       HIPTRY(launch_panel(X_dev, x_dtype, h->at<void>(L.panel[n]), p.panel_dt, A, p.dims[n], B, h->stream));
     }
+    if (p.panel_dt == 2)
+      HIPTRY(launch_panel(X_dev, x_dtype, h->at<void>(L.fitx), 1, p.E / p.dims[p.N - 1], p.dims[p.N - 1], 1,
+                          h->stream));
     if (desc->init_cores) {
       const int r2 = load_cores(h, desc->init_cores, desc->init_dtype);
       if (r2) return r2;
@@ -454,11 +463,11 @@ int trals_fit_error(trals_handle h, double* rel_err) {
   memset(&fa, 0, sizeof(fa));
   fa.ring = make_ring(p);
   for (int m = 0; m < p.N; ++m) fa.cores.p[m] = h->at<const void>(h->L.core[m]);
-  fa.X = h->at<const void>(h->L.panel[p.N - 1]);
+  fa.X = h->at<const void>(h->L.fitx);
   fa.rows = p.E / p.dims[p.N - 1];
   fa.partial = h->at<double>(h->L.partial);
   int nb = 0;
-  HIPTRY(launch_fit(fa, p.real_dt, p.panel_dt, &nb, h->stream));
+  HIPTRY(launch_fit(fa, p.real_dt, p.panel_dt == 2 ? 1 : p.panel_dt, &nb, h->stream));
   HIPTRY(launch_sum_partials(fa.partial, nb, h->scal_d(), h->stream));
   double r2 = 0.0;
   HIPTRY(hipMemcpyAsync(&r2, h->scal_d(), 8, hipMemcpyDeviceToHost, h->stream));

@@ -71,6 +71,8 @@ struct NormalEqPlan {
 };
 constexpr int kPlanCUs = 256;  // MI355X compute units (launch sizing)
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int panel_bytes, int num_cu);
+// real_dtype 0: FP64 sketch and panel; 1: FP32 sketch and panel (FP64 matrix cores);
+// 2: BF16 form (FP32 sketch, BF16 panel, BF16 matrix cores with FP32 accumulation).
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int real_dtype, hipStream_t s);
 // out = fixed-order sum of nparts partial arrays of count doubles (lower != 0: symmetrise a
 // P x P matrix from its lower triangle).

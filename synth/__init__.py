@@ -139,9 +139,10 @@ def video_tensor(H=240, W=320, C=3, T=2000, K=16, seed=0, noise=0.02, dtype=np.f
         gx = np.exp(-((ww[None, None, :] - cx[:, :, None]) ** 2) / (2 * sig[:, None, None] ** 2))
         # frame[t, h, w, c] = sum_k gy[k, t, h] * gx[k, t, w] * amp[k, c]
         gxa = gx[:, :, :, None] * amp[:, None, None, :]  # (K, t, W, C)
-        fr = np.einsum("kth,ktx->thx", gy, gxa.reshape(K, len(t), W * C), optimize=True)
-        fr = fr.reshape(len(t), H, W, C)
-        fr += nrng.uniform(-noise, noise, fr.shape)
+        # per frame: (H x K) @ (K x W*C), batched over the frames of the chunk
+        fr = np.matmul(np.transpose(gy, (1, 2, 0)), np.transpose(gxa.reshape(K, len(t), W * C), (1, 0, 2)))
+        fr = fr.astype(np.float32).reshape(len(t), H, W, C)
+        fr += nrng.uniform(-noise, noise, fr.shape).astype(np.float32)
         np.clip(fr, 0.0, 1.0, out=fr)
         X[:, :, :, t0:t0 + len(t)] = np.transpose(fr, (1, 2, 3, 0)).astype(dtype)
     return X
@@ -184,16 +185,17 @@ CONFIGS = {
 }
 
 
-def make_config(cfg, dims=None, dtype=np.float32, seed=None):
+def make_config(cfg, dims=None, dtype=np.float32, seed=None, ranks=None):
     """Build ``(X, true_cores, init_cores)`` for a workload recipe.
 
-    ``dims`` may shrink the mode sizes (same ranks, noise model and seed) for
-    small parity cases.  ``true_cores`` is None for the video recipe.
+    ``dims`` (and ``ranks``) may replace the recipe's mode sizes (and ranks)
+    with the same noise model and seed, for small parity cases.
+    ``true_cores`` is None for the video recipe.
     """
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
     dims = tuple(cfg["dims"] if dims is None else dims)
-    ranks = tuple(cfg["ranks"])
+    ranks = tuple(cfg["ranks"] if ranks is None else ranks)
     seed = cfg["seed"] if seed is None else seed
     kind, level = cfg["noise"]
     if kind == "video":
