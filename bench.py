@@ -23,7 +23,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix cores
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
@@ -134,7 +134,7 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     kern = {}
-    for k in ("sample", "sketch", "contract", "reduce", "solve", "table"):
+    for k in ("draw", "contract", "reduce", "factor", "solve", "table"):
         ms, cnt = h.profile_read(k)
         kern[k] = {"ms_per_launch": ms / max(cnt, 1), "launches": cnt}
     h.profile(False)
@@ -155,16 +155,16 @@ def main():
     esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
     P = [ranks[(n - 1) % N] * ranks[n] for n in range(N)]
     # the method's contraction: fused fiber gather + [A^T A | A^T X~] (algorithmic FLOPs: B plus
-    # the lower triangle of H); the FP32 path accumulates in FP64 on the FP64 matrix cores
+    # the lower triangle of H), on the matrix cores of the data type (FP32 stages summed in FP64)
     avg_s = kern["contract"]["ms_per_launch"] * 1e-3
     flops = np.mean([2.0 * J * P[n] * dims[n] + J * P[n] * (P[n] + 1.0) for n in range(N)])
     gbytes = np.mean([J * dims[n] * esz for n in range(N)])
-    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[prec]
+    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}[prec]
     achieved = flops / avg_s / 1e12
     traffic = measured_traffic(cfg["name"])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
-                "kernel": "k_normal_eq (fiber gather + [A^T A | A^T X~], FP64 matrix cores)",
+                "kernel": "k_normal_eq (fiber gather + [A^T A | A^T X~] on matrix cores)",
                 "gather_GBps": gbytes / avg_s / 1e9,
                 "gather_hbm_frac": gbytes / avg_s / 1e9 / PEAK_HBM_GBS}
     bytes_sweep = J * sum(dims) * esz

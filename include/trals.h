@@ -9,7 +9,9 @@
  * design matrix from lateral-slice products (Algorithm 4, eq. (5)), gathers
  * the J sampled mode-n fibers of X (Algorithm 2, "sample X"), solves the
  * sampled least-squares problem (Algorithm 2, LS step) and recomputes the
- * leverage distribution of the new core (eq. (3)).
+ * leverage distribution of the new core (eq. (3)).  The cores are held in FP64
+ * in every precision; the precision selects the storage of the data panels and
+ * the sketched rows and the arithmetic of their products.
  *
  * Conventions
  *  - Indices are 0-based.  X is a C-order array X[i_0, ..., i_{N-1}] (last
@@ -59,6 +61,8 @@ typedef enum {
   TRALS_F32 = 1,   /* IEEE single */
   TRALS_BF16 = 2   /* bfloat16 (precision TRALS_BF16 selects the BF16 form: BF16 data panels
                       and sketch on matrix cores with FP32 accumulation, FP64 Gram/Cholesky) */
+  /* TRALS_F32: FP32 data panels and sketch on FP32 matrix cores, each 32-sample stage added
+     into FP64 sums; TRALS_F64: FP64 throughout. */
 } trals_dtype;
 
 /* Problem description (Algorithm 2 inputs: X, target ranks; J per update; seed). */
@@ -129,12 +133,12 @@ int trals_set_update_counter(trals_handle h, int64_t counter);
  * and launch count of one group since profiling was enabled, then keeps
  * accumulating. */
 typedef enum {
-  TRALS_K_SAMPLE = 0,    /* Algorithm 3 sampler */
-  TRALS_K_SKETCH = 1,    /* Algorithm 4 sketched design rows */
+  TRALS_K_DRAW = 0,      /* Algorithm 3 sampler fused with the Algorithm 4 sketched rows */
+  TRALS_K_CONTRACT = 1,  /* fused fiber gather + [A^T A | A^T X~] partials (matrix cores) */
   TRALS_K_REDUCE = 2,    /* fixed-order reduction of the split-K partials of H and B */
-  TRALS_K_CONTRACT = 3,  /* fused fiber gather + [A^T A | A^T X~] partials (matrix cores) */
-  TRALS_K_SOLVE = 4,     /* SPD inverse of H, Z = H^{-1} B, core write */
-  TRALS_K_TABLE = 5,     /* new core's leverage table */
+  TRALS_K_FACTOR = 3,    /* Cholesky factor of H and its inverse */
+  TRALS_K_SOLVE = 4,     /* solve rows: the new core */
+  TRALS_K_TABLE = 5,     /* a core's leverage table (eq. (3)): Gram, factor, leverage rows, scan */
   TRALS_K_COUNT = 6
 } trals_kernel;
 int trals_profile(trals_handle h, int32_t enable);

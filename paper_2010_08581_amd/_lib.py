@@ -21,7 +21,7 @@ EXPORTS = (
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
     "trals_profile_read",
 )
-KERNELS = {"sample": 0, "sketch": 1, "reduce": 2, "contract": 3, "solve": 4, "table": 5}
+KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
 
 class Desc(C.Structure):

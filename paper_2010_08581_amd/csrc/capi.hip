@@ -1,6 +1,8 @@
 // Host runtime behind the C ABI declared in include/trals.h: argument validation, workspace
-// carving, and the per-update launch sequence of Algorithm 2 (sample -> sketch -> normal
-// equations -> solve -> new sampling table).
+// carving, and the per-update launch sequence of Algorithm 2:
+//   draw (sample + sketch) -> normal equations -> fixed-order reduction -> Cholesky and
+//   inverse factor of H -> solve rows (new core) -> new core's table (Gram, Cholesky and
+//   inverse factor, leverage rows + scan).
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -23,7 +25,7 @@ struct Layout {
   size_t core[kMaxOrder];
   size_t cdf[kMaxOrder];
   size_t fitx;
-  size_t idx, w, A, Hpart, Bpart, Bred, M, F, partial, scal, total;
+  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -34,8 +36,8 @@ struct Problem {
   int64_t J;
   uint64_t seed, stream_id;
   int prec;
-  int real_dt, panel_dt, ne_dt;
-  size_t real_sz, panel_sz;
+  int sk_dt, panel_dt, ne_dt;  // cores are FP64 in every precision
+  size_t sk_sz, panel_sz;
   int64_t E;     // prod dims
   int Pmax;
   int64_t Imax;
@@ -69,10 +71,10 @@ int validate(const trals_desc* d, Problem* p) {
   p->seed = d->seed;
   p->stream_id = d->stream_id;
   p->prec = d->precision;
-  // storage of cores and sketch (FP64 or FP32), of the data panels (FP64, FP32 or BF16), and
-  // the arithmetic of the normal-equation products (FP64 matrix cores, or BF16 ones)
-  p->real_dt = p->prec == TRALS_F64 ? 0 : 1;
-  p->real_sz = p->real_dt == 0 ? 8 : 4;
+  // storage of the sketch (FP64 or FP32) and of the data panels (FP64, FP32 or BF16), and the
+  // arithmetic of the normal-equation products; the cores (tiny) are FP64 throughout
+  p->sk_dt = p->prec == TRALS_F64 ? 0 : 1;
+  p->sk_sz = p->sk_dt == 0 ? 8 : 4;
   p->panel_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
   p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
   p->ne_dt = p->panel_dt;
@@ -93,33 +95,31 @@ void plan(const Problem& p, Layout* L) {
   for (int n = 0; n < p.N; ++n) L->panel[n] = take((size_t)p.E * p.panel_sz);
   // the fit error reads X in C order: the last panel, or an FP32 copy in the BF16 form
   L->fitx = p.panel_dt == 2 ? take((size_t)p.E * 4) : L->panel[p.N - 1];
-  for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * p.real_sz);
+  for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * 8);
   for (int n = 0; n < p.N; ++n) L->cdf[n] = take((size_t)p.dims[n] * 8);
   size_t hpart = 0, bpart = 0;
   for (int n = 0; n < p.N; ++n) {
     const int P = P_of(p, n);
-    const NormalEqPlan pl = plan_normal_eq(P, (int)p.dims[n], p.J, (int)p.panel_sz, kPlanCUs);
+    const NormalEqPlan pl = plan_normal_eq(P, (int)p.dims[n], p.J, p.ne_dt, kPlanCUs);
     const size_t h = (size_t)pl.splits * P * P, b = (size_t)pl.splits * P * p.dims[n];
     hpart = h > hpart ? h : hpart;
     bpart = b > bpart ? b : bpart;
-    // Gram of the core itself for its leverage table
-    const NormalEqPlan pk = plan_normal_eq(P, 0, p.dims[n], (int)p.real_sz, kPlanCUs);
-    const size_t hk = (size_t)pk.splits * P * P;
-    hpart = hk > hpart ? hk : hpart;
   }
   L->idx = take((size_t)p.J * (p.N - 1) * 4);
   L->w = take((size_t)p.J * 8);
-  L->A = take((size_t)p.J * p.Pmax * p.real_sz);
+  L->A = take((size_t)p.J * p.Pmax * p.sk_sz);
   L->Hpart = take(hpart * 8);  // FP64 split-K partials
   L->Bpart = take(bpart * 8);
   L->Bred = take((size_t)p.Pmax * p.Imax * 8);
-  L->M = take((size_t)p.Pmax * p.Pmax * 8);
+  L->M = take((size_t)p.Pmax * p.Pmax * 8);   // H
+  L->M2 = take((size_t)p.Pmax * p.Pmax * 8);  // Gram of a core for its leverage
   L->F = take(chol_factor_doubles(p.Pmax) * 8);
+  L->F2 = take(chol_factor_doubles(p.Pmax) * 8);
   const int64_t fit_rows = p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
-  L->scal = take(64);  // [0] double result, [1] u64 nonfinite, [2] int status
+  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [32] u32 counter
   L->total = off;
 }
 
@@ -151,6 +151,7 @@ struct trals_ctx {
   int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
   double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
   unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
+  unsigned* counter() { return reinterpret_cast<unsigned*>(ws + L.scal + 32); }
 };
 
 #define HIPTRY(expr)                      \
@@ -193,35 +194,40 @@ Ring make_ring(const Problem& p) {
   return g;
 }
 
+// Sampling table of core m from the core itself (creation, set_cores): eq. (3) via the Gram
+// of G_(2), its inverse factor and the leverage rows, scanned in place.
 int compute_table(trals_ctx* h, int m) {
   const Problem& p = h->p;
   const int P = P_of(p, m);
   const int I = (int)p.dims[m];
   uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
-  void* core = h->at<void>(h->L.core[m]);
+  const double* core = h->at<const double>(h->L.core[m]);
   PROF_BEGIN(TRALS_K_TABLE);
   if (I > P) {
-    double* M = h->at<double>(h->L.M);
-    double* F = h->at<double>(h->L.F);
-    // K = G_(2)^T G_(2): the Gram-only form of the normal-equation kernel over the I rows
-    const NormalEqPlan pl = plan_normal_eq(P, 0, I, (int)p.real_sz, kPlanCUs);
-    NormalEqArgs na;
-    memset(&na, 0, sizeof(na));
-    na.A = core;
-    na.J = I;
-    na.chunk = pl.chunk;
-    na.P = P;
-    na.gram_tiles = pl.gram_tiles;
-    na.Hpart = h->at<double>(h->L.Hpart);
-    na.status = h->status();
-    HIPTRY(launch_normal_eq(na, pl, p.real_dt, h->stream));
-    HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
-    HIPTRY(launch_chol_factor(P, M, F, h->status(), h->stream));
-    HIPTRY(launch_chol_solve(P, I, F, nullptr, core, p.real_dt, Q, 1, h->status(), h->stream));
+    double* M2 = h->at<double>(h->L.M2);
+    double* F2 = h->at<double>(h->L.F2);
+    HIPTRY(launch_syrk(core, I, P, M2, h->status(), h->stream));
+    CholArgs ca;
+    memset(&ca, 0, sizeof(ca));
+    ca.P = P;
+    ca.H = M2;
+    ca.W = F2;
+    ca.status = h->status();
+    HIPTRY(launch_chol(ca, h->stream));
+    TriArgs ta;
+    memset(&ta, 0, sizeof(ta));
+    ta.P = P;
+    ta.In_lev = I;
+    ta.Wlev = F2;
+    ta.Blev = core;
+    ta.Q = Q;
+    ta.counter = h->counter();
+    ta.status = h->status();
+    HIPTRY(launch_trisolve(ta, h->stream));
   } else {
     HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
+    HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
   }
-  HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
   PROF_END(TRALS_K_TABLE);
   h->table_valid[m] = true;
   return TRALS_OK;
@@ -236,47 +242,36 @@ int run_update(trals_ctx* h) {
       const int rc = compute_table(h, m);
       if (rc) return rc;
     }
-  const Ring ring = make_ring(p);
   const int P = P_of(p, n);
   const int In = (int)p.dims[n];
 
-  SampleArgs sa;
-  memset(&sa, 0, sizeof(sa));
-  sa.ring = ring;
-  sa.n = n;
-  sa.J = p.J;
-  sa.seed = p.seed;
-  sa.stream_id = p.stream_id;
-  sa.u = (uint64_t)h->upd;
-  for (int m = 0; m < N; ++m) sa.cdf.p[m] = h->at<const uint64_t>(h->L.cdf[m]);
-  sa.idx = h->at<int32_t>(h->L.idx);
-  sa.w = h->at<double>(h->L.w);
-  sa.status = h->status();
-  PROF_BEGIN(TRALS_K_SAMPLE);
-  HIPTRY(launch_sample(sa, h->stream));
-  PROF_END(TRALS_K_SAMPLE);
+  DrawArgs da;
+  memset(&da, 0, sizeof(da));
+  da.ring = make_ring(p);
+  da.n = n;
+  da.J = p.J;
+  da.seed = p.seed;
+  da.stream_id = p.stream_id;
+  da.u = (uint64_t)h->upd;
+  for (int m = 0; m < N; ++m) {
+    da.cdf.p[m] = h->at<const uint64_t>(h->L.cdf[m]);
+    da.cores.p[m] = h->at<const double>(h->L.core[m]);
+  }
+  da.idx = h->at<int32_t>(h->L.idx);
+  da.w = h->at<double>(h->L.w);
+  da.A = h->at<void>(h->L.A);
+  da.status = h->status();
+  PROF_BEGIN(TRALS_K_DRAW);
+  HIPTRY(launch_draw(da, p.sk_dt, h->stream));
+  PROF_END(TRALS_K_DRAW);
 
-  SketchArgs ka;
-  memset(&ka, 0, sizeof(ka));
-  ka.ring = ring;
-  ka.n = n;
-  ka.J = p.J;
-  for (int m = 0; m < N; ++m) ka.cores.p[m] = h->at<const void>(h->L.core[m]);
-  ka.idx = sa.idx;
-  ka.w = sa.w;
-  ka.A = h->at<void>(h->L.A);
-  ka.status = h->status();
-  PROF_BEGIN(TRALS_K_SKETCH);
-  HIPTRY(launch_sketch(ka, p.real_dt, h->stream));
-  PROF_END(TRALS_K_SKETCH);
-
-  const NormalEqPlan pl = plan_normal_eq(P, In, p.J, (int)p.panel_sz, kPlanCUs);
+  const NormalEqPlan pl = plan_normal_eq(P, In, p.J, p.ne_dt, kPlanCUs);
   NormalEqArgs na;
   memset(&na, 0, sizeof(na));
-  na.A = ka.A;
+  na.A = da.A;
   na.panel = h->at<const void>(h->L.panel[n]);
-  na.idx = sa.idx;
-  na.w = sa.w;
+  na.idx = da.idx;
+  na.w = da.w;
   // panel rows are the other modes in C order: stride of mode m = prod_{m' > m, m' != n} I_m'
   for (int k = 0; k < N - 1; ++k) {
     const int m = (n + 1 + k) % N;
@@ -300,17 +295,33 @@ int run_update(trals_ctx* h) {
 
   double* M = h->at<double>(h->L.M);
   double* F = h->at<double>(h->L.F);
-  double* Bred = h->at<double>(h->L.Bred);
+  double* Bred = h->at<double>(h->L.Bred);  // I_n x P: row i = b_i
   PROF_BEGIN(TRALS_K_REDUCE);
   HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
-  HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 0, Bred, h->status(), h->stream));
+  HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 2, Bred, h->status(), h->stream));
   PROF_END(TRALS_K_REDUCE);
+  CholArgs ca;
+  memset(&ca, 0, sizeof(ca));
+  ca.P = P;
+  ca.H = M;
+  ca.W = F;
+  ca.status = h->status();
+  PROF_BEGIN(TRALS_K_FACTOR);
+  HIPTRY(launch_chol(ca, h->stream));
+  PROF_END(TRALS_K_FACTOR);
+  TriArgs ta;
+  memset(&ta, 0, sizeof(ta));
+  ta.P = P;
+  ta.In_sol = In;
+  ta.Wsol = F;
+  ta.Bsol = Bred;
+  ta.core = h->at<double>(h->L.core[n]);
+  ta.counter = h->counter();
+  ta.status = h->status();
   PROF_BEGIN(TRALS_K_SOLVE);
-  HIPTRY(launch_chol_factor(P, M, F, h->status(), h->stream));
-  HIPTRY(launch_chol_solve(P, In, F, Bred, h->at<void>(h->L.core[n]), p.real_dt, nullptr, 0, h->status(),
-                           h->stream));
+  HIPTRY(launch_trisolve(ta, h->stream));
   PROF_END(TRALS_K_SOLVE);
-  h->table_valid[n] = false;
+  // eq. (3): the new core's sampling table
   const int rc = compute_table(h, n);
   if (rc) return rc;
   h->upd += 1;
@@ -336,8 +347,8 @@ int load_cores(trals_ctx* h, const void* src, int dtype) {
   for (int n = 0; n < p.N; ++n) {
     const int Rp = p.ranks[(n + p.N - 1) % p.N], Rn = p.ranks[n];
     const int I = (int)p.dims[n];
-    HIPTRY(launch_core_import((const char*)src + off, dtype == TRALS_F64 ? 0 : 1, h->at<void>(h->L.core[n]),
-                              p.real_dt, Rp, I, Rn, h->stream));
+    HIPTRY(launch_core_import((const char*)src + off, dtype == TRALS_F64 ? 0 : 1, h->at<void>(h->L.core[n]), 0,
+                              Rp, I, Rn, h->stream));
     off += (size_t)Rp * I * Rn * esz;
   }
   return TRALS_OK;
@@ -417,7 +428,7 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
     } else {
       for (int n = 0; n < p.N; ++n) {
         const int64_t cnt = (int64_t)p.dims[n] * P_of(p, n);
-        HIPTRY(launch_core_normal(h->at<void>(L.core[n]), p.real_dt, cnt, p.seed, p.stream_id, n, h->stream));
+        HIPTRY(launch_core_normal(h->at<void>(L.core[n]), 0, cnt, p.seed, p.stream_id, n, h->stream));
       }
     }
     for (int m = 1; m < p.N; ++m) {
@@ -467,7 +478,7 @@ int trals_fit_error(trals_handle h, double* rel_err) {
   fa.rows = p.E / p.dims[p.N - 1];
   fa.partial = h->at<double>(h->L.partial);
   int nb = 0;
-  HIPTRY(launch_fit(fa, p.real_dt, p.panel_dt == 2 ? 1 : p.panel_dt, &nb, h->stream));
+  HIPTRY(launch_fit(fa, 0, p.panel_dt == 2 ? 1 : p.panel_dt, &nb, h->stream));
   HIPTRY(launch_sum_partials(fa.partial, nb, h->scal_d(), h->stream));
   double r2 = 0.0;
   HIPTRY(hipMemcpyAsync(&r2, h->scal_d(), 8, hipMemcpyDeviceToHost, h->stream));
@@ -522,7 +533,7 @@ int trals_get_cores(trals_handle h, void* dst_dev, int32_t dtype) {
   for (int n = 0; n < p.N; ++n) {
     const int Rp = p.ranks[(n + p.N - 1) % p.N], Rn = p.ranks[n];
     const int I = (int)p.dims[n];
-    HIPTRY(launch_core_export(h->at<const void>(h->L.core[n]), p.real_dt, (char*)dst_dev + off,
+    HIPTRY(launch_core_export(h->at<const void>(h->L.core[n]), 0, (char*)dst_dev + off,
                               dtype == TRALS_F64 ? 0 : 1, Rp, I, Rn, h->stream));
     off += (size_t)Rp * I * Rn * esz;
   }

@@ -1,13 +1,17 @@
-// Blocked FP64 Cholesky factorisation and triangular solves on matrix cores, for the sampled
-// least-squares solve (Algorithm 2, LS step: H Z = B with H = A^T A, B = A^T X~) and for the
-// leverage scores of a core (eq. (3): with K = G_(2)^T G_(2) = L L^T, row i of G_(2) has
-// leverage ||L^{-1} g_i||^2).  The paper solves the LS problem by QR; the normal equations
-// agree with it up to cond(A)^2 * eps.
+// Small dense FP64 linear algebra of one core update, on matrix cores:
 //
-// Matrices are split into 16 x 16 blocks (P padded to 16 nblk with an identity block tail).
-// The lower-triangular factor is stored block-packed: block (i, j), i >= j, at slot
-// i (i + 1) / 2 + j, each block 16 rows of kLd doubles.  Diagonal blocks of L^{-1} are kept
-// beside it so that every triangular solve is a chain of 16 x 16 x 16 products.
+//  * The Gram matrix K = G_(2)^T G_(2) of a core's I x P unfolding, for its leverage scores
+//    (eq. (3)).
+//  * Cholesky factorisation H = L L^T of a P x P SPD matrix (H of the LS step of Algorithm 2,
+//    or K) and the explicit inverse factor W = L^{-1}.  The paper solves the LS problem by QR;
+//    the normal equations agree with it up to cond(A)^2 * eps.
+//  * With W: the solve Z = W^T (W B) (lateral slices of the new core) and the leverage rows
+//    l_i = ||W g_i||^2 (Definition 4 via K^{-1} = W^T W), as block products without
+//    dependency chains.
+//
+// Matrices are split into 16 x 16 blocks (P padded to 16 nblk with an identity tail).  Lower
+// triangular block matrices are stored block-packed: block (i, j), i >= j, at slot
+// i (i + 1) / 2 + j, each block 16 rows of kLd doubles.
 //
 // v_mfma_f64_16x16x4 layouts (one wave): A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k,
 // D(i, j) in lane j + 16 (i % 4), register i / 4.  Register r of an accumulator therefore holds
@@ -20,11 +24,21 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLd = 17;             // padded row stride of a 16 x 16 block (doubles)
-constexpr int kBlk = 16 * kLd;      // doubles per stored block
-constexpr int kLdsBlocks = 9;       // nblk up to which the factor lives in LDS (45 blocks)
+constexpr int kLd = 17;         // padded row stride of a 16 x 16 block (doubles)
+constexpr int kBlk = 16 * kLd;  // doubles per stored block
+constexpr int kLdsBlocks = 9;   // nblk up to which a factor is staged in LDS (45 blocks, 98 KB)
+constexpr int kCholWaves = 16;
+constexpr int kMaxBlk = 64;     // P <= 1024
 
 __device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__device__ __forceinline__ void slot_ij(int sl, int& i, int& j) {
+  int r = (int)((sqrtf(8.0f * (float)sl + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= sl) ++r;
+  while (r * (r + 1) / 2 > sl) --r;
+  i = r;
+  j = sl - r * (r + 1) / 2;
+}
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
 // (each step squares the relative error), instead of the longer correctly-rounded sqrt and
@@ -36,14 +50,35 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
   return y;
 }
 
+// value of v in lane `src` (wave-uniform) for every lane
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
 
-// acc += A * B^T for 16 x 16 blocks A, B (row-major, stride kLd); sign folds a subtraction.
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// acc += sign * A B^T for 16 x 16 blocks A, B (row-major, stride kLd)
 template <typename PA, typename PB>
 __device__ __forceinline__ d4 mma_abt(PA A, PB B, d4 acc, int lane, double sign) {
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int r = lane & 15, k = 4 * ks + (lane >> 4);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * A[r * kLd + k], B[r * kLd + k], acc, 0, 0, 0);
+    acc = mfma(sign * A[r * kLd + k], B[r * kLd + k], acc);
+  }
+  return acc;
+}
+
+// acc += A B for 16 x 16 blocks A, B (row-major, stride kLd)
+template <typename PA, typename PB>
+__device__ __forceinline__ d4 mma_ab(PA A, PB B, d4 acc, int lane) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int r = lane & 15, k = 4 * ks + (lane >> 4);
+    acc = mfma(A[r * kLd + k], B[k * kLd + r], acc);
   }
   return acc;
 }
@@ -62,40 +97,102 @@ __device__ __forceinline__ void store_acc(Ptr C, d4 v, int lane) {
   for (int r = 0; r < 4; ++r) C[(4 * r + (lane >> 4)) * kLd + (lane & 15)] = v[r];
 }
 
-// One workgroup of 256 threads.  Input: H (P x P, row-major, full symmetric) in global memory.
-// Output: Lp (packed blocks of L) and Dinv (nblk blocks of L_KK^{-1}) in global memory.
+// ---------------------------------------------------------------------------------------
+// K = A^T A (P x P, row-major; the lower blocks including full diagonal blocks are written)
+// for A = rows x P row-major.  One workgroup of 16 waves per lower block; wave w takes the
+// 4-row k-steps w, w + 16, ... (eight loads in flight) and the wave sums are added in the
+// order 0, 1, ..., 15.
+constexpr int kSyrkWaves = 16;
+__global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restrict__ A, int64_t rows, int P,
+                                                          double* __restrict__ Kout, const int* status) {
+  __shared__ double red[kSyrkWaves - 1][4][64];
+  if (*status != kDevOk) return;
+  int bi, bj;
+  slot_ij(blockIdx.x, bi, bj);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int ci = 16 * bi + r16, cj = 16 * bj + r16;
+  const int cic = ci < P ? ci : P - 1, cjc = cj < P ? cj : P - 1;
+  const double mi = ci < P ? 1.0 : 0.0;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t steps = (rows + 3) / 4;
+  for (int64_t k0 = wave; k0 < steps; k0 += 8 * kSyrkWaves) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = 4 * (k0 + (int64_t)u * kSyrkWaves) + k4;
+      const int64_t rc = r < rows ? r : rows - 1;
+      va[u] = (r < rows ? mi : 0.0) * A[rc * P + cic];
+      vb[u] = A[rc * P + cjc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = mfma(va[u], vb[u], acc);
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[wave - 1][q][lane] = acc[q];
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double v = acc[q];
+    for (int w = 0; w < kSyrkWaves - 1; ++w) v += red[w][q][lane];
+    const int row = 16 * bi + 4 * q + k4, col = 16 * bj + r16;
+    if (row < P && col < P) Kout[(int64_t)row * P + col] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Cholesky factorisation and inverse factor, one workgroup of 16 waves.
+//
+// Right-looking over 16-column panels.  Panel K: the panel waves each hold the 16 rows of the
+// diagonal block (lanes 0-15, identical copies) and three sub-diagonal block rows (lanes
+// 16-63) in registers; pivot step k broadcasts column k of the diagonal block across the
+// wave with lane reads (no LDS round trip), and every lane updates its row.  Then all waves
+// apply the trailing update A_ij -= L_iK L_jK^T on matrix cores.  Afterwards the diagonal
+// blocks are inverted (forward substitution per column) and W = L^{-1} is completed block
+// row by block row: W_IK = -W_II sum_{J=K}^{I-1} L_IJ W_JK.
 template <bool kInLds>
-__global__ __launch_bounds__(256) void k_chol_blocked(int P, const double* __restrict__ H, double* Lp,
-                                                      double* Dinv, int* status) {
+__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_fail;
   __shared__ double s_tol;
-  __shared__ double s_dinv[kBlk];
-  __shared__ double s_col[2][16];
-  __shared__ double s_lkk[kBlk];
-  if (*status != kDevOk) return;
+  __shared__ double s_rdiag[16 * kMaxBlk];  // 1 / L_ii
+  __shared__ double s_diag[16 * kLd];       // factored diagonal block of the current panel
+  if (*a.status != kDevOk) return;
+  const int P = a.P;
+  const double* H = a.H;
+  double* Wg = a.W;
   const int nblk = (P + 15) / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* Ls = kInLds ? lds : Lp;
-  // load the lower blocks (identity on the padded diagonal)
   const int nslots = nblk * (nblk + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* Ls = kInLds ? lds : Wg;
+  // stage the lower blocks (full diagonal blocks; identity on the padded diagonal), eight
+  // loads in flight per thread
   {
-    // thread (r, c) of a 16 x 16 grid loads element (r, c) of every lower block
-    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-    for (int bi = 0; bi < nblk; ++bi) {
-      const int i = 16 * bi + r;
-#pragma unroll 4
-      for (int bj = 0; bj <= bi; ++bj) {
-        const int j = 16 * bj + c;
-        double v = 0.0;
-        if (i < P && j < P) v = H[(int64_t)i * P + j];
-        else if (i == j) v = 1.0;
-        Ls[slot(bi, bj) * kBlk + r * kLd + c] = v;
+    const int cnt = nslots * 256;
+    constexpr int kB = 8;
+    for (int base = 0; base < cnt; base += kB * 1024) {
+      double v[kB];
+      int dst[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + 1024 * q;
+        const int sl = e >> 8, rc = e & 255;
+        int bi, bj;
+        slot_ij(sl, bi, bj);
+        const int r = rc >> 4, c = rc & 15;
+        const int i = 16 * bi + r, j = 16 * bj + c;
+        const bool in = e < cnt && i < P && j < P;
+        v[q] = in ? H[(int64_t)i * P + j] : (i == j ? 1.0 : 0.0);
+        dst[q] = sl * kBlk + r * kLd + c;
       }
+#pragma unroll
+      for (int q = 0; q < kB; ++q)
+        if (base + (int)threadIdx.x + 1024 * q < cnt) Ls[dst[q]] = v[q];
     }
   }
   __syncthreads();
-  // largest diagonal entry (from the staged blocks; wave 0, one diagonal element per lane)
   if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < P; i += 64) mx = fmax(mx, Ls[slot(i >> 4, i >> 4) * kBlk + (i & 15) * kLd + (i & 15)]);
@@ -108,84 +205,64 @@ __global__ __launch_bounds__(256) void k_chol_blocked(int P, const double* __res
   }
   __syncthreads();
   if (s_fail) {
-    if (threadIdx.x == 0) *status = kDevSingular;
+    if (threadIdx.x == 0) *a.status = kDevSingular;
     return;
   }
+  const double tol = s_tol;
+  const int l = lane & 15, grp = lane >> 4;
   for (int K = 0; K < nblk; ++K) {
-    double* DK = Ls + slot(K, K) * kBlk;
-    // (a) wave 0: factor the diagonal block (lane l < 16 holds row l) and invert it
-    if (wave == 0) {
-      // Lane l < 16 keeps row l of the block in registers.  Pivot step k publishes column k
-      // (16 doubles) through LDS; every lane reads it back as broadcasts and computes the
-      // pivot's reciprocal square root itself.  LDS operations of one wave complete in issue
-      // order, so only the compiler needs to be kept from reordering them (empty asm barrier).
-      double a[16], il[16];
-      const int l = lane & 15;
+    const int below = nblk - 1 - K;
+    const int triples = below == 0 ? 1 : (below + 2) / 3;  // sub-diagonal block-row triples
+    // The diagonal block stays unmodified in memory during the panel (each pass loads its own
+    // copy); the factored block goes to s_diag and is stored after the panel barrier.
+    for (int tri = wave; tri < triples; tri += kCholWaves) {
+      int bi = grp == 0 ? K : K + 3 * tri + grp;
+      const bool held = grp == 0 || bi < nblk;
+      if (!held) bi = K;
+      double* src = Ls + slot(bi, K) * kBlk + l * kLd;
+      double v[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = DK[l * kLd + c];
+      for (int c = 0; c < 16; ++c) v[c] = src[c];
       bool bad = false;
+      double myil = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        if (lane < 16) s_col[k & 1][l] = a[k];
-        asm volatile("" ::: "memory");
-        double colk[16];
+        const double pk = lane_bcast(v[k], k);
+        bad = bad || !(pk > tol) || !isfinite(pk);
+        const double il = rsqrt_f64(fmax(pk, 1e-300));
+        const double t = v[k] * (il * il);
 #pragma unroll
-        for (int j = k; j < 16; ++j) colk[j] = s_col[k & 1][j];
-        const double pk = colk[k];
-        if (!(pk > s_tol) || !isfinite(pk)) bad = true;
-        il[k] = rsqrt_f64(fmax(pk, 1e-300));
-        if (l > k) a[k] *= il[k];
-        else if (l == k) a[k] = pk * il[k];
-#pragma unroll
-        for (int j = k + 1; j < 16; ++j)
-          if (l >= j) a[j] -= a[k] * (colk[j] * il[k]);
+        for (int j = k + 1; j < 16; ++j) v[j] = fma(-t, lane_bcast(v[k], j), v[j]);
+        v[k] *= il;
+        if (l == k) myil = il;
       }
-      if (lane < 16) {
+      if (grp == 0) {
+        if (tri == 0) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const double v = c <= l ? a[c] : 0.0;
-          DK[l * kLd + c] = v;
-          s_lkk[l * kLd + c] = v;
+          for (int c = 0; c < 16; ++c) s_diag[l * kLd + c] = c <= l ? v[c] : 0.0;
+          s_rdiag[16 * K + l] = myil;
+          if (lane == 0 && bad) s_fail = 1;
         }
-      }
-      if (lane == 0 && bad) s_fail = 1;
-      asm volatile("" ::: "memory");
-      // column l of L_KK^{-1} by forward substitution (lane l < 16), L read back from LDS as
-      // broadcasts
-      double x[16];
+      } else if (held) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double acc = (i == l) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc -= s_lkk[i * kLd + k] * x[k];
-        x[i] = (i >= l) ? acc * il[i] : 0.0;
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) s_dinv[i * kLd + l] = x[i];
+        for (int c = 0; c < 16; ++c) src[c] = v[c];
       }
     }
     __syncthreads();
     if (s_fail) {
-      if (threadIdx.x == 0) *status = kDevSingular;
+      if (threadIdx.x == 0) *a.status = kDevSingular;
       return;
     }
-    for (int e = threadIdx.x; e < 256; e += 256) Dinv[K * 256 + e] = s_dinv[(e >> 4) * kLd + (e & 15)];
-    // (b) panel: L_iK = A_iK L_KK^{-T} = A_iK (L_KK^{-1})^T, block rows i > K over waves
-    for (int i = K + 1 + wave; i < nblk; i += 4) {
-      double* Ai = Ls + slot(i, K) * kBlk;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      acc = mma_abt(Ai, (const double*)s_dinv, acc, lane, 1.0);
-      store_acc(Ai, acc, lane);
+    // factored diagonal block into place (no one reads slot (K, K) during the trailing update)
+    {
+      double* DK = Ls + slot(K, K) * kBlk;
+      for (int e = threadIdx.x; e < 16 * kLd; e += 1024) DK[e] = s_diag[e];
     }
-    __syncthreads();
-    // (c) trailing update: A_ij -= L_iK L_jK^T for K < j <= i
-    const int rem = nblk - 1 - K;
-    const int pairs = rem * (rem + 1) / 2;
-    for (int q = wave; q < pairs; q += 4) {
-      int ii = 0;
-      while ((ii + 1) * (ii + 2) / 2 <= q) ++ii;
-      const int jj = q - ii * (ii + 1) / 2;
+    // trailing update: A_ij -= L_iK L_jK^T for K < j <= i
+    const int pairs = below * (below + 1) / 2;
+    for (int q = wave; q < pairs; q += kCholWaves) {
+      int ii, jj;
+      slot_ij(q, ii, jj);
       const int i = K + 1 + ii, j = K + 1 + jj;
       double* Aij = Ls + slot(i, j) * kBlk;
       d4 acc = load_acc(Aij, lane);
@@ -194,205 +271,248 @@ __global__ __launch_bounds__(256) void k_chol_blocked(int P, const double* __res
     }
     __syncthreads();
   }
-  if (kInLds)
-#pragma unroll 8
-    for (int e = threadIdx.x; e < nslots * kBlk; e += 256) Lp[e] = Ls[e];
+  // inverse diagonal blocks, column l by lanes l (forward substitution in column order)
+  for (int D = wave; D < nblk; D += kCholWaves) {
+    double* Lb = Ls + slot(D, D) * kBlk;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = i == l ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      x[k] *= s_rdiag[16 * D + k];
+#pragma unroll
+      for (int i = k + 1; i < 16; ++i) x[i] = fma(-Lb[i * kLd + k], x[k], x[i]);
+    }
+    if (lane < 16)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Lb[i * kLd + l] = x[i];  // W_DD (lower; zeros above)
+  }
+  __syncthreads();
+  // off-diagonal blocks of W, one block row at a time (rows < I are already W)
+  for (int I = 1; I < nblk; ++I) {
+    constexpr int kTasks = kMaxBlk / kCholWaves;
+    d4 res[kTasks];
+    const double* WII = Ls + slot(I, I) * kBlk;
+#pragma unroll
+    for (int t = 0; t < kTasks; ++t) {
+      const int K = wave + kCholWaves * t;
+      if (K < I) {
+        d4 sacc = {0.0, 0.0, 0.0, 0.0};
+        for (int J = K; J < I; ++J) sacc = mma_ab(Ls + slot(I, J) * kBlk, Ls + slot(J, K) * kBlk, sacc, lane);
+        d4 w = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) w = mfma(-WII[(lane & 15) * kLd + 4 * ks + (lane >> 4)], sacc[ks], w);
+        res[t] = w;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kTasks; ++t) {
+      const int K = wave + kCholWaves * t;
+      if (K < I) store_acc(Ls + slot(I, K) * kBlk, res[t], lane);
+    }
+    __syncthreads();
+  }
+  if (kInLds) copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, 1024);
 }
 
-// Solve L L^T Z = B for 16 columns per wave (64 per workgroup); the factor is staged in LDS
-// when it fits.  NB > 0: exactly NB blocks, loops unrolled so the right-hand sides stay in
-// registers; NB == 0: any nblk <= 64 (right-hand sides in scratch).
-// mode 0: write Z into the slice-major core (core[i * P + p] = Z[p][i]).
-// mode 1: leverage rows: l_i = ||L^{-1} g_i||^2 with g_i = row i of the core (B^T = G_(2));
-//         writes the integer weights Q_i = floor(l_i / P * 2^52).
-template <typename Real, bool kInLds, int NB>
-__global__ __launch_bounds__(256) void k_chol_solve(int P, int In, const double* __restrict__ Lp,
-                                                    const double* __restrict__ Dinv, const double* __restrict__ B,
-                                                    void* core, uint64_t* Q, int mode, const int* status) {
-  extern __shared__ double lds[];
-  if (*status != kDevOk) return;
-  constexpr int kCap = NB > 0 ? NB : 64;
-  constexpr int kUnroll = NB > 0 ? NB : 1;
-  const int nblk = NB > 0 ? NB : (P + 15) / 16;
-  const int nslots = nblk * (nblk + 1) / 2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* Ls = Lp;
-  const double* Ds = Dinv;
-  if (kInLds) {
-    double* l2 = lds;
-    double* d2 = lds + nslots * kBlk;
-#pragma unroll 8
-    for (int e = threadIdx.x; e < nslots * kBlk; e += 256) l2[e] = Lp[e];
-#pragma unroll 8
-    for (int e = threadIdx.x; e < nblk * 256; e += 256) d2[(e >> 8) * kBlk + ((e >> 4) & 15) * kLd + (e & 15)] = Dinv[e];
+// ---------------------------------------------------------------------------------------
+// Right-hand sides in row form (row i = b_i, P doubles).  Workgroups [0, solve_groups) solve
+// 16 rows each: z_i = W^T (W b_i), written as row i of the core (slice-major, FP64).
+// Workgroups [solve_groups, +lev_groups) take 16 rows each of a core unfolding G_(2) and
+// write Q_i = floor(||W g_i||^2 / P * 2^52); the last of them to finish turns Q into the
+// inclusive table C in place.  Each wave takes the 16-row blocks K = wave, wave + 4, ...
+__device__ void block_scan_u64(uint64_t* Q, int n) {
+  __shared__ uint64_t part[256];
+  const int t = threadIdx.x;
+  const int per = (n + 255) / 256;
+  const int b0 = t * per, b1 = b0 + per < n ? b0 + per : n;
+  uint64_t s = 0;
+  for (int i = b0; i < b1; ++i) s += Q[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint64_t v = t >= o ? part[t - o] : 0ull;
     __syncthreads();
-    Ls = l2;
-    Ds = d2;
+    part[t] += v;
+    __syncthreads();
   }
-  const int dstride = kInLds ? kBlk : 256;
-  const int dld = kInLds ? kLd : 16;
-  const int col = blockIdx.x * 64 + wave * 16 + (lane & 15);
-  const bool live = col < In;
-  const int ar = lane & 15, ak = lane >> 4;
-  d4 Y[kCap];
-#pragma unroll kUnroll
-  for (int K = 0; K < kCap; ++K) {
-    if (K < nblk) {
+  uint64_t run = t > 0 ? part[t - 1] : 0ull;
+  for (int i = b0; i < b1; ++i) {
+    run += Q[i];
+    Q[i] = run;
+  }
+}
+
+template <bool kWInLds, int T>
+__global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double s_red[4][16];
+  __shared__ int s_last;
+  if (*a.status != kDevOk) return;
+  constexpr int kLdB = 17;
+  const int P = a.P;
+  const int nblk = (P + 15) / 16;
+  const int nslots = nblk * (nblk + 1) / 2;
+  const bool lev = (int)blockIdx.x >= a.solve_groups;
+  const int grp = lev ? (int)blockIdx.x - a.solve_groups : (int)blockIdx.x;
+  const double* Wg = lev ? a.Wlev : a.Wsol;
+  const double* Bsrc = lev ? a.Blev : a.Bsol;
+  const int In = lev ? a.In_lev : a.In_sol;
+  const int i0 = 16 * grp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
+  double* Ws = lds + nblk * 16 * kLdB;
+  {
+    // right-hand sides, transposed into Bs (batched loads: one round trip per 8 per thread)
+    const int cnt = 16 * nblk * 16;
+    constexpr int kB = 8;
+    for (int base = 0; base < cnt; base += kB * 256) {
+      double v[kB];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int p = 16 * K + 4 * r + ak;
-        double v = 0.0;
-        if (live && p < P) {
-          if (mode == 0) v = B[(int64_t)p * In + col];
-          else v = (double)((const Real*)core)[(int64_t)col * P + p];
-        }
-        Y[K][r] = v;
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + 256 * q;
+        const int j = e / (nblk * 16), p = e - j * (nblk * 16);
+        const bool ok = e < cnt && i0 + j < In && p < P;
+        v[q] = ok ? Bsrc[(int64_t)(i0 + j) * P + p] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + 256 * q;
+        const int j = e / (nblk * 16), p = e - j * (nblk * 16);
+        if (e < cnt) Bs[p * kLdB + j] = v[q];
       }
     }
   }
-  // forward: Y_K = L_KK^{-1} (B_K - sum_{J<K} L_KJ Y_J)
-#pragma unroll kUnroll
-  for (int K = 0; K < kCap; ++K) {
+  if (kWInLds)
+    copy_batched<8>((double2*)Ws, (const double2*)Wg, (int64_t)nslots * kBlk / 2, threadIdx.x, 256);
+  __syncthreads();
+  const double* W = kWInLds ? Ws : Wg;
+  // Y_K = sum_{J <= K} W_KJ B_J
+  d4 Y[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int K = wave + 4 * t;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
     if (K < nblk) {
-      // two independent accumulation chains (even / odd J), combined in a fixed order
-      d4 acc = Y[K], acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll kUnroll
-      for (int J = 0; J < kCap; ++J) {
-        if (J < K) {
-          const double* LKJ = Ls + slot(K, J) * kBlk;
+      for (int J = 0; J <= K; ++J) {
+        const double* WKJ = W + slot(K, J) * kBlk;
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            if (J & 1)
-              acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-LKJ[ar * kLd + 4 * ks + ak], Y[J][ks], acc1, 0, 0, 0);
-            else
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-LKJ[ar * kLd + 4 * ks + ak], Y[J][ks], acc, 0, 0, 0);
-          }
-        }
+        for (int ks = 0; ks < 4; ++ks)
+          acc = mfma(WKJ[r16 * kLd + 4 * ks + k4], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
       }
-      acc += acc1;
-      d4 y = {0.0, 0.0, 0.0, 0.0};
-      const double* D = Ds + K * dstride;
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        y = __builtin_amdgcn_mfma_f64_16x16x4f64(D[ar * dld + 4 * ks + ak], acc[ks], y, 0, 0, 0);
-      Y[K] = y;
     }
+    Y[t] = acc;
   }
-  if (mode == 1) {
+  if (lev) {
     double s = 0.0;
-#pragma unroll kUnroll
-    for (int K = 0; K < kCap; ++K)
-      if (K < nblk)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s += Y[K][r] * Y[K][r];
-    // lanes c, c + 16, c + 32, c + 48 hold the four row groups of column c
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s += Y[t][r] * Y[t][r];
+    // lanes c, c + 16, c + 32, c + 48 hold four row groups of column c
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (live && lane < 16) {
-      const double p = s / (double)P;
-      Q[col] = (uint64_t)floor(p * 4503599627370496.0);  // 2^52
+    if (lane < 16) s_red[wave][lane] = s;
+    __syncthreads();
+    if (threadIdx.x < 16 && i0 + (int)threadIdx.x < In) {
+      const int j = threadIdx.x;
+      const double lv = ((s_red[0][j] + s_red[1][j]) + s_red[2][j]) + s_red[3][j];
+      a.Q[i0 + j] = (uint64_t)floor(lv / (double)P * 4503599627370496.0);  // 2^52
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == (unsigned)(a.lev_groups - 1);
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      block_scan_u64(a.Q, In);
+      if (threadIdx.x == 0) *a.counter = 0u;
     }
     return;
   }
-  // backward: Z_K = L_KK^{-T} (Y_K - sum_{J>K} L_JK^T Z_J)
-#pragma unroll kUnroll
-  for (int K = kCap - 1; K >= 0; --K) {
-    if (K < nblk) {
-      d4 acc = Y[K], acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll kUnroll
-      for (int J = 0; J < kCap; ++J) {
-        if (J > K && J < nblk) {
-          const double* LJK = Ls + slot(J, K) * kBlk;
+  // Z_K = sum_{J >= K} W_JK^T Y_J
+  __syncthreads();
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            if (J & 1)
-              acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-LJK[(4 * ks + ak) * kLd + ar], Y[J][ks], acc1, 0, 0, 0);
-            else
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-LJK[(4 * ks + ak) * kLd + ar], Y[J][ks], acc, 0, 0, 0);
-          }
-        }
-      }
-      acc += acc1;
-      d4 z = {0.0, 0.0, 0.0, 0.0};
-      const double* D = Ds + K * dstride;
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        z = __builtin_amdgcn_mfma_f64_16x16x4f64(D[(4 * ks + ak) * dld + ar], acc[ks], z, 0, 0, 0);
-      Y[K] = z;
-    }
-  }
-  if (!live) return;
-  Real* out = (Real*)core;
-#pragma unroll kUnroll
-  for (int K = 0; K < kCap; ++K)
+  for (int t = 0; t < T; ++t) {
+    const int K = wave + 4 * t;
     if (K < nblk)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int p = 16 * K + 4 * r + ak;
-        if (p < P) out[(int64_t)col * P + p] = (Real)Y[K][r];
+      for (int r = 0; r < 4; ++r) Bs[(16 * K + 4 * r + k4) * kLdB + r16] = Y[t][r];
+  }
+  __syncthreads();
+  const bool live = i0 + r16 < In;
+  double* out = a.core + (int64_t)(i0 + r16) * P;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int K = wave + 4 * t;
+    if (K < nblk) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int J = K; J < nblk; ++J) {
+        const double* WJK = W + slot(J, K) * kBlk;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          acc = mfma(WJK[(4 * ks + k4) * kLd + r16], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = 16 * K + 4 * r + k4;
+        if (live && p < P) out[p] = acc[r];
+      }
+    }
+  }
 }
 
-template <typename Real, bool kInLds>
-void solve_dispatch(int nblk, unsigned blocks, size_t lds, int P, int In, const double* Lp, const double* Dinv,
-                    const double* B, void* core, uint64_t* Q, int mode, const int* status, hipStream_t s) {
-  const size_t sh = kInLds ? lds : 0;
-  switch (nblk) {
-#define TRALS_SOLVE_CASE(NB) \
-  case NB: k_chol_solve<Real, kInLds, NB><<<blocks, 256, sh, s>>>(P, In, Lp, Dinv, B, core, Q, mode, status); break;
-    TRALS_SOLVE_CASE(1)
-    TRALS_SOLVE_CASE(2)
-    TRALS_SOLVE_CASE(3)
-    TRALS_SOLVE_CASE(4)
-    TRALS_SOLVE_CASE(5)
-    TRALS_SOLVE_CASE(6)
-    TRALS_SOLVE_CASE(7)
-    TRALS_SOLVE_CASE(8)
-    TRALS_SOLVE_CASE(9)
-#undef TRALS_SOLVE_CASE
-    default: k_chol_solve<Real, kInLds, 0><<<blocks, 256, sh, s>>>(P, In, Lp, Dinv, B, core, Q, mode, status);
-  }
+template <bool kWInLds>
+hipError_t trisolve_dispatch(const TriArgs& a, int nblk, unsigned grid, size_t lds, hipStream_t s) {
+  if (nblk <= 4) k_trisolve<kWInLds, 1><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 8) k_trisolve<kWInLds, 2><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 16) k_trisolve<kWInLds, 4><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 32) k_trisolve<kWInLds, 8><<<grid, 256, lds, s>>>(a);
+  else k_trisolve<kWInLds, 16><<<grid, 256, lds, s>>>(a);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 size_t chol_factor_doubles(int P) {
   const int nblk = (P + 15) / 16;
-  return (size_t)nblk * (nblk + 1) / 2 * kBlk + (size_t)nblk * 256;
+  return (size_t)nblk * (nblk + 1) / 2 * kBlk;
 }
 
-hipError_t launch_chol_factor(int P, const double* H, double* F, int* status, hipStream_t s) {
+hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s) {
   const int nblk = (P + 15) / 16;
-  double* Lp = F;
-  double* Dinv = F + (size_t)nblk * (nblk + 1) / 2 * kBlk;
+  if (nblk > kMaxBlk || rows < 1) return hipErrorInvalidValue;
+  k_syrk<<<(unsigned)(nblk * (nblk + 1) / 2), 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
+  const int nblk = (a.P + 15) / 16;
+  if (nblk > kMaxBlk) return hipErrorInvalidValue;
   if (nblk <= kLdsBlocks) {
-    const size_t lds = (size_t)nblk * (nblk + 1) / 2 * kBlk * sizeof(double);
-    k_chol_blocked<true><<<1, 256, lds, s>>>(P, H, Lp, Dinv, status);
+    const size_t lds = chol_factor_doubles(a.P) * sizeof(double);
+    k_chol<true><<<1, 1024, lds, s>>>(a);
   } else {
-    k_chol_blocked<false><<<1, 256, 0, s>>>(P, H, Lp, Dinv, status);
+    k_chol<false><<<1, 1024, 0, s>>>(a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_chol_solve(int P, int In, const double* F, const double* B, void* core, int real_dtype,
-                             uint64_t* Q, int mode, const int* status, hipStream_t s) {
-  const int nblk = (P + 15) / 16;
-  if (nblk > 64) return hipErrorInvalidValue;
-  const double* Lp = F;
-  const double* Dinv = F + (size_t)nblk * (nblk + 1) / 2 * kBlk;
-  const unsigned blocks = (unsigned)((In + 63) / 64);
-  const size_t lds = ((size_t)nblk * (nblk + 1) / 2 + nblk) * kBlk * sizeof(double);
-  const bool in_lds = nblk <= kLdsBlocks;
-  if (real_dtype == 0) {
-    if (in_lds) solve_dispatch<double, true>(nblk, blocks, lds, P, In, Lp, Dinv, B, core, Q, mode, status, s);
-    else solve_dispatch<double, false>(nblk, blocks, lds, P, In, Lp, Dinv, B, core, Q, mode, status, s);
-  } else if (real_dtype == 1) {
-    if (in_lds) solve_dispatch<float, true>(nblk, blocks, lds, P, In, Lp, Dinv, B, core, Q, mode, status, s);
-    else solve_dispatch<float, false>(nblk, blocks, lds, P, In, Lp, Dinv, B, core, Q, mode, status, s);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+hipError_t launch_trisolve(const TriArgs& args, hipStream_t s) {
+  TriArgs a = args;
+  const int nblk = (a.P + 15) / 16;
+  if (nblk > kMaxBlk) return hipErrorInvalidValue;
+  a.solve_groups = a.Wsol ? (a.In_sol + 15) / 16 : 0;
+  a.lev_groups = a.Wlev ? (a.In_lev + 15) / 16 : 0;
+  const unsigned grid = (unsigned)(a.solve_groups + a.lev_groups);
+  if (grid == 0) return hipSuccess;
+  const size_t bbytes = (size_t)nblk * 16 * 17 * sizeof(double);
+  const bool w_in_lds = nblk <= kLdsBlocks;
+  const size_t lds = bbytes + (w_in_lds ? chol_factor_doubles(a.P) * sizeof(double) : 0);
+  if (w_in_lds) return trisolve_dispatch<true>(a, nblk, grid, lds, s);
+  return trisolve_dispatch<false>(a, nblk, grid, lds, s);
 }
 
 }  // namespace trals

@@ -36,6 +36,26 @@ __device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64
   }
 }
 
+// Copies n elements src -> dst (typically global -> LDS) with each thread keeping kBatch loads
+// in flight before it stores, so that a latency-bound staging pass costs one memory round trip
+// per kBatch elements per thread instead of one per element.  Requires n >= 1.
+template <int kBatch, typename T>
+__device__ __forceinline__ void copy_batched(T* dst, const T* src, int64_t n, int tid, int nthreads) {
+  for (int64_t base = 0; base < n; base += (int64_t)kBatch * nthreads) {
+    T v[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int64_t e = base + tid + (int64_t)q * nthreads;
+      v[q] = src[e < n ? e : n - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int64_t e = base + tid + (int64_t)q * nthreads;
+      if (e < n) dst[e] = v[q];
+    }
+  }
+}
+
 // Per-mode view of the ring passed by value to kernels.
 struct Ring {
   int N;

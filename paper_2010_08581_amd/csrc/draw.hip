@@ -1,0 +1,217 @@
+// Sampler and sketch of one core update, fused (Algorithm 3 draws, Definition 5 rescaling,
+// Algorithm 4 / eq. (5) subchain rows).
+//
+// Draws.  Sample j, mode draw k (mode m = (n+1+k) mod N) takes 64-bit word (k mod 4) of the
+// Philox4x64-10 block with key (seed, stream_id) and counter (j, k/4, u, 0), u the update
+// number.  With the mode's inclusive integer table C (total T = C[I-1]) the draw is
+// t = floor(r T / 2^64) (high word of the 128-bit product) and i = min{i : t < C_i}, found by
+// binary search; zero-weight entries are never drawn.  The rescaling is w = 1/sqrt(J q) with
+// q = prod_k Q_{i_k} / T_k the exact probability of the tuple, multiplied in FP64 in k order.
+//
+// Sketch.  Row j is w_j times the product of the sampled lateral slices
+// G^(m_0)(:, i_{m_0}, :) ... G^(m_{N-2})(:, i_{m_{N-2}}, :) (an R_n x R_{n-1} matrix M_j),
+// stored with column a*R_n + b holding w_j M_j(b, a).  (This column order is a permutation
+// of the paper's a + R_{n-1} b; it makes the solution columns the lateral slices of the new
+// core in slice-major storage.)  Products run in FP64 from the FP64 cores; the row is
+// rounded once to the sketch type.
+//
+// One workgroup handles jb samples: jb threads draw (tables staged in LDS when they fit),
+// then thread (s, b) carries row b of M_s through the chain, the slices of all jb samples
+// staged in LDS (loads batched, one round trip per eight per thread), and the finished rows
+// leave through LDS as one contiguous store.
+#include "kernels.h"
+
+namespace trals {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr size_t kDrawTableBytes = 48 * 1024;  // staged sampling tables per workgroup
+
+template <typename TA, int RM>
+__global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
+  extern __shared__ double lds[];
+  if (*a.status != kDevOk) return;
+  const int N = a.ring.N;
+  const int K = N - 1;
+  const int n = a.n;
+  const int jb = a.jb;
+  constexpr int kSlice = RM * RM + 1;  // odd stride in doubles: samples fall on distinct banks
+  constexpr int kB = 8;                // loads in flight per thread while staging
+  double* S = lds;                                    // jb * kSlice
+  double* s_w = S + (size_t)jb * kSlice;              // jb
+  int32_t* s_idx = (int32_t*)(s_w + jb);              // jb * K (padded to even)
+  uint64_t* tab = (uint64_t*)(s_w + jb + (jb * K + 1) / 2);
+  const int64_t j0 = (int64_t)blockIdx.x * jb;
+  const int tid = threadIdx.x;
+
+  // ---- draws ----
+  int off[kMaxOrder];
+  if (a.tables_in_lds) {
+    int o = 0;
+    for (int k = 0; k < K; ++k) {
+      int m = n + 1 + k;
+      if (m >= N) m -= N;
+      off[k] = o;
+      const int I = a.ring.dims[m];
+      copy_batched<kB>(tab + o, a.cdf.p[m], I, tid, kThreads);
+      o += I;
+    }
+    __syncthreads();
+  }
+  if (tid < jb) {
+    const int64_t j = j0 + tid;
+    if (j < a.J) {
+      uint64_t x[4] = {0, 0, 0, 0};
+      double q = 1.0;
+      for (int k = 0; k < K; ++k) {
+        const int word = k & 3;
+        if (word == 0) {
+          x[0] = (uint64_t)j;
+          x[1] = (uint64_t)(k >> 2);
+          x[2] = a.u;
+          x[3] = 0;
+          philox4x64_10(x, a.seed, a.stream_id);
+        }
+        const uint64_t r = word == 0 ? x[0] : word == 1 ? x[1] : word == 2 ? x[2] : x[3];
+        int m = n + 1 + k;
+        if (m >= N) m -= N;
+        const uint64_t* C = a.tables_in_lds ? tab + off[k] : a.cdf.p[m];
+        const int I = a.ring.dims[m];
+        const uint64_t T = C[I - 1];
+        const uint64_t t = __umul64hi(r, T);
+        int lo = 0, hi = I - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (C[mid] > t) hi = mid;
+          else lo = mid + 1;
+        }
+        const uint64_t Qi = C[lo] - (lo > 0 ? C[lo - 1] : 0ull);
+        q = q * ((double)Qi / (double)T);
+        s_idx[tid * K + k] = lo;
+        a.idx[j * K + k] = lo;
+      }
+      const double w = 1.0 / sqrt((double)a.J * q);
+      s_w[tid] = w;
+      a.w[j] = w;
+    } else {
+      for (int k = 0; k < K; ++k) s_idx[tid * K + k] = 0;
+      s_w[tid] = 0.0;
+    }
+  }
+
+  // ---- subchain rows ----
+  const int Rn = a.ring.ranks[n];
+  const int sj = tid / Rn, b = tid - sj * Rn;
+  const bool live = sj < jb;
+  double row[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) row[c] = 0.0;
+  int rin = Rn;
+  for (int k = 0; k < K; ++k) {
+    int m = n + 1 + k;
+    if (m >= N) m -= N;
+    const int rout = a.ring.ranks[m];
+    const int ssz = rin * rout;
+    const double* core = a.cores.p[m];
+    __syncthreads();  // draws visible / previous slices consumed
+    // stage the jb slices (rin x rout each, contiguous in slice-major storage)
+    const int tot = jb * ssz;
+    for (int base = 0; base < tot; base += kB * kThreads) {
+      double v[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + tid + kThreads * q;
+        const int ec = e < tot ? e : tot - 1;  // clamped: every load is in bounds
+        const int s = ec / ssz, o = ec - s * ssz;
+        v[q] = core[(int64_t)s_idx[s * K + k] * ssz + o];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + tid + kThreads * q;
+        const int s = e / ssz, o = e - s * ssz;
+        if (e < tot) S[s * kSlice + o] = v[q];
+      }
+    }
+    __syncthreads();
+    if (live) {
+      // rin, rout are uniform: the guards below are scalar branches
+      const double* Sj = S + sj * kSlice;
+      if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < RM; ++c)
+          if (c < rout) row[c] = Sj[b * rout + c];
+      } else {
+        double nr[RM];
+#pragma unroll
+        for (int co = 0; co < RM; ++co) nr[co] = 0.0;
+#pragma unroll
+        for (int ci = 0; ci < RM; ++ci) {
+          if (ci < rin) {
+            const double v = row[ci];
+#pragma unroll
+            for (int co = 0; co < RM; ++co)
+              if (co < rout) nr[co] = fma(v, Sj[ci * rout + co], nr[co]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < RM; ++c) row[c] = nr[c];
+      }
+    }
+    rin = rout;
+  }
+  // rin == R_{n-1}: row b of M_s is row[0 .. R_{n-1})
+  const int Rp = rin;
+  const int P = Rn * Rp;
+  __syncthreads();
+  TA* out = (TA*)S;  // jb x P staging (jb * P <= 256 * RM < jb * kSlice doubles)
+  if (live) {
+    const double w = s_w[sj];
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      if (c < Rp) out[sj * P + c * Rn + b] = (TA)(w * row[c]);
+  }
+  __syncthreads();
+  const int64_t rows = a.J - j0 < jb ? a.J - j0 : jb;
+  TA* A = (TA*)a.A + j0 * P;
+  for (int64_t e = tid; e < rows * P; e += kThreads) A[e] = out[e];
+}
+
+template <typename TA>
+hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
+  int rmax = 0;
+  for (int m = 0; m < a.ring.N; ++m) rmax = a.ring.ranks[m] > rmax ? a.ring.ranks[m] : rmax;
+  const int RM = rmax <= 4 ? 4 : rmax <= 8 ? 8 : rmax <= 16 ? 16 : 32;
+  if (rmax > 32) return hipErrorInvalidValue;
+  const int Rn = a.ring.ranks[a.n];
+  // samples per workgroup: one thread per (sample, row b); slice staging within 64 KB
+  int jb = kThreads / Rn;
+  const int cap = (int)((64 * 1024) / ((RM * RM + 1) * sizeof(double)));
+  jb = jb < cap ? jb : cap;
+  if (jb < 1) return hipErrorInvalidValue;
+  a.jb = jb;
+  const int K = a.ring.N - 1;
+  size_t tbytes = 0;
+  for (int k = 0; k < K; ++k) tbytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
+  a.tables_in_lds = tbytes <= kDrawTableBytes;
+  const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2) * sizeof(double);
+  const size_t lds = head + (a.tables_in_lds ? tbytes : 0);
+  const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);
+  switch (RM) {
+    case 4: k_draw<TA, 4><<<blocks, kThreads, lds, s>>>(a); break;
+    case 8: k_draw<TA, 8><<<blocks, kThreads, lds, s>>>(a); break;
+    case 16: k_draw<TA, 16><<<blocks, kThreads, lds, s>>>(a); break;
+    default: k_draw<TA, 32><<<blocks, kThreads, lds, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_draw(const DrawArgs& a, int sketch_dtype, hipStream_t s) {
+  if (sketch_dtype == 0) return draw_dispatch<double>(a, s);
+  if (sketch_dtype == 1) return draw_dispatch<float>(a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace trals

@@ -23,31 +23,25 @@ hipError_t launch_core_normal(void* dst, int dst_dtype, int64_t count, uint64_t 
                               int core, hipStream_t s);
 
 // ---- per update ----
-struct SampleArgs {
+// Fused sampler and sketch: draws J tuples (indices idx[j * (N-1) + k], rescaling w[j]) and
+// writes the J x P sketched rows A (column a*R_n + b = w_j M_j(b, a)).
+struct DrawArgs {
   Ring ring;
   int n;
   int64_t J;
   uint64_t seed, stream_id, u;
   PerMode<const uint64_t> cdf;
+  PerMode<const double> cores;  // slice-major FP64 cores
   int32_t* idx;
   double* w;
+  void* A;                      // sketch type: FP64 (0) or FP32 (1)
   const int* status;
+  int jb;                       // samples per workgroup (set by launch_draw)
+  int tables_in_lds;            // set by launch_draw
 };
-hipError_t launch_sample(const SampleArgs& a, hipStream_t s);
+hipError_t launch_draw(const DrawArgs& a, int sketch_dtype, hipStream_t s);
 
-struct SketchArgs {
-  Ring ring;
-  int n;
-  int64_t J;
-  PerMode<const void> cores;  // slice-major cores in the compute type
-  const int32_t* idx;
-  const double* w;
-  void* A;                    // J x P sketched design rows, column a*R_n + b
-  const int* status;
-};
-hipError_t launch_sketch(const SketchArgs& a, int real_dtype, hipStream_t s);
-
-// Fused normal equations [H | B] = A^T [A | X~] on FP64 matrix cores (split-K partials).
+// Fused normal equations [H | B] = A^T [A | X~] on matrix cores (split-K partials).
 struct NormalEqArgs {
   const void* A;              // J x P sketched rows (compute type)
   const void* panel;          // mode-n panel (compute type)
@@ -59,6 +53,7 @@ struct NormalEqArgs {
   int64_t chunk;              // sample rows per split
   int P, In;
   int gram_tiles;             // 64-wide column tiles of the Gram part
+  int col_tiles, tiles, splits;  // filled in by launch_normal_eq
   double* Hpart;              // splits x P x P (lower triangle written)
   double* Bpart;              // splits x P x I_n
   const int* status;
@@ -70,24 +65,50 @@ struct NormalEqPlan {
   int64_t chunk;
 };
 constexpr int kPlanCUs = 256;  // MI355X compute units (launch sizing)
-NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int panel_bytes, int num_cu);
-// real_dtype 0: FP64 sketch and panel; 1: FP32 sketch and panel (FP64 matrix cores);
-// 2: BF16 form (FP32 sketch, BF16 panel, BF16 matrix cores with FP32 accumulation).
-hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int real_dtype, hipStream_t s);
-// out = fixed-order sum of nparts partial arrays of count doubles (lower != 0: symmetrise a
-// P x P matrix from its lower triangle).
-hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int lower, double* out,
+// ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel (FP32 matrix
+// cores per 32-row stage, FP64 accumulation); 2: BF16 form (FP32 sketch, BF16 panel, BF16
+// matrix cores with FP32 accumulation).
+NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
+hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s);
+// out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:
+// symmetrise a P x P matrix from its lower triangle; mode 2: transpose P x (count / P) to
+// (count / P) x P.
+hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int mode, double* out,
                                const int* status, hipStream_t s);
 
-// Blocked FP64 Cholesky of the SPD P x P matrix H (full storage, P <= 1024) into the factor
-// buffer F (chol_factor_doubles(P) doubles).  A non-positive pivot sets *status = kDevSingular.
+// K = A^T A (P x P row-major, lower blocks incl. full diagonal blocks) of an FP64 rows x P
+// row-major matrix A.
+hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const int* status, hipStream_t s);
+
+// Cholesky factorisation of an SPD P x P matrix H (full storage, lower triangle read,
+// P <= 1024) into the inverse factor W = L^{-1} (chol_factor_doubles(P) doubles,
+// block-packed).  A non-positive pivot sets *status = kDevSingular.
+struct CholArgs {
+  int P;
+  const double* H;
+  double* W;
+  int* status;
+};
 size_t chol_factor_doubles(int P);
-hipError_t launch_chol_factor(int P, const double* H, double* F, int* status, hipStream_t s);
-// With the factor F of H: mode 0 solves H Z = B (P x I_n) and writes lateral slice i of the
-// core as column i of Z (compute type); mode 1 writes the leverage weights
-// Q_i = floor(||L^{-1} g_i||^2 / P * 2^52) of the rows g_i of the core (B unused).
-hipError_t launch_chol_solve(int P, int In, const double* F, const double* B, void* core, int real_dtype,
-                             uint64_t* Q, int mode, const int* status, hipStream_t s);
+hipError_t launch_chol(const CholArgs& a, hipStream_t s);
+
+// With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
+// leverage rows Q_i = floor(||W g_i||^2 / P * 2^52) of Blev (In_lev x P, a core unfolding)
+// turned into the inclusive table in place.  Either part is skipped when its W is NULL.
+// counter: a device word that is zero between launches.
+struct TriArgs {
+  int P, In_sol, In_lev;
+  const double* Wsol;
+  const double* Wlev;
+  const double* Bsol;
+  const double* Blev;
+  double* core;
+  uint64_t* Q;
+  unsigned* counter;
+  int solve_groups, lev_groups;  // set by launch_trisolve
+  const int* status;
+};
+hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
 
 // ---- leverage tables (eq. (3)) ----
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s);

@@ -1,4 +1,4 @@
-// Normal equations of the sampled least-squares problem (Algorithm 2, LS step) on FP64 matrix
+// Normal equations of the sampled least-squares problem (Algorithm 2, LS step) on matrix
 // cores, fused with the fiber gather (Algorithm 2, "sample X"):
 //
 //     [ H | B ] = A^T [ A | X~ ],   A = J x P sketched design rows,  X~(j, :) = w_j X(..., :, ...)
@@ -6,10 +6,19 @@
 // One launch covers both products.  The extended column space holds the P Gram columns (read
 // from A, padded to a multiple of 64) followed by the I_n data columns (gathered from the
 // mode-n panel, where row j's fiber is contiguous).  A workgroup owns a (16 MB) x 64 output
-// tile and one chunk of sample rows; its four waves each own 16 columns and all MB row blocks
-// and run v_mfma_f64_16x16x4 on FP64 operands (FP32 storage is widened exactly on the way into
-// LDS).  Gram tiles strictly above the diagonal are skipped; consumers read H's lower triangle.
-// Partial tiles per sample chunk are reduced afterwards in a fixed order (deterministic).
+// tile and one chunk of sample rows; each group of four waves takes every KG-th 32-row stage
+// of the chunk, each wave owning 16 columns and all MB row blocks.  Gram tiles strictly above
+// the diagonal are skipped; consumers read H's lower triangle.  Each lane takes the FP64 row
+// factors of its eight k-steps once per stage (w_j for data tiles, 1 for Gram tiles, 0 for
+// padding rows) and applies them to its B operand.  Partial tiles per sample chunk are
+// reduced afterwards in a fixed order (deterministic).
+//
+// Arithmetic: v_mfma_f64_16x16x4 with FP64 accumulation for FP64 and FP32 data alike (FP32
+// operands widen exactly).  Rounding partial sums of H to FP32 would be an unstructured
+// perturbation of the normal equations, amplified by cond(A)^2 in the solution rather than the
+// cond(A) that FP32 storage of A and X costs.
+//   v_mfma_f64_16x16x4 layouts: A(i, k) lane i + 16 k; B(k, j) lane j + 16 k;
+//     D(i, j) lane j + 16 (i % 4), register i / 4.
 #include "kernels.h"
 
 namespace trals {
@@ -17,111 +26,156 @@ namespace trals {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kColTile = 64;
-constexpr int kKB = 32;         // sample rows per LDS stage (8 MFMA k-steps)
-constexpr int kMaxChunk = 512;  // sample rows per split (row offsets and weights cached in LDS)
+constexpr int kKB = 32;          // sample rows per LDS stage (8 MFMA k-steps)
+constexpr int kMaxChunk = 1024;  // sample rows per split, padding included (row offsets and weights in LDS)
+constexpr int kLdsBytes = 160 * 1024;
 
-template <typename Real, int MB>
-__global__ __launch_bounds__(256) void k_normal_eq(NormalEqArgs a) {
+// LDS bytes of the FP64 / FP32 kernel: KG groups x double-buffered A and B stages.
+constexpr size_t ne_dyn_lds(int mb, int kg, int esz) {
+  return (size_t)kg * 2 * (kKB * (16 * mb + 1) + kKB * (kColTile + 1)) * esz;
+}
+
+template <typename Real, int MB, int KG>
+__global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
-  constexpr int NA = (kKB * RT + 255) / 256;        // A elements per thread per stage
-  constexpr int NB = (kKB * kColTile + 255) / 256;  // B elements per thread per stage
-  __shared__ Real As[2][kKB][RT + 1];
-  __shared__ Real Bs[2][kKB][kColTile + 1];
+  constexpr int NA = kKB * RT / 256;          // A elements per thread per stage (= 2 MB)
+  constexpr int NB = kKB * kColTile / 256;    // B elements per thread per stage (= 8)
+  constexpr int LA = RT + 1, LB = kColTile + 1;
+  constexpr int kStageA = kKB * LA, kStageB = kKB * LB;
+  extern __shared__ __align__(16) unsigned char ne_smem[];
   __shared__ int64_t s_roff[kMaxChunk];
   __shared__ double s_w[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
-  const int ct = blockIdx.x, rt = blockIdx.y, s = blockIdx.z;
+  const int s = blockIdx.x / a.tiles, t = blockIdx.x - s * a.tiles;
+  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
   const int row0 = rt * RT;
   const bool gram = ct < a.gram_tiles;
   const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
   if (gram && col0 >= row0 + RT) return;  // strictly upper Gram tile
   const int64_t r0 = (int64_t)s * a.chunk;
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
+  const int64_t rlast = r1 - 1;
   const int nrows = (int)(r1 - r0);
+  const int stages = (nrows + kKB - 1) / kKB;
+  const int rounds = (stages + KG - 1) / KG;
+  const int npad = rounds * KG * kKB;
   const Real* A = (const Real*)a.A;
   const Real* X = (const Real*)a.panel;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // weights and panel-row offsets of the whole chunk (data tiles)
-  if (!gram) {
-    for (int r = threadIdx.x; r < nrows; r += 256) {
-      const int32_t* ij = a.idx + (r0 + r) * a.K;
+  const int g = threadIdx.x >> 8, tl = threadIdx.x & 255;
+  const int lane = tl & 63, wave = tl >> 6;
+  Real* As = (Real*)ne_smem + (size_t)g * 2 * (kStageA + kStageB);
+  Real* Bs = As + 2 * kStageA;
+  // per chunk row: panel-row offset (data tiles) and the row factor (w_j for data tiles, 1 for
+  // Gram tiles, 0 for the padding rows of the last stage)
+  for (int r = threadIdx.x; r < npad; r += 256 * KG) {
+    const bool v = r < nrows;
+    if (gram) {
+      s_w[r] = v ? 1.0 : 0.0;
+    } else {
       int64_t off = 0;
-      for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      if (v) {
+        const int32_t* ij = a.idx + (r0 + r) * a.K;
+        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      }
       s_roff[r] = off * In;
-      s_w[r] = a.w[r0 + r];
+      s_w[r] = v ? a.w[r0 + r] : 0.0;
     }
-    __syncthreads();
   }
+  __syncthreads();
+  // Loads are unguarded: rows past the chunk are clamped to its last row (their row factor is
+  // 0), columns past P or I_n to the last column (those outputs are not stored).
   Real ra[NA], rb[NB];
   auto load_stage = [&](int base) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int r = e / RT, c = e % RT;
-      ra[q] = (e < kKB * RT && base + r < nrows && row0 + c < P) ? A[(r0 + base + r) * P + row0 + c] : Real(0);
+      const int e = tl + 256 * q;
+      const int r = e / RT, c = e - r * RT;
+      int64_t gr = r0 + base + r;
+      gr = gr < rlast ? gr : rlast;
+      const int gc = row0 + c < P ? row0 + c : P - 1;
+      ra[q] = A[gr * P + gc];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int r = e / kColTile, c = e % kColTile;
-      Real v = Real(0);
-      if (base + r < nrows) {
-        if (gram) {
-          if (col0 + c < P) v = A[(r0 + base + r) * P + col0 + c];
-        } else {
-          if (col0 + c < In) v = X[s_roff[base + r] + col0 + c];
-        }
+      const int r = wave + 4 * q;
+      if (gram) {
+        int64_t gr = r0 + base + r;
+        gr = gr < rlast ? gr : rlast;
+        const int gc = col0 + lane < P ? col0 + lane : P - 1;
+        rb[q] = A[gr * P + gc];
+      } else {
+        const int gc = col0 + lane < In ? col0 + lane : In - 1;
+        rb[q] = X[s_roff[base + r] + gc];
       }
-      rb[q] = v;
     }
   };
   auto store_stage = [&](int buf) {
+    Real* as = As + buf * kStageA;
+    Real* bs = Bs + buf * kStageB;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      if (e < kKB * RT) As[buf][e / RT][e % RT] = ra[q];
+      const int e = tl + 256 * q;
+      const int r = e / RT, c = e - r * RT;
+      as[r * LA + c] = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      Bs[buf][e / kColTile][e % kColTile] = rb[q];
-    }
+    for (int q = 0; q < NB; ++q) bs[(wave + 4 * q) * LB + lane] = rb[q];
   };
   d4 acc[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
-  const int stages = (nrows + kKB - 1) / kKB;
-  load_stage(0);
-  for (int t = 0; t < stages; ++t) {
-    const int buf = t & 1;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  load_stage(g * kKB);
+  for (int u = 0; u < rounds; ++u) {
+    const int buf = u & 1;
+    const int base = (u * KG + g) * kKB;
     store_stage(buf);
     __syncthreads();
-    if (t + 1 < stages) load_stage((t + 1) * kKB);
+    if (u + 1 < rounds) load_stage(base + KG * kKB);
+    const Real* as = As + buf * kStageA;
+    const Real* bs = Bs + buf * kStageB;
+    double wv[kKB / 4];
+#pragma unroll
+    for (int ks = 0; ks < kKB / 4; ++ks) wv[ks] = s_w[base + ks * 4 + k4];
 #pragma unroll
     for (int ks = 0; ks < kKB / 4; ++ks) {
-      const int kr = ks * 4 + (lane >> 4);
-      double b = (double)Bs[buf][kr][wave * 16 + (lane & 15)];
-      if (!gram) b *= s_w[t * kKB + kr < nrows ? t * kKB + kr : 0];
+      const int kr = ks * 4 + k4;
+      const double b = (double)bs[kr * LB + wave * 16 + r16] * wv[ks];
 #pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const double av = (double)As[buf][kr][m * 16 + (lane & 15)];
-        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[m], 0, 0, 0);
-      }
+      for (int m = 0; m < MB; ++m)
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)as[kr * LA + m * 16 + r16], b, acc[m], 0, 0, 0);
     }
   }
-  // D(i, j) of each 16 x 16 block sits in lane j + 16 (i % 4), register i / 4
-  const int col = col0 + wave * 16 + (lane & 15);
+  if constexpr (KG > 1) {
+    // fixed-order sum of the groups' accumulators (group 0 + group 1 + ...)
+    double* red = (double*)ne_smem;
+    __syncthreads();
+    if (g > 0)
+#pragma unroll
+      for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((size_t)((g - 1) * MB + m) * 4 + r) * 256 + tl] = acc[m][r];
+    __syncthreads();
+    if (g > 0) return;
+    for (int h = 1; h < KG; ++h)
+#pragma unroll
+      for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][r] += red[((size_t)((h - 1) * MB + m) * 4 + r) * 256 + tl];
+  }
+  const int col = col0 + wave * 16 + r16;
   if (gram) {
     double* H = a.Hpart + (int64_t)s * P * P;
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * r + (lane >> 4);
-        if (row < P && col < P && col <= row) H[(int64_t)row * P + col] = acc[m][r];
+        const int row = row0 + m * 16 + 4 * r + k4;
+        if (row < P && col <= row) H[(int64_t)row * P + col] = acc[m][r];
       }
   } else {
     double* B = a.Bpart + (int64_t)s * P * In;
@@ -129,7 +183,7 @@ __global__ __launch_bounds__(256) void k_normal_eq(NormalEqArgs a) {
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * r + (lane >> 4);
+        const int row = row0 + m * 16 + 4 * r + k4;
         if (row < P && col < In) B[(int64_t)row * In + col] = acc[m][r];
       }
   }
@@ -143,7 +197,6 @@ __global__ __launch_bounds__(256) void k_normal_eq(NormalEqArgs a) {
 // reads its 8 consecutive k values of an operand with one 16-byte load.
 //   v_mfma_f32_16x16x32_bf16 layouts: A(i, k) at lane i + 16 (k / 8), element k % 8;
 //   B(k, j) at lane j + 16 (k / 8), element k % 8; D(i, j) at lane j + 16 (i / 4), register i % 4.
-typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kKB16 = 64;  // sample rows per stage (two MFMA k-steps of 32)
@@ -161,7 +214,8 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   __shared__ float s_w[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
-  const int ct = blockIdx.x, rt = blockIdx.y, s = blockIdx.z;
+  const int s = blockIdx.x / a.tiles, t = blockIdx.x - s * a.tiles;
+  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
   const int row0 = rt * RT;
   const bool gram = ct < a.gram_tiles;
   const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
@@ -266,30 +320,49 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   }
 }
 
-// out[e] = sum_s parts[s * count + e] in a fixed order.  With lower != 0 the P x P matrix is
-// symmetrised from its lower triangle: out(i, j) = sum_s parts_s(max(i,j), min(i,j)).
+// out = sum over s of parts[s * count + e], in a fixed order: four threads per element sum the
+// partials s = g, g + 4, ... (g = 0..3) and the four sums are added in the order g = 0, 1, 2, 3.
+// mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower triangle,
+// out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n partials are written
+// transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P).
+constexpr int kRedElems = 64;
 __global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__ parts, int nparts, int64_t count,
-                                                      int P, int lower, double* __restrict__ out,
+                                                      int P, int mode, double* __restrict__ out,
                                                       const int* status) {
+  __shared__ double red[4][kRedElems];
   if (*status != kDevOk) return;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+  const int g = threadIdx.x / kRedElems, el = threadIdx.x % kRedElems;
+  const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
+  double acc = 0.0;
+  if (e < count) {
     int64_t src = e;
-    if (lower) {
+    if (mode == 1) {
       const int i = (int)(e / P), j = (int)(e % P);
       src = i >= j ? e : (int64_t)j * P + i;
     }
-    double acc = 0.0;
-#pragma unroll 8
-    for (int s = 0; s < nparts; ++s) acc += parts[s * count + src];
-    out[e] = acc;
+#pragma unroll 4
+    for (int s = g; s < nparts; s += 4) acc += parts[s * count + src];
+  }
+  red[g][el] = acc;
+  __syncthreads();
+  if (g == 0 && e < count) {
+    const double v = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+    if (mode == 2) {
+      const int64_t n = count / P;
+      const int64_t p = e / n, i = e - p * n;
+      out[i * P + p] = v;
+    } else {
+      out[e] = v;
+    }
   }
 }
 
-template <typename Real>
-hipError_t dispatch(const NormalEqArgs& a, int mb, dim3 grid, hipStream_t s) {
+template <typename Real, int KG>
+hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s) {
+  const size_t lds = ne_dyn_lds(mb, KG, sizeof(Real));
   switch (mb) {
 #define TRALS_NE_CASE(MB) \
-  case MB: k_normal_eq<Real, MB><<<grid, 256, 0, s>>>(a); break;
+  case MB: k_normal_eq<Real, MB, KG><<<grid, 256 * KG, lds, s>>>(a); break;
     TRALS_NE_CASE(1)
     TRALS_NE_CASE(2)
     TRALS_NE_CASE(3)
@@ -306,7 +379,7 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
-NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int panel_bytes, int num_cu) {
+NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) {
   NormalEqPlan pl;
   // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding
   if (P <= 128) {
@@ -327,29 +400,44 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int panel_bytes, int num_c
   pl.gram_tiles = (P + kColTile - 1) / kColTile;
   pl.data_tiles = (In + kColTile - 1) / kColTile;
   const int64_t tiles = (int64_t)pl.row_tiles * (pl.gram_tiles + pl.data_tiles);
-  // split the samples so that the launch holds ~3 workgroups per CU, but keep the FP64 partial
-  // traffic below the gathered bytes and every chunk at least one LDS stage long
-  int64_t S = (3 * (int64_t)num_cu + tiles - 1) / tiles;
-  if (In > 0) {
-    const int64_t cap_bytes = (2 * J * In * panel_bytes) / (8 * (int64_t)P * (P + In)) + 1;
-    if (S > cap_bytes) S = cap_bytes;
+  // workgroups resident per CU (LDS-bound) and the rows one split must be a multiple of
+  int per_cu, quantum;
+  if (ne_dtype == 2) {
+    per_cu = 2;
+    quantum = kKB16;
+  } else {
+    const int kg = ne_dtype == 1 ? 2 : 1;
+    const int esz = ne_dtype == 1 ? 4 : 8;
+    const size_t lds = ne_dyn_lds(pl.mb, kg, esz) + (size_t)kMaxChunk * 16;
+    per_cu = (int)(kLdsBytes / lds);
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 2) per_cu = 2;
+    quantum = kg * kKB;
   }
-  if (S > J / kKB) S = J / kKB;
-  if (S < (J + kMaxChunk - 1) / kMaxChunk) S = (J + kMaxChunk - 1) / kMaxChunk;
+  // one round of workgroups over the chip: splits = resident slots / tiles, at least one
+  // quantum of rows per split and at most kMaxChunk rows with the padding of the last round
+  int64_t S = ((int64_t)per_cu * num_cu) / tiles;
   if (S < 1) S = 1;
-  if (S > 65535) S = 65535;
-  int64_t chunk = (J + S - 1) / S;
-  chunk = (chunk + kKB - 1) / kKB * kKB;
+  if (S > J / quantum) S = J / quantum;
+  if (S < 1) S = 1;
+  const int64_t maxchunk = kMaxChunk - quantum;
+  if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
+  const int64_t chunk = (J + S - 1) / S;
   pl.chunk = chunk;
   pl.splits = (int)((J + chunk - 1) / chunk);
   return pl;
 }
 
-hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int real_dtype, hipStream_t s) {
-  dim3 grid(pl.gram_tiles + pl.data_tiles, pl.row_tiles, pl.splits);
-  if (real_dtype == 0) return dispatch<double>(a, pl.mb, grid, s);
-  if (real_dtype == 1) return dispatch<float>(a, pl.mb, grid, s);
-  if (real_dtype == 2) {
+hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, int ne_dtype, hipStream_t s) {
+  NormalEqArgs a = args;
+  a.col_tiles = pl.gram_tiles + pl.data_tiles;
+  a.tiles = pl.row_tiles * a.col_tiles;
+  a.splits = pl.splits;
+  if ((int64_t)pl.splits * a.tiles > 0x7fffffff) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)(pl.splits * a.tiles);
+  if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s);
+  if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s);
+  if (ne_dtype == 2) {
     switch (pl.mb) {
 #define TRALS_NE16_CASE(MB) \
   case MB: k_normal_eq_bf16<MB><<<grid, 256, 0, s>>>(a); break;
@@ -369,12 +457,10 @@ hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int r
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int lower, double* out,
+hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int mode, double* out,
                                const int* status, hipStream_t s) {
-  int64_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  k_reduce_parts<<<(unsigned)blocks, 256, 0, s>>>(parts, nparts, count, P, lower, out, status);
+  const int64_t blocks = (count + kRedElems - 1) / kRedElems;
+  k_reduce_parts<<<(unsigned)blocks, 256, 0, s>>>(parts, nparts, count, P, mode, out, status);
   return hipGetLastError();
 }
 
