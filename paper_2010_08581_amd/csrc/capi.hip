@@ -41,6 +41,10 @@ struct Problem {
   int64_t E;     // prod dims
   int Pmax;
   int64_t Imax;
+  // the tables of the N-1 modes one update draws from fit in the draw kernel's LDS for every
+  // n: device tables then hold the weights Q, summed in LDS by each draw; otherwise the
+  // inclusive sums C, scanned on the device after every table computation
+  bool tables_as_weights;
 };
 
 int P_of(const Problem& p, int n) { return p.ranks[(n + p.N - 1) % p.N] * p.ranks[n]; }
@@ -68,6 +72,14 @@ int validate(const trals_desc* d, Problem* p) {
     p->Imax = p->dims[n] > p->Imax ? p->dims[n] : p->Imax;
   }
   if (p->J < p->Pmax || p->J > ((int64_t)1 << 24)) return TRALS_EINVAL;  // grid-z limit of the split-K partials
+  {
+    int64_t tot = 0, mn = p->dims[0];
+    for (int n = 0; n < p->N; ++n) {
+      tot += p->dims[n];
+      mn = p->dims[n] < mn ? p->dims[n] : mn;
+    }
+    p->tables_as_weights = (tot - mn) * 8 <= (int64_t)kDrawTableBytes;
+  }
   p->seed = d->seed;
   p->stream_id = d->stream_id;
   p->prec = d->precision;
@@ -107,7 +119,7 @@ void plan(const Problem& p, Layout* L) {
   }
   L->idx = take((size_t)p.J * (p.N - 1) * 4);
   L->w = take((size_t)p.J * 8);
-  L->A = take((size_t)p.J * p.Pmax * p.sk_sz);
+  L->A = take((size_t)(p.J + kSketchPadRows) * p.Pmax * p.sk_sz);
   L->Hpart = take(hpart * 8);  // FP64 split-K partials
   L->Bpart = take(bpart * 8);
   L->Bred = take((size_t)p.Pmax * p.Imax * 8);
@@ -119,7 +131,7 @@ void plan(const Problem& p, Layout* L) {
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
-  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [32] u32 counter
+  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status
   L->total = off;
 }
 
@@ -151,7 +163,6 @@ struct trals_ctx {
   int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
   double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
   unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
-  unsigned* counter() { return reinterpret_cast<unsigned*>(ws + L.scal + 32); }
 };
 
 #define HIPTRY(expr)                      \
@@ -221,13 +232,12 @@ int compute_table(trals_ctx* h, int m) {
     ta.Wlev = F2;
     ta.Blev = core;
     ta.Q = Q;
-    ta.counter = h->counter();
     ta.status = h->status();
     HIPTRY(launch_trisolve(ta, h->stream));
   } else {
     HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
-    HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
   }
+  if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
   PROF_END(TRALS_K_TABLE);
   h->table_valid[m] = true;
   return TRALS_OK;
@@ -261,6 +271,7 @@ int run_update(trals_ctx* h) {
   da.w = h->at<double>(h->L.w);
   da.A = h->at<void>(h->L.A);
   da.status = h->status();
+  da.weights = p.tables_as_weights ? 1 : 0;
   PROF_BEGIN(TRALS_K_DRAW);
   HIPTRY(launch_draw(da, p.sk_dt, h->stream));
   PROF_END(TRALS_K_DRAW);
@@ -316,7 +327,6 @@ int run_update(trals_ctx* h) {
   ta.Wsol = F;
   ta.Bsol = Bred;
   ta.core = h->at<double>(h->L.core[n]);
-  ta.counter = h->counter();
   ta.status = h->status();
   PROF_BEGIN(TRALS_K_SOLVE);
   HIPTRY(launch_trisolve(ta, h->stream));
@@ -401,6 +411,8 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
   h->stream = (hipStream_t)stream;
   rc = [&]() -> int {
     HIPTRY(hipMemsetAsync(h->ws + L.scal, 0, 64, h->stream));
+    // sketch rows are read past row J (finite values needed there)
+    HIPTRY(hipMemsetAsync(h->ws + L.A, 0, (size_t)(p.J + kSketchPadRows) * p.Pmax * p.sk_sz, h->stream));
     // norm and finiteness of X
     HIPTRY(launch_scan_x(X_dev, x_dtype, p.E, h->at<double>(L.partial), kScanBlocks, h->nonfinite(), h->stream));
     HIPTRY(launch_sum_partials(h->at<double>(L.partial), kScanBlocks, h->scal_d(), h->stream));

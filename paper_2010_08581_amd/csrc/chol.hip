@@ -320,35 +320,12 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
 // Right-hand sides in row form (row i = b_i, P doubles).  Workgroups [0, solve_groups) solve
 // 16 rows each: z_i = W^T (W b_i), written as row i of the core (slice-major, FP64).
 // Workgroups [solve_groups, +lev_groups) take 16 rows each of a core unfolding G_(2) and
-// write Q_i = floor(||W g_i||^2 / P * 2^52); the last of them to finish turns Q into the
-// inclusive table C in place.  Each wave takes the 16-row blocks K = wave, wave + 4, ...
-__device__ void block_scan_u64(uint64_t* Q, int n) {
-  __shared__ uint64_t part[256];
-  const int t = threadIdx.x;
-  const int per = (n + 255) / 256;
-  const int b0 = t * per, b1 = b0 + per < n ? b0 + per : n;
-  uint64_t s = 0;
-  for (int i = b0; i < b1; ++i) s += Q[i];
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint64_t v = t >= o ? part[t - o] : 0ull;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint64_t run = t > 0 ? part[t - 1] : 0ull;
-  for (int i = b0; i < b1; ++i) {
-    run += Q[i];
-    Q[i] = run;
-  }
-}
-
+// write the table weights Q_i = floor(||W g_i||^2 / P * 2^52).  Each wave takes the 16-row
+// blocks K = wave, wave + 4, ...
 template <bool kWInLds, int T>
 __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   extern __shared__ double lds[];
   __shared__ double s_red[4][16];
-  __shared__ int s_last;
   if (*a.status != kDevOk) return;
   constexpr int kLdB = 17;
   const int P = a.P;
@@ -365,28 +342,42 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
   double* Ws = lds + nblk * 16 * kLdB;
   {
-    // right-hand sides, transposed into Bs (batched loads: one round trip per 8 per thread)
+    // right-hand sides (transposed into Bs) and, when staged, W: all loads of a round are
+    // issued before any store, so that the staging costs one memory round trip when it fits
+    // in one round (16 x 16 nblk <= 8 x 256 elements, W <= 16 x 256 double2)
     const int cnt = 16 * nblk * 16;
-    constexpr int kB = 8;
-    for (int base = 0; base < cnt; base += kB * 256) {
+    const int64_t wcnt = kWInLds ? (int64_t)nslots * kBlk / 2 : 0;
+    constexpr int kB = 8, kBW = 16;
+    for (int64_t base = 0, wbase = 0; base < cnt || wbase < wcnt; base += kB * 256, wbase += kBW * 256) {
       double v[kB];
+      double2 wv[kBW];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + 256 * q;
+        const int e = (int)base + (int)threadIdx.x + 256 * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         const bool ok = e < cnt && i0 + j < In && p < P;
         v[q] = ok ? Bsrc[(int64_t)(i0 + j) * P + p] : 0.0;
       }
+      if (kWInLds)
+#pragma unroll
+        for (int q = 0; q < kBW; ++q) {
+          const int64_t e = wbase + threadIdx.x + 256 * q;
+          wv[q] = ((const double2*)Wg)[e < wcnt ? e : wcnt - 1];
+        }
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + 256 * q;
+        const int e = (int)base + (int)threadIdx.x + 256 * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         if (e < cnt) Bs[p * kLdB + j] = v[q];
       }
+      if (kWInLds)
+#pragma unroll
+        for (int q = 0; q < kBW; ++q) {
+          const int64_t e = wbase + threadIdx.x + 256 * q;
+          if (e < wcnt) ((double2*)Ws)[e] = wv[q];
+        }
     }
   }
-  if (kWInLds)
-    copy_batched<8>((double2*)Ws, (const double2*)Wg, (int64_t)nslots * kBlk / 2, threadIdx.x, 256);
   __syncthreads();
   const double* W = kWInLds ? Ws : Wg;
   // Y_K = sum_{J <= K} W_KJ B_J
@@ -420,15 +411,6 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
       const int j = threadIdx.x;
       const double lv = ((s_red[0][j] + s_red[1][j]) + s_red[2][j]) + s_red[3][j];
       a.Q[i0 + j] = (uint64_t)floor(lv / (double)P * 4503599627370496.0);  // 2^52
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(a.counter, 1u) == (unsigned)(a.lev_groups - 1);
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      block_scan_u64(a.Q, In);
-      if (threadIdx.x == 0) *a.counter = 0u;
     }
     return;
   }

@@ -1,6 +1,10 @@
 // Sampler and sketch of one core update, fused (Algorithm 3 draws, Definition 5 rescaling,
 // Algorithm 4 / eq. (5) subchain rows).
 //
+// Tables.  The device tables hold either the integer weights Q_i (then every workgroup forms
+// the inclusive sums C in LDS while staging them) or the sums C themselves (problems whose
+// tables exceed the LDS budget; searched in global memory).
+//
 // Draws.  Sample j, mode draw k (mode m = (n+1+k) mod N) takes 64-bit word (k mod 4) of the
 // Philox4x64-10 block with key (seed, stream_id) and counter (j, k/4, u, 0), u the update
 // number.  With the mode's inclusive integer table C (total T = C[I-1]) the draw is
@@ -26,10 +30,35 @@ namespace trals {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr size_t kDrawTableBytes = 48 * 1024;  // staged sampling tables per workgroup
+
+// inclusive prefix sums of t[0, n) in place (kThreads threads: contiguous chunks per thread,
+// a shuffle scan of the chunk sums per wave, then the wave totals)
+__device__ void lds_scan_u64(uint64_t* t, int n, uint64_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = (n + kThreads - 1) / kThreads;
+  const int b0 = tid * c < n ? tid * c : n, b1 = b0 + c < n ? b0 + c : n;
+  uint64_t s = 0;
+  for (int i = b0; i < b1; ++i) s += t[i];
+  uint64_t x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint64_t pre = x - s;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  for (int i = b0; i < b1; ++i) {
+    pre += t[i];
+    t[i] = pre;
+  }
+  __syncthreads();
+}
 
 template <typename TA, int RM>
 __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
+  __shared__ uint64_t s_wsum[kThreads / 64];
   extern __shared__ double lds[];
   if (*a.status != kDevOk) return;
   const int N = a.ring.N;
@@ -58,6 +87,12 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       o += I;
     }
     __syncthreads();
+    if (a.weights)
+      for (int k = 0; k < K; ++k) {
+        int m = n + 1 + k;
+        if (m >= N) m -= N;
+        lds_scan_u64(tab + off[k], a.ring.dims[m], s_wsum);
+      }
   }
   if (tid < jb) {
     const int64_t j = j0 + tid;
@@ -194,6 +229,7 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   size_t tbytes = 0;
   for (int k = 0; k < K; ++k) tbytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
   a.tables_in_lds = tbytes <= kDrawTableBytes;
+  if (a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
   const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2) * sizeof(double);
   const size_t lds = head + (a.tables_in_lds ? tbytes : 0);
   const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);

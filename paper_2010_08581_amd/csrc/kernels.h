@@ -36,9 +36,11 @@ struct DrawArgs {
   double* w;
   void* A;                      // sketch type: FP64 (0) or FP32 (1)
   const int* status;
+  int weights;                  // 1: cdf holds the weights Q (scanned in LDS); 0: inclusive sums C
   int jb;                       // samples per workgroup (set by launch_draw)
   int tables_in_lds;            // set by launch_draw
 };
+constexpr size_t kDrawTableBytes = 48 * 1024;  // sampling tables staged per draw workgroup
 hipError_t launch_draw(const DrawArgs& a, int sketch_dtype, hipStream_t s);
 
 // Fused normal equations [H | B] = A^T [A | X~] on matrix cores (split-K partials).
@@ -65,6 +67,9 @@ struct NormalEqPlan {
   int64_t chunk;
 };
 constexpr int kPlanCUs = 256;  // MI355X compute units (launch sizing)
+// rows of finite padding the sketch buffer keeps past row J (the contraction reads up to one
+// split quantum past the end of a chunk without bounds checks)
+constexpr int kSketchPadRows = 64;
 // ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel (FP32 matrix
 // cores per 32-row stage, FP64 accumulation); 2: BF16 form (FP32 sketch, BF16 panel, BF16
 // matrix cores with FP32 accumulation).
@@ -93,9 +98,8 @@ size_t chol_factor_doubles(int P);
 hipError_t launch_chol(const CholArgs& a, hipStream_t s);
 
 // With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
-// leverage rows Q_i = floor(||W g_i||^2 / P * 2^52) of Blev (In_lev x P, a core unfolding)
-// turned into the inclusive table in place.  Either part is skipped when its W is NULL.
-// counter: a device word that is zero between launches.
+// table weights Q_i = floor(||W g_i||^2 / P * 2^52) of the rows of Blev (In_lev x P, a core
+// unfolding).  Either part is skipped when its W is NULL.
 struct TriArgs {
   int P, In_sol, In_lev;
   const double* Wsol;
@@ -104,7 +108,6 @@ struct TriArgs {
   const double* Blev;
   double* core;
   uint64_t* Q;
-  unsigned* counter;
   int solve_groups, lev_groups;  // set by launch_trisolve
   const int* status;
 };

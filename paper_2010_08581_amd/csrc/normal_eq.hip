@@ -58,7 +58,6 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   if (gram && col0 >= row0 + RT) return;  // strictly upper Gram tile
   const int64_t r0 = (int64_t)s * a.chunk;
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
-  const int64_t rlast = r1 - 1;
   const int nrows = (int)(r1 - r0);
   const int stages = (nrows + kKB - 1) / kKB;
   const int rounds = (stages + KG - 1) / KG;
@@ -86,31 +85,23 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
     }
   }
   __syncthreads();
-  // Loads are unguarded: rows past the chunk are clamped to its last row (their row factor is
-  // 0), columns past P or I_n to the last column (those outputs are not stored).
+  // Loads are unguarded: rows past the chunk read the following rows of the sketch buffer,
+  // which holds kSketchPadRows finite rows past row J (their row factor is 0); columns past P
+  // or I_n are clamped to the last column (those outputs are not stored).
   Real ra[NA], rb[NB];
+  const int gcb = gram ? (col0 + lane < P ? col0 + lane : P - 1) : (col0 + lane < In ? col0 + lane : In - 1);
   auto load_stage = [&](int base) {
+    const Real* Ab = A + (r0 + base) * P;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tl + 256 * q;
       const int r = e / RT, c = e - r * RT;
-      int64_t gr = r0 + base + r;
-      gr = gr < rlast ? gr : rlast;
-      const int gc = row0 + c < P ? row0 + c : P - 1;
-      ra[q] = A[gr * P + gc];
+      ra[q] = Ab[r * P + (row0 + c < P ? row0 + c : P - 1)];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int r = wave + 4 * q;
-      if (gram) {
-        int64_t gr = r0 + base + r;
-        gr = gr < rlast ? gr : rlast;
-        const int gc = col0 + lane < P ? col0 + lane : P - 1;
-        rb[q] = A[gr * P + gc];
-      } else {
-        const int gc = col0 + lane < In ? col0 + lane : In - 1;
-        rb[q] = X[s_roff[base + r] + gc];
-      }
+      rb[q] = gram ? Ab[r * P + gcb] : X[s_roff[base + r] + gcb];
     }
   };
   auto store_stage = [&](int buf) {
@@ -129,26 +120,42 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
 #pragma unroll
   for (int m = 0; m < MB; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
   const int r16 = lane & 15, k4 = lane >> 4;
-  load_stage(g * kKB);
-  for (int u = 0; u < rounds; ++u) {
-    const int buf = u & 1;
-    const int base = (u * KG + g) * kKB;
-    store_stage(buf);
-    __syncthreads();
-    if (u + 1 < rounds) load_stage(base + KG * kKB);
-    const Real* as = As + buf * kStageA;
-    const Real* bs = Bs + buf * kStageB;
-    double wv[kKB / 4];
+  // Pipeline: round u computes on LDS buffer u & 1; between its first and second half of
+  // k-steps every wave stores the (already loaded) stage of round u + 1 into the other buffer
+  // and issues the loads of round u + 2, so those memory operations overlap the matrix-core
+  // work of the other wave on the SIMD instead of running between barriers.  The other
+  // buffer was last read in round u - 1, which every wave finished before round u's barrier.
+  auto mfma_steps = [&](const Real* as, const Real* bs, const double* wv, int ks0) {
 #pragma unroll
-    for (int ks = 0; ks < kKB / 4; ++ks) wv[ks] = s_w[base + ks * 4 + k4];
-#pragma unroll
-    for (int ks = 0; ks < kKB / 4; ++ks) {
+    for (int kq = 0; kq < kKB / 8; ++kq) {
+      const int ks = ks0 + kq;
       const int kr = ks * 4 + k4;
       const double b = (double)bs[kr * LB + wave * 16 + r16] * wv[ks];
 #pragma unroll
       for (int m = 0; m < MB; ++m)
         acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)as[kr * LA + m * 16 + r16], b, acc[m], 0, 0, 0);
     }
+  };
+  load_stage(g * kKB);
+  store_stage(0);
+  if (rounds > 1) load_stage((KG + g) * kKB);
+  for (int u = 0; u < rounds; ++u) {
+    const int buf = u & 1;
+    const int base = (u * KG + g) * kKB;
+    __syncthreads();
+    const Real* as = As + buf * kStageA;
+    const Real* bs = Bs + buf * kStageB;
+    double wv[kKB / 4];
+#pragma unroll
+    for (int ks = 0; ks < kKB / 4; ++ks) wv[ks] = s_w[base + ks * 4 + k4];
+    mfma_steps(as, bs, wv, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (u + 1 < rounds) {
+      store_stage(buf ^ 1);
+      if (u + 2 < rounds) load_stage(base + 2 * KG * kKB);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_steps(as, bs, wv, kKB / 8);
   }
   if constexpr (KG > 1) {
     // fixed-order sum of the groups' accumulators (group 0 + group 1 + ...)
