@@ -33,13 +33,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+CONTRACT_SOURCES = ("common.h", "normal_eq.hip")  # the contraction kernel's own sources
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_2010_08581_amd", "csrc"))):
-        if fn.endswith((".hip", ".h")):
-            with open(os.path.join(ROOT, "paper_2010_08581_amd", "csrc", fn), "rb") as f:
-                h.update(fn.encode())
-                h.update(f.read())
+    for fn in CONTRACT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_08581_amd", "csrc", fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -53,7 +55,7 @@ def measured_traffic(workload):
         rec = json.load(f)
     if rec.get("source_sha") != kernel_source_sha() or rec.get("workload") != workload:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch")  # {"fetch", "write", "total"} in bytes
 
 
 def cpu_baseline(X, init, cfg, budget_s):
@@ -168,7 +170,9 @@ def main():
     achieved = flops / avg_s / 1e12
     traffic = measured_traffic(cfg["name"])
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": traffic,
+                "frac": achieved / peak, "traffic": traffic["total"] if traffic else None,
+                "traffic_fetch_write": [traffic["fetch"], traffic["write"]] if traffic else None,
+                "algorithmic_bytes": gbytes,
                 "kernel": "k_normal_eq (fiber gather + [A^T A | A^T X~] on matrix cores)",
                 "gather_GBps": gbytes / avg_s / 1e9,
                 "gather_hbm_frac": gbytes / avg_s / 1e9 / PEAK_HBM_GBS}

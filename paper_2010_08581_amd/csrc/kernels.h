@@ -74,7 +74,9 @@ constexpr int kSketchPadRows = 64;
 // cores per 32-row stage, FP64 accumulation); 2: BF16 form (FP32 sketch, BF16 panel, BF16
 // matrix cores with FP32 accumulation).
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
-hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s);
+// e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
+hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:
 // symmetrise a P x P matrix from its lower triangle; mode 2: transpose P x (count / P) to
 // (count / P) x P.

@@ -19,6 +19,8 @@
 // cond(A) that FP32 storage of A and X costs.
 //   v_mfma_f64_16x16x4 layouts: A(i, k) lane i + 16 k; B(k, j) lane j + 16 k;
 //     D(i, j) lane j + 16 (i % 4), register i / 4.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace trals {
@@ -364,12 +366,18 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__
   }
 }
 
+// e0/e1 (optional): events the runtime stamps at the kernel's own start and end
 template <typename Real, int KG>
-hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s) {
+hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const size_t lds = ne_dyn_lds(mb, KG, sizeof(Real));
   switch (mb) {
-#define TRALS_NE_CASE(MB) \
-  case MB: k_normal_eq<Real, MB, KG><<<grid, 256 * KG, lds, s>>>(a); break;
+#define TRALS_NE_CASE(MB)                                                                              \
+  case MB:                                                                                             \
+    if (e0)                                                                                            \
+      hipExtLaunchKernelGGL((k_normal_eq<Real, MB, KG>), dim3(grid), dim3(256 * KG), lds, s, e0, e1, 0, a); \
+    else                                                                                               \
+      k_normal_eq<Real, MB, KG><<<grid, 256 * KG, lds, s>>>(a);                                          \
+    break;
     TRALS_NE_CASE(1)
     TRALS_NE_CASE(2)
     TRALS_NE_CASE(3)
@@ -435,19 +443,25 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   return pl;
 }
 
-hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, int ne_dtype, hipStream_t s) {
+hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,
+                            hipEvent_t e0, hipEvent_t e1) {
   NormalEqArgs a = args;
   a.col_tiles = pl.gram_tiles + pl.data_tiles;
   a.tiles = pl.row_tiles * a.col_tiles;
   a.splits = pl.splits;
   if ((int64_t)pl.splits * a.tiles > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(pl.splits * a.tiles);
-  if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s);
-  if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s);
+  if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s, e0, e1);
+  if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 2) {
     switch (pl.mb) {
-#define TRALS_NE16_CASE(MB) \
-  case MB: k_normal_eq_bf16<MB><<<grid, 256, 0, s>>>(a); break;
+#define TRALS_NE16_CASE(MB)                                                                  \
+  case MB:                                                                                   \
+    if (e0)                                                                                  \
+      hipExtLaunchKernelGGL((k_normal_eq_bf16<MB>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a); \
+    else                                                                                     \
+      k_normal_eq_bf16<MB><<<grid, 256, 0, s>>>(a);                                          \
+    break;
       TRALS_NE16_CASE(1)
       TRALS_NE16_CASE(2)
       TRALS_NE16_CASE(3)
