@@ -79,6 +79,21 @@ typedef struct {
   int32_t init_dtype;      /* TRALS_F64 or TRALS_F32 */
 } trals_desc;
 
+/* Generated data source (serving): the tensor is X = TR(G*) + sigma Z with given "true" cores
+ * G* and iid N(0,1) noise Z, and is never materialised; every update computes only its J
+ * sampled fibers (Algorithm 2, "sample X") from G* and the noise generator.  Z at C-order linear
+ * index e is the Box-Muller transform of the Philox4x64-10 block with key (noise_seed,
+ * noise_stream) and counter (e, ~0, ~0, 0): z = sqrt(-2 ln u1) cos(2 pi u2), u1 =
+ * (w0 >> 11 + 1) 2^-53, u2 = (w1 >> 11) 2^-53.  sigma = noise_rel ||TR(G*)||_F / sqrt(prod I),
+ * the norm taken by transfer matrices. */
+typedef struct {
+  const void* true_cores;   /* device: the N cores of G*, layout as trals_desc.init_cores */
+  int32_t true_dtype;       /* TRALS_F64 or TRALS_F32 */
+  const int32_t* true_ranks;/* host array of N ranks of G*; NULL = the decomposition's ranks */
+  double noise_rel;         /* >= 0 */
+  uint64_t noise_seed, noise_stream;
+} trals_source;
+
 /* Bytes of device workspace trals_create needs for this description.
  * Pure host computation.  Returns TRALS_EINVAL for an invalid description. */
 int trals_workspace_bytes(const trals_desc* desc, size_t* bytes);
@@ -92,6 +107,13 @@ int trals_workspace_bytes(const trals_desc* desc, size_t* bytes);
  * trals_workspace_bytes(desc). */
 int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, void* ws_dev,
                  size_t ws_bytes, void* stream, trals_handle* out);
+
+/* As trals_workspace_bytes / trals_create, for a generated data source (no X, no panels).
+ * trals_fit_error of such a handle returns ||TR(G) - TR(G*)||_F / ||TR(G*)||_F (the error
+ * against the noise-free tensor, by transfer matrices). */
+int trals_workspace_bytes_generated(const trals_desc* desc, const trals_source* src, size_t* bytes);
+int trals_create_generated(const trals_desc* desc, const trals_source* src, void* ws_dev, size_t ws_bytes,
+                           void* stream, trals_handle* out);
 
 /* Run n_sweeps outer iterations of Algorithm 2 (each updates cores 0..N-1 in
  * order), continuing from the handle's update counter. */

@@ -32,9 +32,12 @@ class TRALS:
     """
 
     def __init__(self, X, ranks, samples, seed=0, stream_id=0, precision="f32", init_cores=None,
-                 stream=None):
+                 stream=None, source=None):
         torch = _torch()
         self.lib = _lib.load()
+        if source is not None:
+            self._init_generated(source, ranks, samples, seed, stream_id, precision, init_cores, stream)
+            return
         if not X.is_cuda:
             raise ValueError("X must be a CUDA tensor")
         X = X.contiguous()
@@ -60,6 +63,53 @@ class TRALS:
         _lib.check(self.lib.trals_create(C.byref(desc), C.c_void_p(X.data_ptr()), xdt,
                                          C.c_void_p(self.workspace.data_ptr()), nbytes,
                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)), "trals_create")
+        self.h = h
+        self.core_shapes = [(self.ranks[(n - 1) % self.N], self.dims[n], self.ranks[n]) for n in range(self.N)]
+
+    @classmethod
+    def generated(cls, true_cores, ranks, samples, noise_rel=0.0, noise_seed=0, noise_stream=0,
+                  seed=0, stream_id=0, precision="f32", init_cores=None, stream=None, device=None):
+        """Handle whose data is TR(true_cores) + noise, generated fiber by fiber on the GPU
+        (never materialised).  true_cores: list of N arrays/tensors (R[n-1], I[n], R[n])."""
+        src = dict(true_cores=true_cores, noise_rel=noise_rel, noise_seed=noise_seed,
+                   noise_stream=noise_stream, device=device)
+        return cls(None, ranks, samples, seed=seed, stream_id=stream_id, precision=precision,
+                   init_cores=init_cores, stream=stream, source=src)
+
+    def _init_generated(self, source, ranks, samples, seed, stream_id, precision, init_cores, stream):
+        torch = _torch()
+        tc = source["true_cores"]
+        dev = source.get("device") or (tc[0].device if isinstance(tc[0], torch.Tensor) and tc[0].is_cuda
+                                        else torch.device("cuda", torch.cuda.current_device()))
+        self.dims = tuple(int(c.shape[1]) for c in tc)
+        self.ranks = tuple(int(v) for v in ranks)
+        self.N = len(self.dims)
+        self.J = int(samples)
+        self.precision = precision
+        self.device = dev
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        self._true_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+                                    .to(device=dev, dtype=torch.float64).reshape(-1) for c in tc])
+        true_ranks = [int(c.shape[2]) for c in tc]
+        init_ptr, init_buf = None, None
+        if init_cores is not None:
+            init_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+                                  .to(device=dev, dtype=torch.float64).reshape(-1) for c in init_cores])
+            init_ptr = init_buf.data_ptr()
+        desc, keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
+                                    init_ptr, TRALS_F64)
+        src, keep2 = _lib.make_source(self._true_buf.data_ptr(), TRALS_F64, true_ranks, source["noise_rel"],
+                                      source["noise_seed"], source["noise_stream"])
+        self._keep = (keep, keep2, init_buf)
+        nbytes = C.c_size_t(0)
+        _lib.check(self.lib.trals_workspace_bytes_generated(C.byref(desc), C.byref(src), C.byref(nbytes)),
+                   "trals_workspace_bytes_generated")
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        h = C.c_void_p(0)
+        _lib.check(self.lib.trals_create_generated(C.byref(desc), C.byref(src), C.c_void_p(self.workspace.data_ptr()),
+                                                   nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                   "trals_create_generated")
         self.h = h
         self.core_shapes = [(self.ranks[(n - 1) % self.N], self.dims[n], self.ranks[n]) for n in range(self.N)]
 

@@ -19,7 +19,7 @@ EXPORTS = (
     "trals_workspace_bytes", "trals_create", "trals_sweep", "trals_step", "trals_fit_error",
     "trals_destroy", "trals_get_cores", "trals_set_cores", "trals_get_last_samples",
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
-    "trals_profile_read",
+    "trals_profile_read", "trals_workspace_bytes_generated", "trals_create_generated",
 )
 KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
@@ -35,6 +35,17 @@ class Desc(C.Structure):
         ("precision", C.c_int32),
         ("init_cores", C.c_void_p),
         ("init_dtype", C.c_int32),
+    ]
+
+
+class Source(C.Structure):
+    _fields_ = [
+        ("true_cores", C.c_void_p),
+        ("true_dtype", C.c_int32),
+        ("true_ranks", C.POINTER(C.c_int32)),
+        ("noise_rel", C.c_double),
+        ("noise_seed", C.c_uint64),
+        ("noise_stream", C.c_uint64),
     ]
 
 
@@ -71,6 +82,8 @@ def load(path: str = LIB_PATH):
         "trals_strerror": (C.c_char_p, [C.c_int]),
         "trals_profile": (C.c_int, [vp, i32]),
         "trals_profile_read": (C.c_int, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "trals_workspace_bytes_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), C.POINTER(C.c_size_t)]),
+        "trals_create_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), vp, C.c_size_t, vp, C.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -105,3 +118,13 @@ def workspace_bytes(dims, ranks, samples, precision=TRALS_F32):
     out = C.c_size_t(0)
     check(load().trals_workspace_bytes(C.byref(desc), C.byref(out)), "trals_workspace_bytes")
     return int(out.value)
+
+
+def make_source(true_ptr, true_dtype, true_ranks, noise_rel, noise_seed, noise_stream):
+    """Build a Source plus the host array it points to (keep the tuple alive)."""
+    r_arr = None
+    if true_ranks is not None:
+        r_arr = (C.c_int32 * len(true_ranks))(*[int(v) for v in true_ranks])
+    src = Source(C.c_void_p(true_ptr), int(true_dtype), r_arr, float(noise_rel), int(noise_seed),
+                 int(noise_stream))
+    return src, (r_arr,)

@@ -25,6 +25,10 @@ struct Layout {
   size_t core[kMaxOrder];
   size_t cdf[kMaxOrder];
   size_t fitx;
+  // generated source: true cores (FP64 slice-major), their subchain rows, the sampled fibers,
+  // and the transfer-matrix work area
+  size_t tcore[kMaxOrder];
+  size_t Tm, Xg, inner, inner_res;
   size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, partial, scal, total;
   int64_t partial_count;
 };
@@ -45,11 +49,28 @@ struct Problem {
   // n: device tables then hold the weights Q, summed in LDS by each draw; otherwise the
   // inclusive sums C, scanned on the device after every table computation
   bool tables_as_weights;
+  // generated source (X = TR(G*) + sigma Z, sampled fibers computed per update)
+  bool generated;
+  int32_t tranks[kMaxOrder];
+  int Ptmax;
+  double noise_rel;
+  uint64_t noise_seed, noise_stream;
 };
+
+Ring ring_of(const Problem& p, const int32_t* ranks) {
+  Ring g;
+  memset(&g, 0, sizeof(g));
+  g.N = p.N;
+  for (int n = 0; n < p.N; ++n) {
+    g.dims[n] = (int)p.dims[n];
+    g.ranks[n] = ranks[n];
+  }
+  return g;
+}
 
 int P_of(const Problem& p, int n) { return p.ranks[(n + p.N - 1) % p.N] * p.ranks[n]; }
 
-int validate(const trals_desc* d, Problem* p) {
+int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr) {
   if (!d || !d->dims || !d->ranks) return TRALS_EINVAL;
   if (d->order < 2 || d->order > kMaxOrder) return TRALS_EINVAL;
   if (d->precision != TRALS_F64 && d->precision != TRALS_F32 && d->precision != TRALS_BF16) return TRALS_EINVAL;
@@ -61,7 +82,8 @@ int validate(const trals_desc* d, Problem* p) {
     if (d->ranks[n] < 1 || d->ranks[n] > kMaxRank) return TRALS_EINVAL;
     p->dims[n] = d->dims[n];
     p->ranks[n] = d->ranks[n];
-    if (p->E > ((int64_t)1 << 40) / d->dims[n]) return TRALS_EINVAL;
+    // a materialised tensor is limited to 2^40 entries; a generated one to int64 linear indices
+    if (p->E > ((int64_t)1 << (src ? 62 : 40)) / d->dims[n]) return TRALS_EINVAL;
     p->E *= d->dims[n];
   }
   p->J = d->samples;
@@ -91,6 +113,24 @@ int validate(const trals_desc* d, Problem* p) {
   p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
   p->ne_dt = p->panel_dt;
   if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
+  if (src) {
+    if (!src->true_cores || (src->true_dtype != TRALS_F64 && src->true_dtype != TRALS_F32)) return TRALS_EINVAL;
+    if (!(src->noise_rel >= 0.0) || !isfinite(src->noise_rel)) return TRALS_EINVAL;
+    p->generated = true;
+    p->Ptmax = 0;
+    for (int n = 0; n < p->N; ++n) {
+      const int32_t r = src->true_ranks ? src->true_ranks[n] : d->ranks[n];
+      if (r < 1 || r > kMaxRank) return TRALS_EINVAL;
+      p->tranks[n] = r;
+    }
+    for (int n = 0; n < p->N; ++n) {
+      const int Pt = p->tranks[(n + p->N - 1) % p->N] * p->tranks[n];
+      p->Ptmax = Pt > p->Ptmax ? Pt : p->Ptmax;
+    }
+    p->noise_rel = src->noise_rel;
+    p->noise_seed = src->noise_seed;
+    p->noise_stream = src->noise_stream;
+  }
   return TRALS_OK;
 }
 
@@ -104,9 +144,24 @@ void plan(const Problem& p, Layout* L) {
     off = align_up(off + bytes);
     return o;
   };
-  for (int n = 0; n < p.N; ++n) L->panel[n] = take((size_t)p.E * p.panel_sz);
-  // the fit error reads X in C order: the last panel, or an FP32 copy in the BF16 form
-  L->fitx = p.panel_dt == 2 ? take((size_t)p.E * 4) : L->panel[p.N - 1];
+  if (!p.generated) {
+    for (int n = 0; n < p.N; ++n) L->panel[n] = take((size_t)p.E * p.panel_sz);
+    // the fit error reads X in C order: the last panel, or an FP32 copy in the BF16 form
+    L->fitx = p.panel_dt == 2 ? take((size_t)p.E * 4) : L->panel[p.N - 1];
+  } else {
+    for (int n = 0; n < p.N; ++n) {
+      const int Pt = p.tranks[(n + p.N - 1) % p.N] * p.tranks[n];
+      L->tcore[n] = take((size_t)p.dims[n] * Pt * 8);
+    }
+    L->Tm = take((size_t)p.J * p.Ptmax * 8);
+    L->Xg = take((size_t)p.J * p.Imax * p.panel_sz);
+    const Ring rr = ring_of(p, p.ranks), rt = ring_of(p, p.tranks);
+    size_t w = ring_inner_doubles(rr, rr);
+    w = ring_inner_doubles(rr, rt) > w ? ring_inner_doubles(rr, rt) : w;
+    w = ring_inner_doubles(rt, rt) > w ? ring_inner_doubles(rt, rt) : w;
+    L->inner = take((w + 4) * 8);  // work area, then 4 result doubles
+    L->inner_res = L->inner + w * 8;
+  }
   for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * 8);
   for (int n = 0; n < p.N; ++n) L->cdf[n] = take((size_t)p.dims[n] * 8);
   size_t hpart = 0, bpart = 0;
@@ -127,7 +182,7 @@ void plan(const Problem& p, Layout* L) {
   L->M2 = take((size_t)p.Pmax * p.Pmax * 8);  // Gram of a core for its leverage
   L->F = take(chol_factor_doubles(p.Pmax) * 8);
   L->F2 = take(chol_factor_doubles(p.Pmax) * 8);
-  const int64_t fit_rows = p.E / p.dims[p.N - 1];
+  const int64_t fit_rows = p.generated ? 0 : p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
@@ -155,7 +210,8 @@ struct trals_ctx {
   bool failed = false;
   bool table_valid[kMaxOrder] = {};
   bool have_last = false;
-  double xnorm2 = 0.0;
+  double xnorm2 = 0.0;   // ||X||_F^2, or ||TR(G*)||_F^2 for a generated source
+  double sigma = 0.0;    // noise level of a generated source
   hipError_t last_hip = hipSuccess;
 
   template <typename T>
@@ -212,16 +268,7 @@ hipError_t prof_pair(trals_ctx* h, int k, hipEvent_t* e0, hipEvent_t* e1) {
 #define PROF_BEGIN(k) HIPTRY(prof_mark(h, (k), 0))
 #define PROF_END(k) HIPTRY(prof_mark(h, (k), 1))
 
-Ring make_ring(const Problem& p) {
-  Ring g;
-  memset(&g, 0, sizeof(g));
-  g.N = p.N;
-  for (int n = 0; n < p.N; ++n) {
-    g.dims[n] = (int)p.dims[n];
-    g.ranks[n] = p.ranks[n];
-  }
-  return g;
-}
+Ring make_ring(const Problem& p) { return ring_of(p, p.ranks); }
 
 // Sampling table of core m from the core itself (creation, set_cores): eq. (3) via the Gram
 // of G_(2), its inverse factor and the leverage rows, scanned in place.
@@ -290,15 +337,49 @@ int run_update(trals_ctx* h) {
   da.A = h->at<void>(h->L.A);
   da.status = h->status();
   da.weights = p.tables_as_weights ? 1 : 0;
+  da.draw = 1;
   PROF_BEGIN(TRALS_K_DRAW);
   HIPTRY(launch_draw(da, p.sk_dt, h->stream));
+  if (p.generated) {
+    // the sampled fibers of X = TR(G*) + sigma Z: true-core subchain rows for the same
+    // indices, then the fibers themselves
+    DrawArgs dt = da;
+    dt.ring = ring_of(p, p.tranks);
+    for (int m = 0; m < N; ++m) dt.cores.p[m] = h->at<const double>(h->L.tcore[m]);
+    dt.draw = 0;
+    dt.A = h->at<void>(h->L.Tm);
+    HIPTRY(launch_draw(dt, 0, h->stream));
+    FiberArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.J = p.J;
+    fa.P = p.tranks[(n + N - 1) % N] * p.tranks[n];
+    fa.In = In;
+    fa.K = N - 1;
+    fa.T = h->at<const double>(h->L.Tm);
+    fa.idx = da.idx;
+    auto cstride = [&](int m) {
+      int64_t st = 1;
+      for (int m2 = m + 1; m2 < N; ++m2) st *= p.dims[m2];
+      return st;
+    };
+    for (int k = 0; k < N - 1; ++k) fa.lin_stride[k] = cstride((n + 1 + k) % N);
+    fa.lin_stride_n = cstride(n);
+    fa.true_core = h->at<const double>(h->L.tcore[n]);
+    fa.sigma = h->sigma;
+    fa.noise_seed = p.noise_seed;
+    fa.noise_stream = p.noise_stream;
+    fa.out = h->at<void>(h->L.Xg);
+    fa.status = h->status();
+    HIPTRY(launch_fibers(fa, p.panel_dt, h->stream));
+  }
   PROF_END(TRALS_K_DRAW);
 
   const NormalEqPlan pl = plan_normal_eq(P, In, p.J, p.ne_dt, kPlanCUs);
   NormalEqArgs na;
   memset(&na, 0, sizeof(na));
   na.A = da.A;
-  na.panel = h->at<const void>(h->L.panel[n]);
+  na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
+  na.direct = p.generated ? 1 : 0;
   na.idx = da.idx;
   na.w = da.w;
   // panel rows are the other modes in C order: stride of mode m = prod_{m' > m, m' != n} I_m'
@@ -370,6 +451,27 @@ int sync_status(trals_ctx* h) {
     return TRALS_ESINGULAR;
   }
   return TRALS_OK;
+}
+
+int load_cores(trals_ctx* h, const void* src, int dtype);
+
+// initial cores (given, or N(0,1) from the seed) and the sampling tables of cores 1..N-1
+int init_cores_and_tables(trals_ctx* h, const trals_desc* desc) {
+  const Problem& p = h->p;
+  if (desc->init_cores) {
+    const int r2 = load_cores(h, desc->init_cores, desc->init_dtype);
+    if (r2) return r2;
+  } else {
+    for (int n = 0; n < p.N; ++n) {
+      const int64_t cnt = (int64_t)p.dims[n] * P_of(p, n);
+      HIPTRY(launch_core_normal(h->at<void>(h->L.core[n]), 0, cnt, p.seed, p.stream_id, n, h->stream));
+    }
+  }
+  for (int m = 1; m < p.N; ++m) {
+    const int r3 = compute_table(h, m);
+    if (r3) return r3;
+  }
+  return sync_status(h);
 }
 
 int load_cores(trals_ctx* h, const void* src, int dtype) {
@@ -456,20 +558,72 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
     if (p.panel_dt == 2)
       HIPTRY(launch_panel(X_dev, x_dtype, h->at<void>(L.fitx), 1, p.E / p.dims[p.N - 1], p.dims[p.N - 1], 1,
                           h->stream));
-    if (desc->init_cores) {
-      const int r2 = load_cores(h, desc->init_cores, desc->init_dtype);
-      if (r2) return r2;
-    } else {
-      for (int n = 0; n < p.N; ++n) {
-        const int64_t cnt = (int64_t)p.dims[n] * P_of(p, n);
-        HIPTRY(launch_core_normal(h->at<void>(L.core[n]), 0, cnt, p.seed, p.stream_id, n, h->stream));
-      }
+    return init_cores_and_tables(h, desc);
+  }();
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return TRALS_OK;
+}
+
+int trals_workspace_bytes_generated(const trals_desc* desc, const trals_source* src, size_t* bytes) {
+  if (!bytes || !src) return TRALS_EINVAL;
+  Problem p;
+  const int rc = validate(desc, &p, src);
+  if (rc) return rc;
+  Layout L;
+  plan(p, &L);
+  *bytes = L.total;
+  return TRALS_OK;
+}
+
+int trals_create_generated(const trals_desc* desc, const trals_source* src, void* ws_dev, size_t ws_bytes,
+                           void* stream, trals_handle* out) {
+  if (!out || !src) return TRALS_EINVAL;
+  *out = nullptr;
+  Problem p;
+  int rc = validate(desc, &p, src);
+  if (rc) return rc;
+  if (!ws_dev || ((uintptr_t)ws_dev) % kAlign) return TRALS_EINVAL;
+  Layout L;
+  plan(p, &L);
+  if (ws_bytes < L.total) return TRALS_EINVAL;
+  trals_ctx* h = new (std::nothrow) trals_ctx();
+  if (!h) return TRALS_ENOMEM;
+  h->p = p;
+  h->L = L;
+  h->ws = (char*)ws_dev;
+  h->stream = (hipStream_t)stream;
+  rc = [&]() -> int {
+    HIPTRY(hipMemsetAsync(h->ws + L.scal, 0, 64, h->stream));
+    HIPTRY(hipMemsetAsync(h->ws + L.A, 0, (size_t)(p.J + kSketchPadRows) * p.Pmax * p.sk_sz, h->stream));
+    // true cores into slice-major FP64
+    const size_t esz = src->true_dtype == TRALS_F64 ? 8 : 4;
+    size_t off = 0;
+    for (int n = 0; n < p.N; ++n) {
+      const int Rp = p.tranks[(n + p.N - 1) % p.N], Rn = p.tranks[n];
+      const int I = (int)p.dims[n];
+      HIPTRY(launch_core_import((const char*)src->true_cores + off, src->true_dtype == TRALS_F64 ? 0 : 1,
+                                h->at<void>(L.tcore[n]), 0, Rp, I, Rn, h->stream));
+      off += (size_t)Rp * I * Rn * esz;
     }
-    for (int m = 1; m < p.N; ++m) {
-      const int r3 = compute_table(h, m);
-      if (r3) return r3;
-    }
-    return sync_status(h);
+    // ||TR(G*)||_F^2 by transfer matrices; noise sigma = noise_rel ||TR(G*)||_F / sqrt(prod I)
+    const Ring rt = ring_of(p, p.tranks);
+    PerMode<const double> T;
+    for (int n = 0; n < p.N; ++n) T.p[n] = h->at<const double>(L.tcore[n]);
+    double* res = h->at<double>(L.inner_res);
+    HIPTRY(launch_ring_inner(rt, T, rt, T, h->at<double>(L.inner), res, h->stream));
+    double x2 = 0.0;
+    HIPTRY(hipMemcpyAsync(&x2, res, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if (!(x2 > 0.0) || !isfinite(x2)) return TRALS_EINVAL;
+    h->xnorm2 = x2;
+    double entries = 1.0;
+    for (int n = 0; n < p.N; ++n) entries *= (double)p.dims[n];
+    h->sigma = p.noise_rel * sqrt(x2 / entries);
+    return init_cores_and_tables(h, desc);
   }();
   if (rc) {
     delete h;
@@ -504,6 +658,25 @@ int trals_fit_error(trals_handle h, double* rel_err) {
   if (!h || !rel_err) return TRALS_EINVAL;
   if (h->failed) return TRALS_ESTATE;
   const Problem& p = h->p;
+  if (p.generated) {
+    // ||TR(G) - TR(G*)||^2 = <G,G> - 2 <G,G*> + <G*,G*> by transfer matrices (noise excluded)
+    const Ring rr = make_ring(p), rt = ring_of(p, p.tranks);
+    PerMode<const double> G, T;
+    for (int n = 0; n < p.N; ++n) {
+      G.p[n] = h->at<const double>(h->L.core[n]);
+      T.p[n] = h->at<const double>(h->L.tcore[n]);
+    }
+    double* work = h->at<double>(h->L.inner);
+    double* res = h->at<double>(h->L.inner_res);
+    HIPTRY(launch_ring_inner(rr, G, rr, G, work, res, h->stream));
+    HIPTRY(launch_ring_inner(rr, G, rt, T, work, res + 1, h->stream));
+    double r[2] = {0.0, 0.0};
+    HIPTRY(hipMemcpyAsync(r, res, 16, hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    const double d2 = r[0] - 2.0 * r[1] + h->xnorm2;
+    *rel_err = sqrt((d2 > 0.0 ? d2 : 0.0) / h->xnorm2);
+    return TRALS_OK;
+  }
   FitArgs fa;
   memset(&fa, 0, sizeof(fa));
   fa.ring = make_ring(p);

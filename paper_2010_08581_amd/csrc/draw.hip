@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
 
   // ---- draws ----
   int off[kMaxOrder];
-  if (a.tables_in_lds) {
+  if (a.draw && a.tables_in_lds) {
     int o = 0;
     for (int k = 0; k < K; ++k) {
       int m = n + 1 + k;
@@ -94,7 +94,12 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
         lds_scan_u64(tab + off[k], a.ring.dims[m], s_wsum);
       }
   }
-  if (tid < jb) {
+  if (tid < jb && !a.draw) {
+    // given samples (same rows, no rescaling)
+    const int64_t j = j0 + tid;
+    for (int k = 0; k < K; ++k) s_idx[tid * K + k] = j < a.J ? a.idx[j * K + k] : 0;
+    s_w[tid] = j < a.J ? 1.0 : 0.0;
+  } else if (tid < jb) {
     const int64_t j = j0 + tid;
     if (j < a.J) {
       uint64_t x[4] = {0, 0, 0, 0};
@@ -229,9 +234,9 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   size_t tbytes = 0;
   for (int k = 0; k < K; ++k) tbytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
   a.tables_in_lds = tbytes <= kDrawTableBytes;
-  if (a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
+  if (a.draw && a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
   const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2) * sizeof(double);
-  const size_t lds = head + (a.tables_in_lds ? tbytes : 0);
+  const size_t lds = head + (a.draw && a.tables_in_lds ? tbytes : 0);
   const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);
   switch (RM) {
     case 4: k_draw<TA, 4><<<blocks, kThreads, lds, s>>>(a); break;

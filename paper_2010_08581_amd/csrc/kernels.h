@@ -37,6 +37,7 @@ struct DrawArgs {
   void* A;                      // sketch type: FP64 (0) or FP32 (1)
   const int* status;
   int weights;                  // 1: cdf holds the weights Q (scanned in LDS); 0: inclusive sums C
+  int draw;                     // 1: draw the samples; 0: take idx as given, rows without weights
   int jb;                       // samples per workgroup (set by launch_draw)
   int tables_in_lds;            // set by launch_draw
 };
@@ -58,6 +59,7 @@ struct NormalEqArgs {
   int col_tiles, tiles, splits;  // filled in by launch_normal_eq
   double* Hpart;              // splits x P x P (lower triangle written)
   double* Bpart;              // splits x P x I_n
+  int direct;                 // 1: the fiber of sample j is row j of `panel` (I_n wide)
   const int* status;
 };
 struct NormalEqPlan {
@@ -114,6 +116,30 @@ struct TriArgs {
   const int* status;
 };
 hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
+
+// ---- generated data source and transfer-matrix inner products ----
+// Sampled fibers of X = TR(G*) + sigma Z: out[j][i] = sum_p G*_n[i][p] T[j][p] + sigma z(lin),
+// T[j] the true-core subchain product of sample j (column order of the sketch), lin the C-order
+// linear index of the entry (lin_stride[k] of the k-th sampled mode, lin_stride_n of mode n).
+struct FiberArgs {
+  int64_t J;
+  int P, In, K;
+  const double* T;
+  const int32_t* idx;
+  int64_t lin_stride[kMaxOrder];
+  int64_t lin_stride_n;
+  const double* true_core;    // slice-major I_n x P, FP64
+  double sigma;
+  uint64_t noise_seed, noise_stream;
+  void* out;                  // J x I_n, panel type
+  const int* status;
+};
+hipError_t launch_fibers(const FiberArgs& a, int out_dtype, hipStream_t s);
+// *out = <TR(A), TR(B)> for two rings with equal mode sizes (FP64 slice-major cores); work:
+// ring_inner_doubles(ra, rb) doubles.
+size_t ring_inner_doubles(const Ring& ra, const Ring& rb);
+hipError_t launch_ring_inner(const Ring& ra, PerMode<const double> A, const Ring& rb, PerMode<const double> B,
+                             double* work, double* out, hipStream_t s);
 
 // ---- leverage tables (eq. (3)) ----
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s);

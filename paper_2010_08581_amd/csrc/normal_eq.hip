@@ -79,8 +79,12 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
     } else {
       int64_t off = 0;
       if (v) {
-        const int32_t* ij = a.idx + (r0 + r) * a.K;
-        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+        if (a.direct) {
+          off = r0 + r;
+        } else {
+          const int32_t* ij = a.idx + (r0 + r) * a.K;
+          for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+        }
       }
       s_roff[r] = off * In;
       s_w[r] = v ? a.w[r0 + r] : 0.0;
@@ -237,9 +241,13 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (!gram) {
     for (int r = threadIdx.x; r < nrows; r += 256) {
-      const int32_t* ij = a.idx + (r0 + r) * a.K;
       int64_t off = 0;
-      for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      if (a.direct) {
+        off = r0 + r;
+      } else {
+        const int32_t* ij = a.idx + (r0 + r) * a.K;
+        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      }
       s_roff[r] = off * In;
       s_w[r] = (float)a.w[r0 + r];
     }

@@ -1,0 +1,174 @@
+// Generated data source and transfer-matrix inner products.
+//
+// Generated source.  The data tensor is X = TR(G*) + sigma Z: a tensor ring of given "true"
+// cores G* (eq. (1)) plus iid standard normal noise Z, never materialised.  The sampled fibers
+// of an update (Algorithm 2, "sample X") are computed where they are needed: with T_j the
+// product of the true cores' lateral slices for sample j's indices in the other modes (the
+// same chain Algorithm 4 forms from the current cores), entry i of fiber j is
+// trace(G*_n(:, i, :) T_j) = sum_p G*_n[i][p] T_j[p] in the column order shared by cores and
+// sketch rows.  Z at C-order linear index e is the Box-Muller transform of two Philox4x64-10
+// words, key (noise_seed, noise_stream), counter (e, ~0, ~0, 0).
+//
+// Transfer matrices.  For two rings A, B with cores of the same mode sizes,
+// <TR(A), TR(B)> = trace(E_0 E_1 ... E_{N-1}) with E_n = sum_i A_n(:, i, :) (x) B_n(:, i, :), a
+// (Ra_{n-1} Rb_{n-1}) x (Ra_n Rb_n) matrix (the Frobenius inner product of eq. (1) rings,
+// evaluated without forming either tensor).
+#include "kernels.h"
+
+namespace trals {
+
+namespace {
+
+__device__ __forceinline__ double philox_normal(uint64_t e, uint64_t k0, uint64_t k1) {
+  uint64_t x[4] = {e, ~0ull, ~0ull, 0ull};
+  philox4x64_10(x, k0, k1);
+  const double u1 = ((double)(x[0] >> 11) + 1.0) * 0x1.0p-53;  // (0, 1]
+  const double u2 = (double)(x[1] >> 11) * 0x1.0p-53;          // [0, 1)
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+template <typename Tout>
+__device__ __forceinline__ Tout cvt_out(double v);
+template <>
+__device__ __forceinline__ double cvt_out<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ float cvt_out<float>(double v) { return (float)v; }
+template <>
+__device__ __forceinline__ __bf16 cvt_out<__bf16>(double v) { return (__bf16)(float)v; }
+
+// one workgroup per 8 samples: their products T_j staged in LDS, one thread per (sample, i)
+constexpr int kFiberSamples = 8;
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
+  extern __shared__ double s_t[];  // kFiberSamples x P
+  __shared__ int64_t s_base[kFiberSamples];
+  if (*a.status != kDevOk) return;
+  const int P = a.P, In = a.In, K = a.K;
+  const int64_t j0 = (int64_t)blockIdx.x * kFiberSamples;
+  const int ns = a.J - j0 < kFiberSamples ? (int)(a.J - j0) : kFiberSamples;
+  for (int e = threadIdx.x; e < ns * P; e += 256) s_t[e] = a.T[j0 * P + e];
+  if (threadIdx.x < ns) {
+    const int32_t* ij = a.idx + (j0 + threadIdx.x) * K;
+    int64_t b = 0;
+    for (int k = 0; k < K; ++k) b += (int64_t)ij[k] * a.lin_stride[k];
+    s_base[threadIdx.x] = b;
+  }
+  __syncthreads();
+  const double* G = a.true_core;  // slice-major I_n x P
+  Tout* out = (Tout*)a.out;
+  for (int e = threadIdx.x; e < ns * In; e += 256) {
+    const int s = e / In, i = e - s * In;
+    const double* t = s_t + s * P;
+    const double* g = G + (int64_t)i * P;
+    double v = 0.0;
+    for (int p = 0; p < P; ++p) v = fma(g[p], t[p], v);
+    const int64_t lin = s_base[s] + (int64_t)i * a.lin_stride_n;
+    v += a.sigma * philox_normal((uint64_t)lin, a.noise_seed, a.noise_stream);
+    out[(j0 + s) * In + i] = cvt_out<Tout>(v);
+  }
+}
+
+// E[(a a') x (b b')] = sum_i A(a, i, b) B(a', i, b'); A, B slice-major (I, Ra0, Ra1), (I, Rb0, Rb1)
+__global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ A, const double* __restrict__ B, int I,
+                                                  int Ra0, int Ra1, int Rb0, int Rb1, double* __restrict__ E) {
+  const int rows = Ra0 * Rb0, cols = Ra1 * Rb1;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e - (int64_t)r * cols);
+  const int a = r / Rb0, a2 = r - a * Rb0, b = c / Rb1, b2 = c - b * Rb1;
+  const int pa = Ra0 * Ra1, pb = Rb0 * Rb1;
+  double s = 0.0;
+  for (int i = 0; i < I; ++i) s = fma(A[(int64_t)i * pa + a * Ra1 + b], B[(int64_t)i * pb + a2 * Rb1 + b2], s);
+  E[e] = s;
+}
+
+// C = A (m x k) B (k x n), row-major FP64, 16 x 16 tiles through LDS
+__global__ __launch_bounds__(256) void k_gemm(const double* __restrict__ A, const double* __restrict__ B, int m, int k,
+                                              int n, double* __restrict__ C) {
+  __shared__ double sa[16][17], sb[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    sa[ty][tx] = (row < m && k0 + tx < k) ? A[(int64_t)row * k + k0 + tx] : 0.0;
+    sb[ty][tx] = (k0 + ty < k && col < n) ? B[(int64_t)(k0 + ty) * n + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc = fma(sa[ty][q], sb[q][tx], acc);
+    __syncthreads();
+  }
+  if (row < m && col < n) C[(int64_t)row * n + col] = acc;
+}
+
+// out[0] = trace of the m x m matrix M (fixed-order reduction)
+__global__ __launch_bounds__(256) void k_trace(const double* __restrict__ M, int m, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) s += M[(int64_t)i * m + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace
+
+hipError_t launch_fibers(const FiberArgs& a, int out_dtype, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.J + kFiberSamples - 1) / kFiberSamples);
+  const size_t lds = (size_t)kFiberSamples * a.P * sizeof(double);
+  if (out_dtype == 0) k_fibers<double><<<blocks, 256, lds, s>>>(a);
+  else if (out_dtype == 1) k_fibers<float><<<blocks, 256, lds, s>>>(a);
+  else if (out_dtype == 2) k_fibers<__bf16><<<blocks, 256, lds, s>>>(a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+size_t ring_inner_doubles(const Ring& ra, const Ring& rb) {
+  // two chain buffers + one transfer matrix, each at most max_n (Ra Rb)^2
+  size_t m = 0;
+  for (int n = 0; n < ra.N; ++n) {
+    const size_t d = (size_t)ra.ranks[n] * rb.ranks[n];
+    m = d * d > m ? d * d : m;
+  }
+  return 3 * m + 8;
+}
+
+hipError_t launch_ring_inner(const Ring& ra, PerMode<const double> A, const Ring& rb, PerMode<const double> B,
+                             double* work, double* out, hipStream_t s) {
+  const int N = ra.N;
+  size_t m = 0;
+  for (int n = 0; n < N; ++n) {
+    const size_t d = (size_t)ra.ranks[n] * rb.ranks[n];
+    m = d * d > m ? d * d : m;
+  }
+  double* E = work;
+  double* C0 = work + m;
+  double* C1 = work + 2 * m;
+  double* cur = nullptr;
+  int cur_rows = 0, cur_cols = 0;
+  for (int n = 0; n < N; ++n) {
+    const int Ra0 = rank_before(ra, n), Ra1 = ra.ranks[n], Rb0 = rank_before(rb, n), Rb1 = rb.ranks[n];
+    const int rows = Ra0 * Rb0, cols = Ra1 * Rb1;
+    double* dst = n == 0 ? C0 : E;
+    const int64_t cnt = (int64_t)rows * cols;
+    k_transfer<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(A.p[n], B.p[n], ra.dims[n], Ra0, Ra1, Rb0, Rb1, dst);
+    if (n == 0) {
+      cur = C0;
+      cur_rows = rows;
+      cur_cols = cols;
+    } else {
+      double* nxt = cur == C0 ? C1 : C0;
+      dim3 grid((unsigned)((cols + 15) / 16), (unsigned)((cur_rows + 15) / 16));
+      k_gemm<<<grid, 256, 0, s>>>(cur, E, cur_rows, cur_cols, cols, nxt);
+      cur = nxt;
+      cur_cols = cols;
+    }
+  }
+  k_trace<<<1, 256, 0, s>>>(cur, cur_rows, out);
+  return hipGetLastError();
+}
+
+}  // namespace trals
