@@ -90,6 +90,39 @@ def cpu_baseline(X, init, cfg, budget_s):
     }
 
 
+def serving_form(args):
+    """Poisson stream of small decomposition requests (orders 3-5, sizes 32-256, ranks 3-12,
+    J=2048, 5 sweeps, FP32, 1% noise) through the continuous-batching loop."""
+    import synth
+    from paper_2010_08581_amd.serve import TralsEngine, run, summarize
+    eng = TralsEngine(synth.serving_true_cores, precision="f32", noise_rel=0.01, keep_cores=False)
+    budget = 16 << 30
+    warm = synth.serving_requests(8, rate=1e9, seed=99)
+    run(eng, warm, slots=args.serve_slots, mem_budget=budget)
+    reqs = synth.serving_requests(args.serve_requests, rate=200.0, seed=0)
+    log(f"serving: {len(reqs)} requests at 200 req/s, {args.serve_slots} slots")
+    res, wall, sched = run(eng, reqs, slots=args.serve_slots, mem_budget=budget)
+    live = summarize(res, wall)
+    live.update(rate_req_per_s=200.0, slots=args.serve_slots, peak_running=sched.peak_running)
+    log(f"serving live: p50 {live['p50_ms']:.2f} ms p99 {live['p99_ms']:.2f} ms")
+    # saturation: the same requests all at once, one at a time (plain) and concurrently
+    burst = [dict(r, arrival=0.0) for r in reqs]
+    res1, wall1, _ = run(eng, burst, slots=1, mem_budget=budget)
+    resk, wallk, schedk = run(eng, burst, slots=args.serve_slots, mem_budget=budget)
+    seq, conc = summarize(res1, wall1), summarize(resk, wallk)
+    same = all(a.fit == b.fit for a, b in zip(res1, resk))
+    log(f"serving saturated: sequential {seq['req_per_s']:.1f} req/s, concurrent {conc['req_per_s']:.1f} req/s")
+    return {
+        "workload": "Poisson 200 req/s; N in {3,4,5}, I_n in [32,256], R_n in [3,12], J=2048, 5 sweeps, "
+                    "fp32, 1% noise, generated source",
+        "live": live,
+        "saturated_sequential": seq,
+        "saturated_concurrent": dict(conc, slots=args.serve_slots, peak_running=schedk.peak_running),
+        "speedup_concurrent_vs_sequential": conc["req_per_s"] / seq["req_per_s"],
+        "fit_identical_alone_and_mixed": same,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +133,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16-form", action="store_true")
+    ap.add_argument("--no-serving-form", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -219,6 +255,10 @@ def main():
             "contract_gather_GBps": np.mean([J * dims[n] * 2 for n in range(N)]) / (ms / max(cnt, 1) * 1e-3) / 1e9,
         }}
         log(f"bf16 form: {eb / args.steps * 1e3:.3f} ms/sweep, fit {fb:.4e}")
+    if not args.no_serving_form:
+        h = hb = None  # noqa: F841 (releases the handles' workspaces)
+        torch.cuda.empty_cache()
+        out.setdefault("forms", {})["serving"] = serving_form(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(X, init, cfg, args.cpu_budget)

@@ -53,7 +53,8 @@ typedef enum {
   TRALS_ESINGULAR = -3,  /* sampled normal equations or a core's Gram not positive definite;
                             the core being updated is left unchanged */
   TRALS_EHIP = -4,       /* a HIP runtime call failed */
-  TRALS_ESTATE = -5      /* handle is in a failed state (reset it with trals_set_cores) */
+  TRALS_ESTATE = -5,     /* handle is in a failed state (reset it with trals_set_cores) */
+  TRALS_PENDING = 1      /* trals_query: work still running on the stream */
 } trals_status;
 
 typedef enum {
@@ -110,7 +111,9 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
 
 /* As trals_workspace_bytes / trals_create, for a generated data source (no X, no panels).
  * trals_fit_error of such a handle returns ||TR(G) - TR(G*)||_F / ||TR(G*)||_F (the error
- * against the noise-free tensor, by transfer matrices). */
+ * against the noise-free tensor, by transfer matrices).  The sizing call reads only the ranks,
+ * dtype and noise level of src (true_cores may be NULL there); trals_create_generated needs
+ * the device pointer. */
 int trals_workspace_bytes_generated(const trals_desc* desc, const trals_source* src, size_t* bytes);
 int trals_create_generated(const trals_desc* desc, const trals_source* src, void* ws_dev, size_t ws_bytes,
                            void* stream, trals_handle* out);
@@ -118,6 +121,14 @@ int trals_create_generated(const trals_desc* desc, const trals_source* src, void
 /* Run n_sweeps outer iterations of Algorithm 2 (each updates cores 0..N-1 in
  * order), continuing from the handle's update counter. */
 int trals_sweep(trals_handle h, int32_t n_sweeps);
+
+/* Enqueue n_sweeps like trals_sweep and return without synchronising the stream (several
+ * handles on different streams then overlap on the device).  trals_query reports completion:
+ * TRALS_PENDING while the stream still runs the enqueued work, TRALS_OK once it finished
+ * successfully, TRALS_ESINGULAR if a solve failed; it never blocks.  trals_destroy waits for
+ * pending work before it returns. */
+int trals_sweep_async(trals_handle h, int32_t n_sweeps);
+int trals_query(trals_handle h);
 
 /* Run n_updates single core updates (inner iterations of Algorithm 2),
  * continuing from the update counter; core n = counter mod N is updated next. */

@@ -117,6 +117,18 @@ class TRALS:
     def sweep(self, n=1):
         _lib.check(self.lib.trals_sweep(self.h, int(n)), "trals_sweep")
 
+    def sweep_async(self, n=1):
+        """Enqueue n sweeps on the handle's stream without waiting (see query)."""
+        _lib.check(self.lib.trals_sweep_async(self.h, int(n)), "trals_sweep_async")
+
+    def query(self) -> bool:
+        """True once the enqueued work has finished (raises if a solve failed)."""
+        rc = self.lib.trals_query(self.h)
+        if rc == _lib.TRALS_PENDING:
+            return False
+        _lib.check(rc, "trals_query")
+        return True
+
     def step(self, n=1):
         _lib.check(self.lib.trals_step(self.h, int(n)), "trals_step")
 

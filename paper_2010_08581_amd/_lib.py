@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtrals.so")
 
 TRALS_OK, TRALS_EINVAL, TRALS_ENOMEM, TRALS_ESINGULAR, TRALS_EHIP, TRALS_ESTATE = 0, -1, -2, -3, -4, -5
+TRALS_PENDING = 1
 TRALS_F64, TRALS_F32, TRALS_BF16 = 0, 1, 2
 
 # every symbol include/trals.h declares
@@ -20,6 +21,7 @@ EXPORTS = (
     "trals_destroy", "trals_get_cores", "trals_set_cores", "trals_get_last_samples",
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
     "trals_profile_read", "trals_workspace_bytes_generated", "trals_create_generated",
+    "trals_sweep_async", "trals_query",
 )
 KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
@@ -83,6 +85,8 @@ def load(path: str = LIB_PATH):
         "trals_profile": (C.c_int, [vp, i32]),
         "trals_profile_read": (C.c_int, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "trals_workspace_bytes_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), C.POINTER(C.c_size_t)]),
+        "trals_sweep_async": (C.c_int, [vp, i32]),
+        "trals_query": (C.c_int, [vp]),
         "trals_create_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), vp, C.c_size_t, vp, C.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():

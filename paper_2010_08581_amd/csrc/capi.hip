@@ -114,7 +114,7 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   p->ne_dt = p->panel_dt;
   if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
   if (src) {
-    if (!src->true_cores || (src->true_dtype != TRALS_F64 && src->true_dtype != TRALS_F32)) return TRALS_EINVAL;
+    if (src->true_dtype != TRALS_F64 && src->true_dtype != TRALS_F32) return TRALS_EINVAL;
     if (!(src->noise_rel >= 0.0) || !isfinite(src->noise_rel)) return TRALS_EINVAL;
     p->generated = true;
     p->Ptmax = 0;
@@ -210,6 +210,8 @@ struct trals_ctx {
   bool failed = false;
   bool table_valid[kMaxOrder] = {};
   bool have_last = false;
+  hipEvent_t done = nullptr;  // end of the last asynchronous sweep
+  bool pending = false;
   double xnorm2 = 0.0;   // ||X||_F^2, or ||TR(G*)||_F^2 for a generated source
   double sigma = 0.0;    // noise level of a generated source
   hipError_t last_hip = hipSuccess;
@@ -500,6 +502,7 @@ const char* trals_strerror(int code) {
     case TRALS_ESINGULAR: return "sampled normal equations or core Gram not positive definite";
     case TRALS_EHIP: return "HIP runtime error";
     case TRALS_ESTATE: return "handle in a failed or incomplete state";
+    case TRALS_PENDING: return "work still running";
     default: return "unknown status";
   }
 }
@@ -581,7 +584,7 @@ int trals_workspace_bytes_generated(const trals_desc* desc, const trals_source* 
 
 int trals_create_generated(const trals_desc* desc, const trals_source* src, void* ws_dev, size_t ws_bytes,
                            void* stream, trals_handle* out) {
-  if (!out || !src) return TRALS_EINVAL;
+  if (!out || !src || !src->true_cores) return TRALS_EINVAL;
   *out = nullptr;
   Problem p;
   int rc = validate(desc, &p, src);
@@ -652,6 +655,34 @@ int trals_sweep(trals_handle h, int32_t n_sweeps) {
   return run_updates(h, (int64_t)n_sweeps * h->p.N);
 }
 
+int trals_sweep_async(trals_handle h, int32_t n_sweeps) {
+  if (!h || n_sweeps < 0) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  const int64_t count = (int64_t)n_sweeps * h->p.N;
+  for (int64_t u = 0; u < count; ++u) {
+    const int rc = run_update(h);
+    if (rc) {
+      h->failed = true;
+      return rc;
+    }
+  }
+  if (!h->done) HIPTRY(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+  HIPTRY(hipEventRecord(h->done, h->stream));
+  h->pending = true;
+  return TRALS_OK;
+}
+
+int trals_query(trals_handle h) {
+  if (!h) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  if (!h->pending) return TRALS_OK;
+  const hipError_t q = hipEventQuery(h->done);
+  if (q == hipErrorNotReady) return TRALS_PENDING;
+  HIPTRY(q);
+  h->pending = false;
+  return sync_status(h);  // the stream is idle: copies the status word and returns at once
+}
+
 int trals_step(trals_handle h, int32_t n_updates) { return run_updates(h, n_updates); }
 
 int trals_fit_error(trals_handle h, double* rel_err) {
@@ -696,6 +727,8 @@ int trals_fit_error(trals_handle h, double* rel_err) {
 
 int trals_destroy(trals_handle h) {
   if (!h) return TRALS_OK;
+  if (h->pending) (void)hipStreamSynchronize(h->stream);  // work may still use the workspace
+  if (h->done) (void)hipEventDestroy(h->done);
   for (auto& v : h->prof.ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   delete h;

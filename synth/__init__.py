@@ -41,6 +41,7 @@ __all__ = [
     "add_noise_rel",
     "video_tensor",
     "serving_requests",
+    "serving_true_cores",
     "CONFIGS",
     "make_config",
 ]
@@ -169,6 +170,13 @@ def serving_requests(n_requests: int, rate: float = 200.0, seed: int = 0,
         reqs.append(dict(id=r, arrival=float(t[r]), dims=dims, ranks=ranks,
                          samples=int(samples), sweeps=int(sweeps), seed=int(seed)))
     return reqs
+
+
+def serving_true_cores(req, dtype=np.float64):
+    """True cores of one serving request: iid N(0,1), drawn from the request's
+    seed and id alone (so the request can be rebuilt without the others)."""
+    rng = np.random.default_rng([int(req["seed"]), TAG_SERVE, int(req["id"])])
+    return random_cores(req["dims"], req["ranks"], rng, dtype)
 
 
 # Workloads: sizes and noise of the paper's synthetic experiments

@@ -93,6 +93,16 @@ def test_wide_and_square_cores_fp64():
     lockstep(t, X, 6, 64, core_tol=1e-10)
 
 
+def test_large_scale_cores_ragged_P_fp64():
+    # Gram and core-Gram diagonals far above 1 / (P eps) with P = 15, 27, 45 (not multiples
+    # of the 16-wide Cholesky blocks): the padded unit pivots must not count as breakdown
+    say("case: fp64 40x50x60 R=(3,9,5) cores scaled by 1e7, J=200")
+    X = rng_for(65, 0).standard_normal((40, 50, 60))
+    init = [1e7 * c for c in random_cores(X.shape, (3, 9, 5), rng_for(65, 3))]
+    t = TR(torch.tensor(X, device="cuda"), (3, 9, 5), 200, precision="f64", init_cores=init)
+    lockstep(t, X, 6, 200, core_tol=1e-9)
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_fit_error_matches_oracle(prec, tol):
     say(f"case: fit error {prec}")
