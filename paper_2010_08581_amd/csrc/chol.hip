@@ -223,20 +223,25 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
       double v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = src[c];
-      bool bad = false;
+      int bad = 0;
       double myil = 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const double pk = lane_bcast(v[k], k);
         // rows past P are padding (unit pivots), outside the tolerance test: it is relative to
-        // the largest diagonal entry and can exceed 1
-        bad = bad || (16 * K + k < P && (!(pk > tol) || !isfinite(pk)));
+        // the largest diagonal entry and can exceed 1.  Bitwise flags: no branch per pivot.
+        const int ok = (int)(pk > tol) & (int)(pk < __builtin_huge_val());
+        bad |= (int)(16 * K + k < P) & (ok ^ 1);
         const double il = rsqrt_f64(fmax(pk, 1e-300));
         const double t = v[k] * (il * il);
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) v[j] = fma(-t, lane_bcast(v[k], j), v[j]);
         v[k] *= il;
         if (l == k) myil = il;
+        // keep the update right-looking: each column is final when its pivot step starts, so
+        // the compiler cannot defer the updates into a dependent chain at the pivot
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) asm volatile("" : "+v"(v[j]));
       }
       if (grp == 0) {
         if (tri == 0) {
