@@ -62,22 +62,32 @@ typedef enum {
   TRALS_F32 = 1,   /* IEEE single */
   TRALS_BF16 = 2   /* bfloat16 (precision TRALS_BF16 selects the BF16 form: BF16 data panels
                       and sketch on matrix cores with FP32 accumulation, FP64 Gram/Cholesky) */
-  /* TRALS_F32: FP32 data panels and sketch on FP32 matrix cores, each 32-sample stage added
-     into FP64 sums; TRALS_F64: FP64 throughout. */
+  /* TRALS_F32: FP32 data panels and sketch, multiplied on the FP64 matrix cores (FP32 operands
+     widen exactly) with FP64 sums; TRALS_F64: FP64 throughout. */
 } trals_dtype;
+
+typedef enum {
+  TRALS_LEVERAGE = 0,  /* Algorithm 2: samples drawn from the leverage-score distributions (3) */
+  TRALS_UNIFORM = 1,   /* Algorithm 2 with every p^(m) uniform (Section 4's uniform-sampling
+                          comparison): same draws, sketch and solve, no leverage computation */
+  TRALS_EXACT = 2      /* Algorithm 1 (TR-ALS): every update solves against the full design
+                          matrix G^{!=n}_[2] and all of X_[n] (prod_{m!=n} I_m rows, at most 2^24) */
+} trals_method;
 
 /* Problem description (Algorithm 2 inputs: X, target ranks; J per update; seed). */
 typedef struct {
   int32_t order;           /* N, 2 <= N <= 16 */
   const int64_t* dims;     /* host array I[0..N-1], each in [1, 2^21] */
   const int32_t* ranks;    /* host array R[0..N-1], each in [1, 32]; core n is R[n-1] x I[n] x R[n] */
-  int64_t samples;         /* J in [max_n R[n-1]*R[n], 2^24] (fewer rows cannot give a full-rank system) */
+  int64_t samples;         /* J in [max_n R[n-1]*R[n], 2^24] (fewer rows cannot give a full-rank
+                              system); ignored by TRALS_EXACT */
   uint64_t seed;           /* Philox4x64-10 key word 0 */
   uint64_t stream_id;      /* Philox4x64-10 key word 1 (independent problems use distinct ids) */
   int32_t precision;       /* TRALS_F64, TRALS_F32 or TRALS_BF16 */
   const void* init_cores;  /* optional device pointer to all N cores (layout above), element type
                               init_dtype; NULL draws every entry iid N(0,1) (Section 3) from the seed */
   int32_t init_dtype;      /* TRALS_F64 or TRALS_F32 */
+  int32_t method;          /* trals_method; 0 (TRALS_LEVERAGE) is the paper's proposal */
 } trals_desc;
 
 /* Generated data source (serving): the tensor is X = TR(G*) + sigma Z with given "true" cores
@@ -95,7 +105,8 @@ typedef struct {
   uint64_t noise_seed, noise_stream;
 } trals_source;
 
-/* Bytes of device workspace trals_create needs for this description.
+/* Bytes of device workspace trals_create needs for this description (TRALS_EXACT holds the full
+ * design matrix of the largest update: (max_n prod_{m!=n} I_m) x max_n R[n-1]R[n] entries).
  * Pure host computation.  Returns TRALS_EINVAL for an invalid description. */
 int trals_workspace_bytes(const trals_desc* desc, size_t* bytes);
 
@@ -121,6 +132,22 @@ int trals_create_generated(const trals_desc* desc, const trals_source* src, void
 /* Run n_sweeps outer iterations of Algorithm 2 (each updates cores 0..N-1 in
  * order), continuing from the handle's update counter. */
 int trals_sweep(trals_handle h, int32_t n_sweeps);
+
+/* Sample count of the following updates (Section 3.5: J may change between updates at no
+ * cost).  Sampled methods only; samples in [max_n R[n-1]*R[n], the J given at creation] (the
+ * workspace was sized for that J).  trals_samples returns the current J (-1 for NULL). */
+int trals_set_samples(trals_handle h, int64_t samples);
+int64_t trals_samples(trals_handle h);
+
+/* ||TR(G)||_F of the current cores by transfer matrices (trace of prod_n sum_i G_n(:,i,:) (x)
+ * G_n(:,i,:), O(sum_n I_n R^4) work, no pass over X).  Synchronises the stream. */
+int trals_tr_norm(trals_handle h, double* norm);
+
+/* Termination by the change of ||TR(G)||_F (Section 3.4): run whole sweeps until
+ * |n_k - n_{k-1}| / n_k < rel_tol after sweep k, or max_sweeps sweeps.  Reports the sweeps run
+ * and the last relative change (-1 if none).  Synchronises once per sweep. */
+int trals_sweep_until(trals_handle h, int32_t max_sweeps, double rel_tol, int32_t* sweeps_done,
+                      double* last_change);
 
 /* Enqueue n_sweeps like trals_sweep and return without synchronising the stream (several
  * handles on different streams then overlap on the device).  trals_query reports completion:
@@ -149,8 +176,9 @@ int trals_set_cores(trals_handle h, const void* src_dev, int32_t dtype);
 
 /* Samples of the most recent update (host arrays): idx_host[j*(N-1)+k] is the
  * index drawn in mode (n+1+k) mod N for sample j, w_host[j] the Definition 5
- * rescaling 1/sqrt(J q_j).  Either pointer may be NULL.  TRALS_ESTATE before
- * the first update. */
+ * rescaling 1/sqrt(J q_j), J the current sample count.  Either pointer may be
+ * NULL.  TRALS_ESTATE before the first update (or after trals_set_samples);
+ * TRALS_EINVAL for TRALS_EXACT. */
 int trals_get_last_samples(trals_handle h, int32_t* idx_host, double* w_host);
 
 /* Number of core updates run so far (sweeps * N + position in the sweep). */

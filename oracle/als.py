@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .leverage import core_table
+from .leverage import core_table, uniform_table
 from .ring import core_from_unfolding, cyclic_modes, subchain_unfolding, unfold_cyclic, tr_full
 from .sampler import draw_update
 
@@ -88,7 +88,12 @@ def sampled_update(X, cores, tables, n, J, seed, stream_id, u):
     return solve_core(A, B, Rp, Rn), idx, w
 
 
-def lockstep_update(X, cores, n, J, seed, stream_id, u):
+def table_of(G, uniform=False):
+    """Sampling table of core G: leverage scores (eq. (3)) or uniform."""
+    return uniform_table(G.shape[1]) if uniform else core_table(G)
+
+
+def lockstep_update(X, cores, n, J, seed, stream_id, u, uniform=False):
     """Sampled update of core n taking every table from ``cores`` afresh.
 
     Used to compare against a GPU run one update at a time: the GPU's cores
@@ -99,42 +104,51 @@ def lockstep_update(X, cores, n, J, seed, stream_id, u):
     tables = [None] * N
     for m in range(N):
         if m != n:
-            tables[m] = core_table(cores[m])
+            tables[m] = table_of(cores[m], uniform)
     return sampled_update(X, cores, tables, n, J, seed, stream_id, u)
 
 
-def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u0=0):
+def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u0=0, uniform=False):
     """Algorithm 2 with a fixed number of sweeps (the paper's experiments fix
     the iteration count, Section 4.1).  ``record`` (a list) receives
-    (u, n, idx, w) for every update.  Returns the list of cores."""
+    (u, n, idx, w) for every update.  ``J`` may be a function of the update
+    number u (the sample size can change between updates, Section 3.5).
+    ``uniform`` draws from uniform distributions instead of eq. (3).
+    Returns the list of cores."""
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
     cores = [np.array(c, dtype=np.float64) for c in init_cores]
     tables = [None] * N
     for m in range(N):
         if m != (u0 % N):
-            tables[m] = core_table(cores[m])
+            tables[m] = table_of(cores[m], uniform)
     for u in range(u0, u0 + sweeps * N):
         n = u % N
-        cores[n], idx, w = sampled_update(X, cores, tables, n, J, seed, stream_id, u)
-        tables[n] = core_table(cores[n])
+        Ju = J(u) if callable(J) else J
+        cores[n], idx, w = sampled_update(X, cores, tables, n, Ju, seed, stream_id, u)
+        tables[n] = table_of(cores[n], uniform)
         if record is not None:
             record.append((u, n, idx, w))
     return cores
 
 
+def exact_update(X, cores, n):
+    """One inner iteration of Algorithm 1: core n refit against the full design
+    matrix G^{!=n}_[2] and the full unfolding X_[n]^T."""
+    A = subchain_unfolding(cores, n)
+    B = unfold_cyclic(np.asarray(X, dtype=np.float64), n).T
+    Rp, _, Rn = cores[n].shape
+    return solve_core(A, B, Rp, Rn)
+
+
 def tr_als_exact(X, init_cores, sweeps):
-    """Algorithm 1 (TR-ALS): each core refit against the full design matrix
-    G^{!=n}_[2] and the full unfolding X_[n]^T.  For small tensors only."""
+    """Algorithm 1 (TR-ALS) with a fixed number of sweeps.  For small tensors only."""
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
     cores = [np.array(c, dtype=np.float64) for c in init_cores]
     for _ in range(sweeps):
         for n in range(N):
-            A = subchain_unfolding(cores, n)
-            B = unfold_cyclic(X, n).T
-            Rp, _, Rn = cores[n].shape
-            cores[n] = solve_core(A, B, Rp, Rn)
+            cores[n] = exact_update(X, cores, n)
     return cores
 
 

@@ -60,3 +60,9 @@ def integer_table(p):
 def core_table(G):
     """Integer sampling table of one core: integer_table(mode_distribution(G))."""
     return integer_table(mode_distribution(G))
+
+
+def uniform_table(I):
+    """Integer table of the uniform distribution over I indices (the uniform-sampling
+    comparison of Section 4: p_i = 1/I)."""
+    return integer_table(np.full(int(I), 1.0 / int(I)))

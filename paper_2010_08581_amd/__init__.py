@@ -15,6 +15,7 @@ from . import _lib
 from ._lib import TRALS_F32, TRALS_F64, TRALS_BF16, TralsError  # noqa: F401
 
 _PREC = {"f64": TRALS_F64, "f32": TRALS_F32, "bf16": TRALS_BF16}
+_METHOD = {"leverage": _lib.TRALS_LEVERAGE, "uniform": _lib.TRALS_UNIFORM, "exact": _lib.TRALS_EXACT}
 
 
 def _torch():
@@ -29,12 +30,15 @@ class TRALS:
     R[n-1] x I[n] x R[n]).  samples: J per core update.  precision: "f64",
     "f32" or "bf16".  init_cores: optional list of N tensors (any device) of
     shapes (R[n-1], I[n], R[n]); None draws N(0,1) entries on the GPU.
+    method: "leverage" (Algorithm 2), "uniform" (Algorithm 2 with uniform
+    sampling) or "exact" (Algorithm 1; samples is ignored).
     """
 
     def __init__(self, X, ranks, samples, seed=0, stream_id=0, precision="f32", init_cores=None,
-                 stream=None, source=None):
+                 stream=None, source=None, method="leverage"):
         torch = _torch()
         self.lib = _lib.load()
+        self.method = method
         if source is not None:
             self._init_generated(source, ranks, samples, seed, stream_id, precision, init_cores, stream)
             return
@@ -55,7 +59,7 @@ class TRALS:
                                   .to(device=X.device, dtype=torch.float64).reshape(-1) for c in init_cores])
             init_ptr = init_buf.data_ptr()
         desc, self._keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
-                                          init_ptr, init_dt)
+                                          init_ptr, init_dt, _METHOD[method])
         nbytes = C.c_size_t(0)
         _lib.check(self.lib.trals_workspace_bytes(C.byref(desc), C.byref(nbytes)), "trals_workspace_bytes")
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=X.device)
@@ -68,13 +72,14 @@ class TRALS:
 
     @classmethod
     def generated(cls, true_cores, ranks, samples, noise_rel=0.0, noise_seed=0, noise_stream=0,
-                  seed=0, stream_id=0, precision="f32", init_cores=None, stream=None, device=None):
+                  seed=0, stream_id=0, precision="f32", init_cores=None, stream=None, device=None,
+                  method="leverage"):
         """Handle whose data is TR(true_cores) + noise, generated fiber by fiber on the GPU
         (never materialised).  true_cores: list of N arrays/tensors (R[n-1], I[n], R[n])."""
         src = dict(true_cores=true_cores, noise_rel=noise_rel, noise_seed=noise_seed,
                    noise_stream=noise_stream, device=device)
         return cls(None, ranks, samples, seed=seed, stream_id=stream_id, precision=precision,
-                   init_cores=init_cores, stream=stream, source=src)
+                   init_cores=init_cores, stream=stream, source=src, method=method)
 
     def _init_generated(self, source, ranks, samples, seed, stream_id, precision, init_cores, stream):
         torch = _torch()
@@ -97,7 +102,7 @@ class TRALS:
                                   .to(device=dev, dtype=torch.float64).reshape(-1) for c in init_cores])
             init_ptr = init_buf.data_ptr()
         desc, keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
-                                    init_ptr, TRALS_F64)
+                                    init_ptr, TRALS_F64, _METHOD[self.method])
         src, keep2 = _lib.make_source(self._true_buf.data_ptr(), TRALS_F64, true_ranks, source["noise_rel"],
                                       source["noise_seed"], source["noise_stream"])
         self._keep = (keep, keep2, init_buf)
@@ -131,6 +136,25 @@ class TRALS:
 
     def step(self, n=1):
         _lib.check(self.lib.trals_step(self.h, int(n)), "trals_step")
+
+    def set_samples(self, J):
+        """Sample count of the following updates (at most the J given at creation)."""
+        _lib.check(self.lib.trals_set_samples(self.h, int(J)), "trals_set_samples")
+        self.J = int(J)
+
+    def tr_norm(self) -> float:
+        """||TR(G)||_F of the current cores (transfer matrices on the GPU)."""
+        out = C.c_double(0.0)
+        _lib.check(self.lib.trals_tr_norm(self.h, C.byref(out)), "trals_tr_norm")
+        return float(out.value)
+
+    def sweep_until(self, max_sweeps, rel_tol):
+        """Sweeps until the relative change of ||TR(G)||_F falls below rel_tol; returns
+        (sweeps run, last relative change)."""
+        done, change = C.c_int32(0), C.c_double(0.0)
+        _lib.check(self.lib.trals_sweep_until(self.h, int(max_sweeps), float(rel_tol), C.byref(done),
+                                              C.byref(change)), "trals_sweep_until")
+        return int(done.value), float(change.value)
 
     def fit_error(self) -> float:
         out = C.c_double(0.0)

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtrals.so")
 TRALS_OK, TRALS_EINVAL, TRALS_ENOMEM, TRALS_ESINGULAR, TRALS_EHIP, TRALS_ESTATE = 0, -1, -2, -3, -4, -5
 TRALS_PENDING = 1
 TRALS_F64, TRALS_F32, TRALS_BF16 = 0, 1, 2
+TRALS_LEVERAGE, TRALS_UNIFORM, TRALS_EXACT = 0, 1, 2
 
 # every symbol include/trals.h declares
 EXPORTS = (
@@ -21,7 +22,8 @@ EXPORTS = (
     "trals_destroy", "trals_get_cores", "trals_set_cores", "trals_get_last_samples",
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
     "trals_profile_read", "trals_workspace_bytes_generated", "trals_create_generated",
-    "trals_sweep_async", "trals_query",
+    "trals_sweep_async", "trals_query", "trals_set_samples", "trals_samples", "trals_tr_norm",
+    "trals_sweep_until",
 )
 KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
@@ -37,6 +39,7 @@ class Desc(C.Structure):
         ("precision", C.c_int32),
         ("init_cores", C.c_void_p),
         ("init_dtype", C.c_int32),
+        ("method", C.c_int32),
     ]
 
 
@@ -87,6 +90,10 @@ def load(path: str = LIB_PATH):
         "trals_workspace_bytes_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), C.POINTER(C.c_size_t)]),
         "trals_sweep_async": (C.c_int, [vp, i32]),
         "trals_query": (C.c_int, [vp]),
+        "trals_set_samples": (C.c_int, [vp, i64]),
+        "trals_samples": (i64, [vp]),
+        "trals_tr_norm": (C.c_int, [vp, C.POINTER(C.c_double)]),
+        "trals_sweep_until": (C.c_int, [vp, i32, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "trals_create_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), vp, C.c_size_t, vp, C.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
@@ -107,18 +114,18 @@ def check(code: int, what: str):
 
 
 def make_desc(dims, ranks, samples, seed=0, stream_id=0, precision=TRALS_F32, init_ptr=None,
-              init_dtype=TRALS_F64):
+              init_dtype=TRALS_F64, method=TRALS_LEVERAGE):
     """Build a Desc plus the host arrays it points to (keep the tuple alive)."""
     N = len(dims)
     d_arr = (C.c_int64 * N)(*[int(v) for v in dims])
     r_arr = (C.c_int32 * N)(*[int(v) for v in ranks])
     desc = Desc(N, d_arr, r_arr, int(samples), int(seed), int(stream_id), int(precision),
-                C.c_void_p(init_ptr) if init_ptr else None, int(init_dtype))
+                C.c_void_p(init_ptr) if init_ptr else None, int(init_dtype), int(method))
     return desc, (d_arr, r_arr)
 
 
-def workspace_bytes(dims, ranks, samples, precision=TRALS_F32):
-    desc, keep = make_desc(dims, ranks, samples, precision=precision)
+def workspace_bytes(dims, ranks, samples, precision=TRALS_F32, method=TRALS_LEVERAGE):
+    desc, keep = make_desc(dims, ranks, samples, precision=precision, method=method)
     out = C.c_size_t(0)
     check(load().trals_workspace_bytes(C.byref(desc), C.byref(out)), "trals_workspace_bytes")
     return int(out.value)

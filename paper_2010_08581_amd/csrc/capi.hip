@@ -37,7 +37,9 @@ struct Problem {
   int N;
   int64_t dims[kMaxOrder];
   int32_t ranks[kMaxOrder];
-  int64_t J;
+  int64_t J;     // samples per update (sampled methods); rows of the largest design (exact)
+  int64_t Jcap;  // J at creation: the workspace holds up to this many samples
+  int method;    // TRALS_LEVERAGE, TRALS_UNIFORM or TRALS_EXACT
   uint64_t seed, stream_id;
   int prec;
   int sk_dt, panel_dt, ne_dt;  // cores are FP64 in every precision
@@ -70,6 +72,9 @@ Ring ring_of(const Problem& p, const int32_t* ranks) {
 
 int P_of(const Problem& p, int n) { return p.ranks[(n + p.N - 1) % p.N] * p.ranks[n]; }
 
+// rows of update n's least-squares problem: J samples, or every index tuple of the other modes
+int64_t J_of(const Problem& p, int n) { return p.method == TRALS_EXACT ? p.E / p.dims[n] : p.J; }
+
 int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr) {
   if (!d || !d->dims || !d->ranks) return TRALS_EINVAL;
   if (d->order < 2 || d->order > kMaxOrder) return TRALS_EINVAL;
@@ -86,14 +91,29 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
     if (p->E > ((int64_t)1 << (src ? 62 : 40)) / d->dims[n]) return TRALS_EINVAL;
     p->E *= d->dims[n];
   }
-  p->J = d->samples;
+  p->method = d->method;
+  if (p->method != TRALS_LEVERAGE && p->method != TRALS_UNIFORM && p->method != TRALS_EXACT) return TRALS_EINVAL;
   p->Pmax = 0;
   p->Imax = 0;
   for (int n = 0; n < p->N; ++n) {
     p->Pmax = P_of(*p, n) > p->Pmax ? P_of(*p, n) : p->Pmax;
     p->Imax = p->dims[n] > p->Imax ? p->dims[n] : p->Imax;
   }
-  if (p->J < p->Pmax || p->J > ((int64_t)1 << 24)) return TRALS_EINVAL;  // grid-z limit of the split-K partials
+  if (p->method == TRALS_EXACT) {
+    // Algorithm 1: the full design matrix of update n has prod_{m != n} I_m rows
+    if (src) return TRALS_EINVAL;  // needs the data panels
+    p->J = 0;
+    for (int n = 0; n < p->N; ++n) {
+      const int64_t rows = p->E / p->dims[n];
+      if (rows < P_of(*p, n) || rows > ((int64_t)1 << 24)) return TRALS_EINVAL;
+      p->J = rows > p->J ? rows : p->J;
+    }
+  } else {
+    p->J = d->samples;
+    // grid-z limit of the split-K partials; fewer than Pmax rows cannot give a full-rank system
+    if (p->J < p->Pmax || p->J > ((int64_t)1 << 24)) return TRALS_EINVAL;
+  }
+  p->Jcap = p->J;
   {
     int64_t tot = 0, mn = p->dims[0];
     for (int n = 0; n < p->N; ++n) {
@@ -155,10 +175,17 @@ void plan(const Problem& p, Layout* L) {
     }
     L->Tm = take((size_t)p.J * p.Ptmax * 8);
     L->Xg = take((size_t)p.J * p.Imax * p.panel_sz);
-    const Ring rr = ring_of(p, p.ranks), rt = ring_of(p, p.tranks);
+  }
+  {
+    // transfer-matrix inner products: <G, G> (norm of the ring), and <G, G*>, <G*, G*> for a
+    // generated source
+    const Ring rr = ring_of(p, p.ranks);
     size_t w = ring_inner_doubles(rr, rr);
-    w = ring_inner_doubles(rr, rt) > w ? ring_inner_doubles(rr, rt) : w;
-    w = ring_inner_doubles(rt, rt) > w ? ring_inner_doubles(rt, rt) : w;
+    if (p.generated) {
+      const Ring rt = ring_of(p, p.tranks);
+      w = ring_inner_doubles(rr, rt) > w ? ring_inner_doubles(rr, rt) : w;
+      w = ring_inner_doubles(rt, rt) > w ? ring_inner_doubles(rt, rt) : w;
+    }
     L->inner = take((w + 4) * 8);  // work area, then 4 result doubles
     L->inner_res = L->inner + w * 8;
   }
@@ -167,7 +194,7 @@ void plan(const Problem& p, Layout* L) {
   size_t hpart = 0, bpart = 0;
   for (int n = 0; n < p.N; ++n) {
     const int P = P_of(p, n);
-    const NormalEqPlan pl = plan_normal_eq(P, (int)p.dims[n], p.J, p.ne_dt, kPlanCUs);
+    const NormalEqPlan pl = plan_normal_eq(P, (int)p.dims[n], J_of(p, n), p.ne_dt, kPlanCUs);
     const size_t h = (size_t)pl.splits * P * P, b = (size_t)pl.splits * P * p.dims[n];
     hpart = h > hpart ? h : hpart;
     bpart = b > bpart ? b : bpart;
@@ -280,8 +307,12 @@ int compute_table(trals_ctx* h, int m) {
   const int I = (int)p.dims[m];
   uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
   const double* core = h->at<const double>(h->L.core[m]);
+  if (p.method == TRALS_EXACT) {  // no sampling
+    h->table_valid[m] = true;
+    return TRALS_OK;
+  }
   PROF_BEGIN(TRALS_K_TABLE);
-  if (I > P) {
+  if (p.method == TRALS_LEVERAGE && I > P) {
     double* M2 = h->at<double>(h->L.M2);
     double* F2 = h->at<double>(h->L.F2);
     HIPTRY(launch_syrk(core, I, P, M2, h->status(), h->stream));
@@ -321,12 +352,23 @@ int run_update(trals_ctx* h) {
     }
   const int P = P_of(p, n);
   const int In = (int)p.dims[n];
+  const int64_t Jn = J_of(p, n);
+  const bool exact = p.method == TRALS_EXACT;
+  // panel rows are the other modes in C order: stride of mode m = prod_{m' > m, m' != n} I_m'
+  int64_t pstride[kMaxOrder];
+  for (int k = 0; k < N - 1; ++k) {
+    const int m = (n + 1 + k) % N;
+    int64_t st = 1;
+    for (int m2 = m + 1; m2 < N; ++m2)
+      if (m2 != n) st *= p.dims[m2];
+    pstride[k] = st;
+  }
 
   DrawArgs da;
   memset(&da, 0, sizeof(da));
   da.ring = make_ring(p);
   da.n = n;
-  da.J = p.J;
+  da.J = Jn;
   da.seed = p.seed;
   da.stream_id = p.stream_id;
   da.u = (uint64_t)h->upd;
@@ -339,7 +381,9 @@ int run_update(trals_ctx* h) {
   da.A = h->at<void>(h->L.A);
   da.status = h->status();
   da.weights = p.tables_as_weights ? 1 : 0;
-  da.draw = 1;
+  da.draw = exact ? 0 : 1;
+  da.enumerate = exact ? 1 : 0;
+  for (int k = 0; k < N - 1; ++k) da.en_stride[k] = pstride[k];
   PROF_BEGIN(TRALS_K_DRAW);
   HIPTRY(launch_draw(da, p.sk_dt, h->stream));
   if (p.generated) {
@@ -376,24 +420,19 @@ int run_update(trals_ctx* h) {
   }
   PROF_END(TRALS_K_DRAW);
 
-  const NormalEqPlan pl = plan_normal_eq(P, In, p.J, p.ne_dt, kPlanCUs);
+  const NormalEqPlan pl = plan_normal_eq(P, In, Jn, p.ne_dt, kPlanCUs);
   NormalEqArgs na;
   memset(&na, 0, sizeof(na));
   na.A = da.A;
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
-  na.direct = p.generated ? 1 : 0;
+  // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the
+  // panel's rows: row r of the sketch pairs with fiber row r
+  na.direct = (p.generated || exact) ? 1 : 0;
   na.idx = da.idx;
   na.w = da.w;
-  // panel rows are the other modes in C order: stride of mode m = prod_{m' > m, m' != n} I_m'
-  for (int k = 0; k < N - 1; ++k) {
-    const int m = (n + 1 + k) % N;
-    int64_t st = 1;
-    for (int m2 = m + 1; m2 < N; ++m2)
-      if (m2 != n) st *= p.dims[m2];
-    na.stride[k] = st;
-  }
+  for (int k = 0; k < N - 1; ++k) na.stride[k] = pstride[k];
   na.K = N - 1;
-  na.J = p.J;
+  na.J = Jn;
   na.chunk = pl.chunk;
   na.P = P;
   na.In = In;
@@ -440,7 +479,17 @@ int run_update(trals_ctx* h) {
   const int rc = compute_table(h, n);
   if (rc) return rc;
   h->upd += 1;
-  h->have_last = true;
+  h->have_last = !exact;
+  return TRALS_OK;
+}
+
+// <TR(G), TR(G)> by transfer matrices into inner_res[0] (enqueued on the handle's stream)
+int ring_norm_enqueue(trals_ctx* h) {
+  const Problem& p = h->p;
+  const Ring rr = make_ring(p);
+  PerMode<const double> G;
+  for (int n = 0; n < p.N; ++n) G.p[n] = h->at<const double>(h->L.core[n]);
+  HIPTRY(launch_ring_inner(rr, G, rr, G, h->at<double>(h->L.inner), h->at<double>(h->L.inner_res), h->stream));
   return TRALS_OK;
 }
 
@@ -798,7 +847,7 @@ int trals_set_cores(trals_handle h, const void* src_dev, int32_t dtype) {
 }
 
 int trals_get_last_samples(trals_handle h, int32_t* idx_host, double* w_host) {
-  if (!h) return TRALS_EINVAL;
+  if (!h || h->p.method == TRALS_EXACT) return TRALS_EINVAL;
   if (!h->have_last) return TRALS_ESTATE;
   const Problem& p = h->p;
   if (idx_host)
@@ -811,6 +860,52 @@ int trals_get_last_samples(trals_handle h, int32_t* idx_host, double* w_host) {
 }
 
 int64_t trals_update_counter(trals_handle h) { return h ? h->upd : -1; }
+
+int trals_set_samples(trals_handle h, int64_t samples) {
+  if (!h || h->p.method == TRALS_EXACT) return TRALS_EINVAL;
+  if (samples < h->p.Pmax || samples > h->p.Jcap) return TRALS_EINVAL;
+  h->p.J = samples;
+  h->have_last = false;
+  return TRALS_OK;
+}
+
+int64_t trals_samples(trals_handle h) { return h ? h->p.J : -1; }
+
+int trals_tr_norm(trals_handle h, double* norm) {
+  if (!h || !norm) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  const int rc = ring_norm_enqueue(h);
+  if (rc) return rc;
+  double g2 = 0.0;
+  HIPTRY(hipMemcpyAsync(&g2, h->at<double>(h->L.inner_res), 8, hipMemcpyDeviceToHost, h->stream));
+  HIPTRY(hipStreamSynchronize(h->stream));
+  *norm = sqrt(g2 > 0.0 ? g2 : 0.0);
+  return TRALS_OK;
+}
+
+int trals_sweep_until(trals_handle h, int32_t max_sweeps, double rel_tol, int32_t* sweeps_done,
+                      double* last_change) {
+  if (!h || max_sweeps < 1 || !(rel_tol >= 0.0)) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  double prev = 0.0, change = -1.0;
+  int rc = trals_tr_norm(h, &prev);
+  if (rc) return rc;
+  int32_t done = 0;
+  while (done < max_sweeps) {
+    rc = run_updates(h, h->p.N);
+    if (rc) break;
+    ++done;
+    double cur = 0.0;
+    rc = trals_tr_norm(h, &cur);
+    if (rc) break;
+    change = cur > 0.0 ? fabs(cur - prev) / cur : 0.0;
+    prev = cur;
+    if (change < rel_tol) break;
+  }
+  if (sweeps_done) *sweeps_done = done;
+  if (last_change) *last_change = change;
+  return rc;
+}
 
 int trals_set_update_counter(trals_handle h, int64_t counter) {
   if (!h || counter < 0) return TRALS_EINVAL;

@@ -1,5 +1,7 @@
 // Sampler and sketch of one core update, fused (Algorithm 3 draws, Definition 5 rescaling,
-// Algorithm 4 / eq. (5) subchain rows).
+// Algorithm 4 / eq. (5) subchain rows).  The same kernel forms the rows for given index tuples
+// (the true-core rows of a generated source) and, enumerating every tuple, the full design
+// matrix G^{!=n}_[2] of Algorithm 1 (exact TR-ALS).
 //
 // Tables.  The device tables hold either the integer weights Q_i (then every workgroup forms
 // the inclusive sums C in LDS while staging them) or the sums C themselves (problems whose
@@ -95,10 +97,23 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       }
   }
   if (tid < jb && !a.draw) {
-    // given samples (same rows, no rescaling)
+    // given samples (same rows, no rescaling), or every index tuple in panel-row order
     const int64_t j = j0 + tid;
-    for (int k = 0; k < K; ++k) s_idx[tid * K + k] = j < a.J ? a.idx[j * K + k] : 0;
+    for (int k = 0; k < K; ++k) {
+      int v = 0;
+      if (j < a.J) {
+        if (a.enumerate) {
+          int m = n + 1 + k;
+          if (m >= N) m -= N;
+          v = (int)((j / a.en_stride[k]) % a.ring.dims[m]);
+        } else {
+          v = a.idx[j * K + k];
+        }
+      }
+      s_idx[tid * K + k] = v;
+    }
     s_w[tid] = j < a.J ? 1.0 : 0.0;
+    if (a.enumerate && j < a.J) a.w[j] = 1.0;
   } else if (tid < jb) {
     const int64_t j = j0 + tid;
     if (j < a.J) {

@@ -38,6 +38,11 @@ struct DrawArgs {
   const int* status;
   int weights;                  // 1: cdf holds the weights Q (scanned in LDS); 0: inclusive sums C
   int draw;                     // 1: draw the samples; 0: take idx as given, rows without weights
+  // with draw == 0: 1 = row j is the j-th index tuple in the order of the mode-n panel's rows
+  // (digit k = (j / en_stride[k]) mod I of the k-th mode after n; idx is not read) and
+  // w[j] = 1 is written (the full design matrix of Algorithm 1)
+  int enumerate;
+  int64_t en_stride[kMaxOrder];
   int jb;                       // samples per workgroup (set by launch_draw)
   int tables_in_lds;            // set by launch_draw
 };

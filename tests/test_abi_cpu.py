@@ -77,3 +77,39 @@ def test_null_arguments(lib):
     # NULL data / workspace pointers are rejected before any device call
     assert lib.trals_create(C.byref(desc), None, 1, None, 0, None, C.byref(h)) == _lib.TRALS_EINVAL
     assert h.value is None
+
+
+def test_method_validation_and_exact_sizing(lib):
+    # unknown method
+    rc, _ = ws((20, 20, 20), (2, 2, 2), 100, method=3)
+    assert rc == _lib.TRALS_EINVAL
+    # exact: the samples field is ignored; the workspace holds the largest full design
+    rc, b_ex = ws((40, 30, 20), (2, 3, 2), 0, _lib.TRALS_F64, method=_lib.TRALS_EXACT)
+    assert rc == 0
+    rc, b_lev = ws((40, 30, 20), (2, 3, 2), 100, _lib.TRALS_F64)
+    assert rc == 0
+    assert b_ex - b_lev >= (30 * 40 - 100) * 6 * 8  # sketch of max prod_{m!=n} I_m = 1200 rows
+    # exact needs prod_{m != n} I_m >= R[n-1] R[n] for every n (here 2 * 2 < 3 * 3)
+    rc, _ = ws((2, 2, 50), (3, 3, 3), 0, method=_lib.TRALS_EXACT)
+    assert rc == _lib.TRALS_EINVAL
+    # uniform sizes like leverage sampling
+    rc, b_uni = ws((40, 30, 20), (2, 3, 2), 100, _lib.TRALS_F64, method=_lib.TRALS_UNIFORM)
+    assert rc == 0 and b_uni == b_lev
+
+
+def test_exact_rejects_generated_source(lib):
+    desc, keep = _lib.make_desc((20, 20, 20), (2, 2, 2), 0, method=_lib.TRALS_EXACT)
+    src, keep2 = _lib.make_source(None, _lib.TRALS_F64, None, 0.01, 0, 0)
+    out = C.c_size_t(0)
+    assert lib.trals_workspace_bytes_generated(C.byref(desc), C.byref(src), C.byref(out)) == _lib.TRALS_EINVAL
+    desc, keep = _lib.make_desc((20, 20, 20), (2, 2, 2), 100, method=_lib.TRALS_UNIFORM)
+    assert lib.trals_workspace_bytes_generated(C.byref(desc), C.byref(src), C.byref(out)) == 0
+
+
+def test_null_handles_of_new_entries(lib):
+    assert lib.trals_set_samples(None, 100) == _lib.TRALS_EINVAL
+    assert lib.trals_samples(None) == -1
+    assert lib.trals_tr_norm(None, None) == _lib.TRALS_EINVAL
+    assert lib.trals_sweep_until(None, 1, 0.0, None, None) == _lib.TRALS_EINVAL
+    assert lib.trals_sweep_async(None, 1) == _lib.TRALS_EINVAL
+    assert lib.trals_query(None) == _lib.TRALS_EINVAL

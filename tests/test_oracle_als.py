@@ -155,3 +155,36 @@ def test_exact_als_and_sampled_agree_on_noisy_data():
     e_ex = als.fit_error(als.tr_als_exact(X, init, 15), X)
     e_s = als.fit_error(als.tr_als_sampled(X, init, 400, 15, seed=0), X)
     assert e_s <= 1.2 * e_ex
+
+
+@pytest.mark.parametrize("n", [0, 2])
+def test_uniform_sampled_and_exact_updates_recover_consistent_core(n):
+    # noise-free TR data with the other cores at the truth: any full-rank row subset (uniform
+    # draws) and the full design (Algorithm 1) both return the true core
+    dims, ranks = (11, 13, 12), (2, 3, 2)
+    true = random_cores(dims, ranks, rng_for(58, n))
+    X = ring_tensor(true)
+    cores = [c.copy() for c in true]
+    cores[n] = rng_for(59, n).standard_normal(cores[n].shape)
+    tol = 1e-10 * np.abs(true[n]).max()
+    new_u, idx, w = als.lockstep_update(X, cores, n, 80, 0, 0, n, uniform=True)
+    np.testing.assert_allclose(new_u, true[n], rtol=0, atol=tol)
+    N = 3
+    others = [dims[(n + 1 + k) % N] for k in range(N - 1)]
+    np.testing.assert_allclose(w, np.sqrt(np.prod(others) / 80), rtol=1e-15)
+    np.testing.assert_allclose(als.exact_update(X, cores, n), true[n], rtol=0, atol=tol)
+
+
+def test_sample_count_may_change_between_updates():
+    dims, ranks = (9, 10, 11), (2, 2, 2)
+    X = rng_for(60, 0).standard_normal(dims)
+    init = random_cores(dims, ranks, rng_for(60, 3))
+    rec = []
+    Js = {0: 50, 1: 50, 2: 50, 3: 20, 4: 20, 5: 90}
+    als.tr_als_sampled(X, init, lambda u: Js[u], 2, seed=0, record=rec)
+    assert [r[2].shape[0] for r in rec] == [Js[u] for u in range(6)]
+    # the first updates are those of a run with a fixed J (same counters, same tables)
+    rec2 = []
+    als.tr_als_sampled(X, init, 50, 1, seed=0, record=rec2)
+    for a, b in zip(rec[:3], rec2):
+        assert np.array_equal(a[2], b[2])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import philox, sampler
-from oracle.leverage import integer_table
+from oracle.leverage import integer_table, uniform_table
 from synth import rng_for
 
 
@@ -99,3 +99,25 @@ def test_update_streams_are_distinct_and_weights_definition5():
             Q, C, T = tables[m]
             q *= Fraction(int(Q[i0[j, k]]), T)
         assert abs(w0[j] ** -2 / J - float(q)) <= 1e-14 * float(q)
+
+
+@pytest.mark.parametrize("I", [1, 3, 7, 40, 500, 2000])
+def test_uniform_table_is_exactly_uniform(I):
+    Q, C, T = uniform_table(I)
+    assert len(set(int(v) for v in Q)) == 1
+    assert T == I * int(Q[0])
+    assert Fraction(int(Q[0]), T) == Fraction(1, I)
+
+
+def test_uniform_draws_weights_closed_form_and_chi2():
+    dims = (5, 9, 6)
+    tables = [uniform_table(I) for I in dims]
+    J = 30000
+    idx, w = sampler.draw_update(tables, 0, J, seed=4, stream_id=2, u=1)
+    # Definition 5 with q = prod_k 1/I_k: w = sqrt(I_1 I_2 / J) for every sample
+    np.testing.assert_allclose(w, np.sqrt(9 * 6 / J), rtol=1e-15)
+    for k, I in enumerate((9, 6)):
+        counts = np.bincount(idx[:, k], minlength=I)
+        exp = J / I
+        chi2 = float(np.sum((counts - exp) ** 2 / exp))
+        assert chi2 < {9: 26.1, 6: 20.5}[I]  # I-1 dof, p ~ 1e-3
