@@ -90,6 +90,60 @@ def cpu_baseline(X, init, cfg, budget_s):
     }
 
 
+def method_forms(args, X, init, cfg):
+    """Exact TR-ALS (Algorithm 1) and uniform sampling beside the leverage-score method, on the
+    same tensor and initial cores, the same number of sweeps from fresh handles (the paper's
+    protocol, Section 4.1: speedup at comparable error)."""
+    import torch
+    from paper_2010_08581_amd import TRALS
+    dev = torch.device("cuda:0")
+    ranks, J, prec = cfg["ranks"], cfg["samples"], cfg["precision"]
+    S = args.method_sweeps
+    out = {}
+    Xt = torch.from_numpy(X).to(dev)
+    for name, method, Jm in (("leverage", "leverage", J), ("uniform", "uniform", J),
+                             ("uniform_4J", "uniform", 4 * J), ("exact", "exact", 0)):
+        h = TRALS(Xt, ranks, Jm, seed=cfg["seed"], precision=prec, init_cores=init, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.sweep(S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"method": method, "samples": Jm or None, "sweeps": S,
+                     "ms_per_sweep": el / S * 1e3, "fit_error": h.fit_error()}
+        log(f"{name}: {el / S * 1e3:.3f} ms/sweep, fit {out[name]['fit_error']:.5e}")
+        del h
+        torch.cuda.empty_cache()
+    del Xt
+    lev, ex = out["leverage"], out["exact"]
+    out["speedup_leverage_vs_exact"] = ex["ms_per_sweep"] / lev["ms_per_sweep"]
+    out["fit_ratio_leverage_vs_exact"] = lev["fit_error"] / ex["fit_error"]
+    out["fit_ratio_uniform_vs_leverage"] = out["uniform"]["fit_error"] / lev["fit_error"]
+    return out
+
+
+def oscillatory_form():
+    """Section 4.1.2 workload: 10-way 4^10 tensors of three oscillatory functions, ranks 10, the
+    paper's protocol (exact TR-ALS until the error changes by less than 1e-3, at most 100
+    sweeps; J from 2R^2 in steps of 100 until the sampled error is below 1.1x the exact one)."""
+    import torch
+    import synth
+    from paper_2010_08581_amd import protocol
+    out = {}
+    R10 = (10,) * 10
+    for name in synth.OSC_FUNCTIONS:
+        X = synth.oscillatory_tensor(name)
+        init = synth.random_cores(X.shape, R10, synth.rng_for(0, 3))
+        Xt = torch.from_numpy(X).to("cuda:0")
+        res = protocol.compare(Xt, R10, init, precision="f64", tol=1e-3, max_sweeps=100, factor=1.1,
+                               J0=200, step=100, J_max=5000)
+        out[name] = res
+        log(f"oscillatory {name}: {res}")
+        del Xt
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving_form(args):
     """Poisson stream of small decomposition requests (orders 3-5, sizes 32-256, ranks 3-12,
     J=2048, 5 sweeps, FP32, 1% noise) through the continuous-batching loop."""
@@ -134,6 +188,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16-form", action="store_true")
     ap.add_argument("--no-serving-form", action="store_true")
+    ap.add_argument("--no-method-forms", action="store_true")
+    ap.add_argument("--method-sweeps", type=int, default=10)
+    ap.add_argument("--no-oscillatory-form", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
@@ -255,6 +312,14 @@ def main():
             "contract_gather_GBps": np.mean([J * dims[n] * 2 for n in range(N)]) / (ms / max(cnt, 1) * 1e-3) / 1e9,
         }}
         log(f"bf16 form: {eb / args.steps * 1e3:.3f} ms/sweep, fit {fb:.4e}")
+    if not args.no_method_forms and J * 4 <= (1 << 24):
+        h = hb = None  # noqa: F841
+        torch.cuda.empty_cache()
+        out.setdefault("forms", {})["methods"] = method_forms(args, X, init, cfg)
+    if not args.no_oscillatory_form:
+        h = hb = None  # noqa: F841
+        torch.cuda.empty_cache()
+        out.setdefault("forms", {})["oscillatory"] = oscillatory_form()
     if not args.no_serving_form:
         h = hb = None  # noqa: F841 (releases the handles' workspaces)
         torch.cuda.empty_cache()

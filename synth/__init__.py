@@ -27,6 +27,8 @@ datasets, Section 4.1.3):
 * ``video_tensor``: H x W x C x T frames of K smooth Gaussian blobs moving on
   straight lines, plus uniform noise, clipped to [0, 1].
 * ``serving_requests``: Poisson arrivals of small decomposition requests.
+* ``oscillatory_tensor``: a highly oscillatory function sampled at 4^10 points and
+  reshaped to a 10-way 4 x ... x 4 tensor (Section 4.1.2).
 """
 from __future__ import annotations
 
@@ -42,6 +44,8 @@ __all__ = [
     "video_tensor",
     "serving_requests",
     "serving_true_cores",
+    "OSC_FUNCTIONS",
+    "oscillatory_tensor",
     "CONFIGS",
     "make_config",
 ]
@@ -170,6 +174,26 @@ def serving_requests(n_requests: int, rate: float = 200.0, seed: int = 0,
         reqs.append(dict(id=r, arrival=float(t[r]), dims=dims, ranks=ranks,
                          samples=int(samples), sweeps=int(sweeps), seed=int(seed)))
     return reqs
+
+
+# Highly oscillatory functions (Section 4.1.2) and the intervals they are sampled on.  The
+# paper gives the functions but not the grid; each is evaluated at 4^10 points
+# x_k = a + (k + 1) (b - a) / 4^10, k = 0 .. 4^10 - 1 (the left end excluded: two of the
+# functions are singular at 0), on an interval over which it oscillates many times.
+OSC_FUNCTIONS = {
+    "linear_growth": ((0.0, 1.0), lambda x: (x + 1.0) * np.sin(100.0 * (x + 1.0) ** 2)),
+    "airy": ((0.0, 100.0), lambda x: x ** -0.25 * np.sin(2.0 * x ** 1.5 / 3.0)),
+    "chirp": ((0.0, 10.0), lambda x: np.sin(4.0 / x) * np.cos(x ** 2)),
+}
+
+
+def oscillatory_tensor(name, levels=10, dtype=np.float64):
+    """The function sampled at 4^levels points, reshaped to a levels-way 4 x ... x 4 tensor in
+    C order (x's index k = sum_j i_j 4^(levels-1-j): the first mode is the coarsest scale)."""
+    (a, b), f = OSC_FUNCTIONS[name]
+    n = 4 ** levels
+    x = a + (np.arange(n, dtype=np.float64) + 1.0) * ((b - a) / n)
+    return f(x).reshape((4,) * levels).astype(dtype)
 
 
 def serving_true_cores(req, dtype=np.float64):
