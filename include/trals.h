@@ -88,6 +88,14 @@ typedef struct {
                               init_dtype; NULL draws every entry iid N(0,1) (Section 3) from the seed */
   int32_t init_dtype;      /* TRALS_F64 or TRALS_F32 */
   int32_t method;          /* trals_method; 0 (TRALS_LEVERAGE) is the paper's proposal */
+  int32_t normalize;       /* 0: the algorithms as stated.  1: after each update, core n is
+                              replaced by Q and core n+1 by R G_{n+1} (mode-1 product), where
+                              G_n = Q R is the QR factorisation of its (R[n-1] I[n]) x R[n]
+                              unfolding with R's diagonal positive (a normalisation step, which
+                              Section 2.1 allows).  TR(G) and every sampling distribution are
+                              unchanged in exact arithmetic; the core scales cannot drift apart,
+                              which keeps the sampled systems well conditioned on long runs.  A
+                              rank-deficient core then fails with TRALS_ESINGULAR after its update. */
 } trals_desc;
 
 /* Generated data source (serving): the tensor is X = TR(G*) + sigma Z with given "true" cores

@@ -75,6 +75,26 @@ def solve_core(A, B, Rp, Rn):
     return core_from_unfolding(Zt.T, Rp, Rn)
 
 
+def normalize_core(cores, n):
+    """Normalisation step after the update of core n (Section 2.1 allows such steps):
+    G_n = Q R with Q from the (R_{n-1} I_n) x R_n unfolding (Householder QR, R's diagonal made
+    positive), core n <- Q and core n+1 <- R G_{n+1} (product over its first index).  TR is
+    unchanged, and so are the leverage scores of both cores.  Returns a new list."""
+    N = len(cores)
+    Rp, I, Rn = cores[n].shape
+    Q, R = np.linalg.qr(np.asarray(cores[n], dtype=np.float64).reshape(Rp * I, Rn))
+    d = np.abs(np.diag(R))
+    if d.size and d.min() <= max(Q.shape) * np.finfo(np.float64).eps * d.max():
+        raise SingularSystem("core is rank deficient along its bond to the next core")
+    sgn = np.sign(np.diag(R))
+    Q, R = Q * sgn, sgn[:, None] * R
+    out = list(cores)
+    out[n] = Q.reshape(Rp, I, Rn)
+    nx = (n + 1) % N
+    out[nx] = np.einsum("ab,bic->aic", R, np.asarray(cores[nx], dtype=np.float64))
+    return out
+
+
 def sampled_update(X, cores, tables, n, J, seed, stream_id, u):
     """One inner iteration of Algorithm 2 for core n (update number u).
 
@@ -108,12 +128,14 @@ def lockstep_update(X, cores, n, J, seed, stream_id, u, uniform=False):
     return sampled_update(X, cores, tables, n, J, seed, stream_id, u)
 
 
-def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u0=0, uniform=False):
+def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u0=0, uniform=False,
+                   normalize=False):
     """Algorithm 2 with a fixed number of sweeps (the paper's experiments fix
     the iteration count, Section 4.1).  ``record`` (a list) receives
     (u, n, idx, w) for every update.  ``J`` may be a function of the update
     number u (the sample size can change between updates, Section 3.5).
-    ``uniform`` draws from uniform distributions instead of eq. (3).
+    ``uniform`` draws from uniform distributions instead of eq. (3);
+    ``normalize`` applies ``normalize_core`` after every update.
     Returns the list of cores."""
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
@@ -126,6 +148,8 @@ def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u
         n = u % N
         Ju = J(u) if callable(J) else J
         cores[n], idx, w = sampled_update(X, cores, tables, n, Ju, seed, stream_id, u)
+        if normalize:
+            cores = normalize_core(cores, n)
         tables[n] = table_of(cores[n], uniform)
         if record is not None:
             record.append((u, n, idx, w))
@@ -141,7 +165,7 @@ def exact_update(X, cores, n):
     return solve_core(A, B, Rp, Rn)
 
 
-def tr_als_exact(X, init_cores, sweeps):
+def tr_als_exact(X, init_cores, sweeps, normalize=False):
     """Algorithm 1 (TR-ALS) with a fixed number of sweeps.  For small tensors only."""
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
@@ -149,6 +173,8 @@ def tr_als_exact(X, init_cores, sweeps):
     for _ in range(sweeps):
         for n in range(N):
             cores[n] = exact_update(X, cores, n)
+            if normalize:
+                cores = normalize_core(cores, n)
     return cores
 
 

@@ -31,14 +31,17 @@ class TRALS:
     "f32" or "bf16".  init_cores: optional list of N tensors (any device) of
     shapes (R[n-1], I[n], R[n]); None draws N(0,1) entries on the GPU.
     method: "leverage" (Algorithm 2), "uniform" (Algorithm 2 with uniform
-    sampling) or "exact" (Algorithm 1; samples is ignored).
+    sampling) or "exact" (Algorithm 1; samples is ignored).  normalize:
+    orthonormalise each updated core along its bond to the next (QR, R moved
+    into the next core); TR(G) and the sampling are unchanged.
     """
 
     def __init__(self, X, ranks, samples, seed=0, stream_id=0, precision="f32", init_cores=None,
-                 stream=None, source=None, method="leverage"):
+                 stream=None, source=None, method="leverage", normalize=False):
         torch = _torch()
         self.lib = _lib.load()
         self.method = method
+        self.normalize = bool(normalize)
         if source is not None:
             self._init_generated(source, ranks, samples, seed, stream_id, precision, init_cores, stream)
             return
@@ -59,7 +62,7 @@ class TRALS:
                                   .to(device=X.device, dtype=torch.float64).reshape(-1) for c in init_cores])
             init_ptr = init_buf.data_ptr()
         desc, self._keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
-                                          init_ptr, init_dt, _METHOD[method])
+                                          init_ptr, init_dt, _METHOD[method], self.normalize)
         nbytes = C.c_size_t(0)
         _lib.check(self.lib.trals_workspace_bytes(C.byref(desc), C.byref(nbytes)), "trals_workspace_bytes")
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=X.device)
@@ -73,13 +76,13 @@ class TRALS:
     @classmethod
     def generated(cls, true_cores, ranks, samples, noise_rel=0.0, noise_seed=0, noise_stream=0,
                   seed=0, stream_id=0, precision="f32", init_cores=None, stream=None, device=None,
-                  method="leverage"):
+                  method="leverage", normalize=False):
         """Handle whose data is TR(true_cores) + noise, generated fiber by fiber on the GPU
         (never materialised).  true_cores: list of N arrays/tensors (R[n-1], I[n], R[n])."""
         src = dict(true_cores=true_cores, noise_rel=noise_rel, noise_seed=noise_seed,
                    noise_stream=noise_stream, device=device)
         return cls(None, ranks, samples, seed=seed, stream_id=stream_id, precision=precision,
-                   init_cores=init_cores, stream=stream, source=src, method=method)
+                   init_cores=init_cores, stream=stream, source=src, method=method, normalize=normalize)
 
     def _init_generated(self, source, ranks, samples, seed, stream_id, precision, init_cores, stream):
         torch = _torch()
@@ -102,7 +105,7 @@ class TRALS:
                                   .to(device=dev, dtype=torch.float64).reshape(-1) for c in init_cores])
             init_ptr = init_buf.data_ptr()
         desc, keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
-                                    init_ptr, TRALS_F64, _METHOD[self.method])
+                                    init_ptr, TRALS_F64, _METHOD[self.method], self.normalize)
         src, keep2 = _lib.make_source(self._true_buf.data_ptr(), TRALS_F64, true_ranks, source["noise_rel"],
                                       source["noise_seed"], source["noise_stream"])
         self._keep = (keep, keep2, init_buf)

@@ -40,6 +40,7 @@ class Desc(C.Structure):
         ("init_cores", C.c_void_p),
         ("init_dtype", C.c_int32),
         ("method", C.c_int32),
+        ("normalize", C.c_int32),
     ]
 
 
@@ -114,13 +115,13 @@ def check(code: int, what: str):
 
 
 def make_desc(dims, ranks, samples, seed=0, stream_id=0, precision=TRALS_F32, init_ptr=None,
-              init_dtype=TRALS_F64, method=TRALS_LEVERAGE):
+              init_dtype=TRALS_F64, method=TRALS_LEVERAGE, normalize=False):
     """Build a Desc plus the host arrays it points to (keep the tuple alive)."""
     N = len(dims)
     d_arr = (C.c_int64 * N)(*[int(v) for v in dims])
     r_arr = (C.c_int32 * N)(*[int(v) for v in ranks])
     desc = Desc(N, d_arr, r_arr, int(samples), int(seed), int(stream_id), int(precision),
-                C.c_void_p(init_ptr) if init_ptr else None, int(init_dtype), int(method))
+                C.c_void_p(init_ptr) if init_ptr else None, int(init_dtype), int(method), int(bool(normalize)))
     return desc, (d_arr, r_arr)
 
 

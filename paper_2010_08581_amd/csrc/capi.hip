@@ -29,7 +29,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, partial, scal, total;
+  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, gauge, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -40,6 +40,7 @@ struct Problem {
   int64_t J;     // samples per update (sampled methods); rows of the largest design (exact)
   int64_t Jcap;  // J at creation: the workspace holds up to this many samples
   int method;    // TRALS_LEVERAGE, TRALS_UNIFORM or TRALS_EXACT
+  bool normalize;  // orthonormalise each updated core along its bond to the next core
   uint64_t seed, stream_id;
   int prec;
   int sk_dt, panel_dt, ne_dt;  // cores are FP64 in every precision
@@ -92,6 +93,8 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
     p->E *= d->dims[n];
   }
   p->method = d->method;
+  if (d->normalize != 0 && d->normalize != 1) return TRALS_EINVAL;
+  p->normalize = d->normalize == 1;
   if (p->method != TRALS_LEVERAGE && p->method != TRALS_UNIFORM && p->method != TRALS_EXACT) return TRALS_EINVAL;
   p->Pmax = 0;
   p->Imax = 0;
@@ -207,8 +210,9 @@ void plan(const Problem& p, Layout* L) {
   L->Bred = take((size_t)p.Pmax * p.Imax * 8);
   L->M = take((size_t)p.Pmax * p.Pmax * 8);   // H
   L->M2 = take((size_t)p.Pmax * p.Pmax * 8);  // Gram of a core for its leverage
-  L->F = take(chol_factor_doubles(p.Pmax) * 8);
-  L->F2 = take(chol_factor_doubles(p.Pmax) * 8);
+  L->F = take(chol_work_doubles(p.Pmax) * 8);
+  L->F2 = take(chol_work_doubles(p.Pmax) * 8);
+  L->gauge = take(gauge_work_doubles() * 8);
   const int64_t fit_rows = p.generated ? 0 : p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
@@ -452,8 +456,8 @@ int run_update(trals_ctx* h) {
   double* F = h->at<double>(h->L.F);
   double* Bred = h->at<double>(h->L.Bred);  // I_n x P: row i = b_i
   PROF_BEGIN(TRALS_K_REDUCE);
-  HIPTRY(launch_reduce_parts(na.Hpart, pl.splits, (int64_t)P * P, P, 1, M, h->status(), h->stream));
-  HIPTRY(launch_reduce_parts(na.Bpart, pl.splits, (int64_t)P * In, P, 2, Bred, h->status(), h->stream));
+  HIPTRY(launch_reduce_parts(ReduceJob{na.Hpart, (int64_t)P * P, 1, M}, ReduceJob{na.Bpart, (int64_t)P * In, 2, Bred},
+                             pl.splits, P, h->status(), h->stream));
   PROF_END(TRALS_K_REDUCE);
   CholArgs ca;
   memset(&ca, 0, sizeof(ca));
@@ -474,6 +478,12 @@ int run_update(trals_ctx* h) {
   ta.status = h->status();
   PROF_BEGIN(TRALS_K_SOLVE);
   HIPTRY(launch_trisolve(ta, h->stream));
+  if (p.normalize) {
+    const int nx = (n + 1) % N;
+    HIPTRY(launch_gauge(h->at<double>(h->L.core[n]), In, p.ranks[(n + N - 1) % N], p.ranks[n],
+                        h->at<double>(h->L.core[nx]), p.dims[nx], p.ranks[nx], h->at<double>(h->L.M2),
+                        h->at<double>(h->L.gauge), h->status(), h->stream));
+  }
   PROF_END(TRALS_K_SOLVE);
   // eq. (3): the new core's sampling table
   const int rc = compute_table(h, n);

@@ -159,6 +159,7 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   __shared__ double s_tol;
   __shared__ double s_rdiag[16 * kMaxBlk];  // 1 / L_ii
   __shared__ double s_diag[16 * kLd];       // factored diagonal block of the current panel
+  __shared__ double s_lt[16 * 16];          // transpose of the diagonal block being inverted
   if (*a.status != kDevOk) return;
   const int P = a.P;
   const double* H = a.H;
@@ -210,9 +211,23 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   }
   const double tol = s_tol;
   const int l = lane & 15, grp = lane >> 4;
-  for (int K = 0; K < nblk; ++K) {
+  // W = L^{-1} is built while the factorisation proceeds.  Phase A of step K runs panel K on
+  // waves [0, triples) and, on the other waves (counted from the top), the inverse of diagonal
+  // block K-1 (wave 15, in place: slot (K-1, K-1) has no other reader after panel K-1) and the
+  // off-diagonal blocks of W's block row K-2,
+  //   W_IJ = -W_II sum_{M=J}^{I-1} L_IM W_MJ   (I = K-2, J < I),
+  // held in registers.  Phase B stores the factored diagonal block, applies the trailing update
+  // of column K and copies the block row of W into place from its staging blocks (nothing else
+  // reads row K-2 any more).  Steps nblk and nblk+1 finish the last inverse and the last two
+  // block rows.
+  constexpr int kHelpers = kCholWaves - 1;  // waves taking W block-row tasks (stride)
+  const int hw = kCholWaves - 1 - wave;     // 0: the inverse wave, 1.. : W block-row tasks
+  double* Stg = Ls + nslots * kBlk;         // nblk staging blocks for one block row of W
+  for (int K = 0; K <= nblk + 1; ++K) {
+    const bool factor = K < nblk;
     const int below = nblk - 1 - K;
-    const int triples = below == 0 ? 1 : (below + 2) / 3;  // sub-diagonal block-row triples
+    const int triples = !factor ? 0 : below == 0 ? 1 : (below + 2) / 3;  // sub-diagonal triples
+    // ---- phase A: panel K ----
     // The diagonal block stays unmodified in memory during the panel (each pass loads its own
     // copy); the factored block goes to s_diag and is stored after the panel barrier.
     for (int tri = wave; tri < triples; tri += kCholWaves) {
@@ -255,68 +270,67 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
         for (int c = 0; c < 16; ++c) src[c] = v[c];
       }
     }
-    __syncthreads();
-    if (s_fail) {
-      if (threadIdx.x == 0) *a.status = kDevSingular;
-      return;
+    // ---- phase A: inverse of diagonal block K-1, column l by lane l (forward substitution) ----
+    if (hw == 0 && K >= 1 && K <= nblk) {
+      // lane l computes column l of the inverse by forward substitution; the block is first
+      // transposed into s_lt so that column k of L is a contiguous (broadcast) read
+      const int D = K - 1;
+      double* Lb = Ls + slot(D, D) * kBlk;
+      if (lane < 16)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) s_lt[c * 16 + l] = Lb[l * kLd + c];
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = i == l ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        x[k] *= s_rdiag[16 * D + k];
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) x[i] = fma(-s_lt[k * 16 + i], x[k], x[i]);
+      }
+      if (lane < 16)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Lb[i * kLd + l] = x[i];  // W_DD (lower; zeros above)
     }
-    // factored diagonal block into place (no one reads slot (K, K) during the trailing update)
-    {
-      double* DK = Ls + slot(K, K) * kBlk;
-      for (int e = threadIdx.x; e < 16 * kLd; e += 1024) DK[e] = s_diag[e];
-    }
-    // trailing update: A_ij -= L_iK L_jK^T for K < j <= i
-    const int pairs = below * (below + 1) / 2;
-    for (int q = wave; q < pairs; q += kCholWaves) {
-      int ii, jj;
-      slot_ij(q, ii, jj);
-      const int i = K + 1 + ii, j = K + 1 + jj;
-      double* Aij = Ls + slot(i, j) * kBlk;
-      d4 acc = load_acc(Aij, lane);
-      acc = mma_abt(Ls + slot(i, K) * kBlk, Ls + slot(j, K) * kBlk, acc, lane, -1.0);
-      store_acc(Aij, acc, lane);
-    }
-    __syncthreads();
-  }
-  // inverse diagonal blocks, column l by lanes l (forward substitution in column order)
-  for (int D = wave; D < nblk; D += kCholWaves) {
-    double* Lb = Ls + slot(D, D) * kBlk;
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = i == l ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      x[k] *= s_rdiag[16 * D + k];
-#pragma unroll
-      for (int i = k + 1; i < 16; ++i) x[i] = fma(-Lb[i * kLd + k], x[k], x[i]);
-    }
-    if (lane < 16)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Lb[i * kLd + l] = x[i];  // W_DD (lower; zeros above)
-  }
-  __syncthreads();
-  // off-diagonal blocks of W, one block row at a time (rows < I are already W)
-  for (int I = 1; I < nblk; ++I) {
-    constexpr int kTasks = kMaxBlk / kCholWaves;
-    d4 res[kTasks];
-    const double* WII = Ls + slot(I, I) * kBlk;
-#pragma unroll
-    for (int t = 0; t < kTasks; ++t) {
-      const int K = wave + kCholWaves * t;
-      if (K < I) {
+    // ---- phase A: off-diagonal blocks of W's block row I = K-2 (into the staging blocks) ----
+    const int I = K - 2;
+    if (hw >= 1 && I >= 1) {
+      const double* WII = Ls + slot(I, I) * kBlk;
+      for (int J = hw - 1; J < I; J += kHelpers) {
         d4 sacc = {0.0, 0.0, 0.0, 0.0};
-        for (int J = K; J < I; ++J) sacc = mma_ab(Ls + slot(I, J) * kBlk, Ls + slot(J, K) * kBlk, sacc, lane);
+        for (int M = J; M < I; ++M) sacc = mma_ab(Ls + slot(I, M) * kBlk, Ls + slot(M, J) * kBlk, sacc, lane);
         d4 w = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) w = mfma(-WII[(lane & 15) * kLd + 4 * ks + (lane >> 4)], sacc[ks], w);
-        res[t] = w;
+        store_acc(Stg + J * kBlk, w, lane);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kTasks; ++t) {
-      const int K = wave + kCholWaves * t;
-      if (K < I) store_acc(Ls + slot(I, K) * kBlk, res[t], lane);
+    if (factor && s_fail) {
+      if (threadIdx.x == 0) *a.status = kDevSingular;
+      return;
+    }
+    // ---- phase B ----
+    if (factor) {
+      // factored diagonal block into place (no one reads slot (K, K) during the trailing update)
+      double* DK = Ls + slot(K, K) * kBlk;
+      for (int e = threadIdx.x; e < 16 * kLd; e += 1024) DK[e] = s_diag[e];
+      // trailing update: A_ij -= L_iK L_jK^T for K < j <= i
+      const int pairs = below * (below + 1) / 2;
+      for (int q = wave; q < pairs; q += kCholWaves) {
+        int ii, jj;
+        slot_ij(q, ii, jj);
+        const int i = K + 1 + ii, j = K + 1 + jj;
+        double* Aij = Ls + slot(i, j) * kBlk;
+        d4 acc = load_acc(Aij, lane);
+        acc = mma_abt(Ls + slot(i, K) * kBlk, Ls + slot(j, K) * kBlk, acc, lane, -1.0);
+        store_acc(Aij, acc, lane);
+      }
+    }
+    if (I >= 1) {
+      // blocks (I, 0 .. I-1) are contiguous slots: one flat copy
+      double* dst = Ls + slot(I, 0) * kBlk;
+      for (int e = threadIdx.x; e < I * kBlk; e += 1024) dst[e] = Stg[e];
     }
     __syncthreads();
   }
@@ -470,6 +484,8 @@ size_t chol_factor_doubles(int P) {
   return (size_t)nblk * (nblk + 1) / 2 * kBlk;
 }
 
+size_t chol_work_doubles(int P) { return chol_factor_doubles(P) + (size_t)((P + 15) / 16) * kBlk; }
+
 hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s) {
   const int nblk = (P + 15) / 16;
   if (nblk > kMaxBlk || rows < 1) return hipErrorInvalidValue;
@@ -481,7 +497,7 @@ hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
   const int nblk = (a.P + 15) / 16;
   if (nblk > kMaxBlk) return hipErrorInvalidValue;
   if (nblk <= kLdsBlocks) {
-    const size_t lds = chol_factor_doubles(a.P) * sizeof(double);
+    const size_t lds = chol_work_doubles(a.P) * sizeof(double);
     k_chol<true><<<1, 1024, lds, s>>>(a);
   } else {
     k_chol<false><<<1, 1024, 0, s>>>(a);

@@ -86,9 +86,15 @@ hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int n
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:
 // symmetrise a P x P matrix from its lower triangle; mode 2: transpose P x (count / P) to
-// (count / P) x P.
-hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int mode, double* out,
-                               const int* status, hipStream_t s);
+// (count / P) x P.  Two independent reductions share one launch.
+struct ReduceJob {
+  const double* parts;
+  int64_t count;
+  int mode;
+  double* out;
+};
+hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
+                               hipStream_t s);
 
 // K = A^T A (P x P row-major, lower blocks incl. full diagonal blocks) of an FP64 rows x P
 // row-major matrix A.
@@ -103,7 +109,8 @@ struct CholArgs {
   double* W;
   int* status;
 };
-size_t chol_factor_doubles(int P);
+size_t chol_factor_doubles(int P);  // the block-packed factor W
+size_t chol_work_doubles(int P);    // W plus the staging blocks k_chol uses (size of CholArgs.W)
 hipError_t launch_chol(const CholArgs& a, hipStream_t s);
 
 // With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
@@ -147,6 +154,12 @@ hipError_t launch_ring_inner(const Ring& ra, PerMode<const double> A, const Ring
                              double* work, double* out, hipStream_t s);
 
 // ---- leverage tables (eq. (3)) ----
+// Normalisation of core n after its update: G_n <- Q, G_{n+1} <- R G_{n+1} with G_n = Q R (the
+// (I_n R_{n-1}) x R_n unfolding, R upper with positive diagonal).  S: R x R scratch for the
+// Gram; work: gauge_work_doubles() doubles.  A singular Gram sets *status = kDevSingular.
+size_t gauge_work_doubles();
+hipError_t launch_gauge(double* core, int64_t In, int Rp, int R, double* next, int64_t In_next, int Rnext,
+                        double* S, double* work, int* status, hipStream_t s);
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s);
 hipError_t launch_scan_u64(uint64_t* Q, int In, const int* status, hipStream_t s);
 

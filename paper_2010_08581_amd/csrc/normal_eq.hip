@@ -343,13 +343,19 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
 // out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n partials are written
 // transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P).
 constexpr int kRedElems = 64;
-__global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__ parts, int nparts, int64_t count,
-                                                      int P, int mode, double* __restrict__ out,
+// Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
+__global__ __launch_bounds__(256) void k_reduce_parts(ReduceJob j0, ReduceJob j1, int64_t nb0, int nparts, int P,
                                                       const int* status) {
   __shared__ double red[4][kRedElems];
   if (*status != kDevOk) return;
+  const bool first = (int64_t)blockIdx.x < nb0;
+  const ReduceJob& jb = first ? j0 : j1;
+  const double* __restrict__ parts = jb.parts;
+  double* __restrict__ out = jb.out;
+  const int64_t count = jb.count;
+  const int mode = jb.mode;
   const int g = threadIdx.x / kRedElems, el = threadIdx.x % kRedElems;
-  const int64_t e = (int64_t)blockIdx.x * kRedElems + el;
+  const int64_t e = ((int64_t)blockIdx.x - (first ? 0 : nb0)) * kRedElems + el;
   double acc = 0.0;
   if (e < count) {
     int64_t src = e;
@@ -486,10 +492,11 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_parts(const double* parts, int nparts, int64_t count, int P, int mode, double* out,
-                               const int* status, hipStream_t s) {
-  const int64_t blocks = (count + kRedElems - 1) / kRedElems;
-  k_reduce_parts<<<(unsigned)blocks, 256, 0, s>>>(parts, nparts, count, P, mode, out, status);
+hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
+                               hipStream_t s) {
+  const int64_t na = (a.count + kRedElems - 1) / kRedElems, nb = (b.count + kRedElems - 1) / kRedElems;
+  if (na + nb == 0) return hipSuccess;
+  k_reduce_parts<<<(unsigned)(na + nb), 256, 0, s>>>(a, b, na, nparts, P, status);
   return hipGetLastError();
 }
 

@@ -113,3 +113,12 @@ def test_null_handles_of_new_entries(lib):
     assert lib.trals_sweep_until(None, 1, 0.0, None, None) == _lib.TRALS_EINVAL
     assert lib.trals_sweep_async(None, 1) == _lib.TRALS_EINVAL
     assert lib.trals_query(None) == _lib.TRALS_EINVAL
+
+
+def test_normalize_flag_validated(lib):
+    desc, keep = _lib.make_desc((20, 20, 20), (2, 2, 2), 100)
+    desc.normalize = 2
+    out = C.c_size_t(0)
+    assert lib.trals_workspace_bytes(C.byref(desc), C.byref(out)) == _lib.TRALS_EINVAL
+    desc.normalize = 1
+    assert lib.trals_workspace_bytes(C.byref(desc), C.byref(out)) == 0

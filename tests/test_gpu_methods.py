@@ -1,6 +1,6 @@
 """GPU parity of the other methods the handle runs: uniform sampling, a sample count changed
-between updates (Section 3.5), exact TR-ALS (Algorithm 1), the ring norm by transfer matrices
-and the norm-change termination (Section 3.4)."""
+between updates (Section 3.5), exact TR-ALS (Algorithm 1), the ring norm by transfer matrices,
+the norm-change termination (Section 3.4) and the optional normalisation step (Section 2.1)."""
 import numpy as np
 import pytest
 
@@ -159,3 +159,59 @@ def test_sweep_until_norm_change():
     t.sweep(1)
     if done < 40:
         assert abs(t.tr_norm() - n0) / n0 < 1e-3
+
+
+def test_normalize_fp64_lockstep_cores_n_and_next():
+    say("case: normalisation fp64 4-way 12x13x11x14 R=(2,3,4,3) J=200, lockstep 8 updates")
+    dims, ranks = (12, 13, 11, 14), (2, 3, 4, 3)
+    X = _noisy_ring(dims, ranks, 76)
+    init = random_cores(dims, ranks, rng_for(76, 3))
+    init[2] = init[2] * 300.0  # drifted scales
+    t = TR(torch.tensor(X, device="cuda"), ranks, 200, seed=3, precision="f64", init_cores=init, normalize=True)
+    N = 4
+    for u in range(8):
+        n = u % N
+        before = to_np(t.get_cores())
+        t.step(1)
+        core_o, idx_o, _ = oals.lockstep_update(X, before, n, 200, 3, 0, u)
+        idx_g, _ = t.last_samples()
+        assert np.array_equal(idx_g, idx_o), f"update {u}: indices differ"
+        want = list(before)
+        want[n] = core_o
+        want = oals.normalize_core(want, n)
+        got = to_np(t.get_cores())
+        for m in (n, (n + 1) % N):
+            r = rel(got[m], want[m])
+            assert r < 1e-9, f"update {u}, core {m}: {r:.3e}"
+        Rp, I, Rn = got[n].shape
+        Q = got[n].reshape(Rp * I, Rn)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(Rn), atol=1e-12)
+
+
+def test_normalize_exact_free_running():
+    say("case: exact TR-ALS with normalisation fp64 10x11x12 R=(3,2,4), 3 sweeps")
+    dims, ranks = (10, 11, 12), (3, 2, 4)
+    X = _noisy_ring(dims, ranks, 77)
+    init = random_cores(dims, ranks, rng_for(77, 3))
+    ref = oals.tr_als_exact(X, init, 3, normalize=True)
+    t = TR(torch.tensor(X, device="cuda"), ranks, 0, precision="f64", init_cores=init, method="exact",
+           normalize=True)
+    t.sweep(3)
+    got = to_np(t.get_cores())
+    for n in range(3):
+        assert rel(got[n], ref[n]) < 1e-8
+
+
+def test_normalize_keeps_long_oscillatory_run_solvable():
+    # without normalisation the core scales drift apart on this tensor and the sampled normal
+    # equations lose positive definiteness after ~90 updates (cond of the design ~5e8)
+    from synth import oscillatory_tensor
+    say("case: chirp 4^10 R=10 J=5000 fp64 with normalisation, 200 updates")
+    X = oscillatory_tensor("chirp")
+    init = random_cores(X.shape, (10,) * 10, rng_for(0, 3))
+    t = TR(torch.tensor(X, device="cuda"), (10,) * 10, 5000, precision="f64", init_cores=init, normalize=True)
+    t.step(200)
+    fit = t.fit_error()
+    norms = [float(np.linalg.norm(c)) for c in to_np(t.get_cores())]
+    say(f"fit {fit:.4e}, core norms {min(norms):.2e} .. {max(norms):.2e}")
+    assert np.isfinite(fit) and fit < 0.2

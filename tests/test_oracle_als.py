@@ -188,3 +188,40 @@ def test_sample_count_may_change_between_updates():
     als.tr_als_sampled(X, init, 50, 1, seed=0, record=rec2)
     for a, b in zip(rec[:3], rec2):
         assert np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("n", [0, 1, 3])
+def test_normalize_core_is_a_gauge_change(n):
+    # QR with positive diagonal: Q orthonormal, R upper, TR and both cores' leverage unchanged
+    from oracle.leverage import leverage_scores
+    dims, ranks = (5, 6, 4, 7), (2, 3, 4, 2)
+    cores = random_cores(dims, ranks, rng_for(61, n))
+    cores[n] = cores[n] * 1e3  # scales drifted apart
+    out = als.normalize_core(cores, n)
+    Rp, I, Rn = cores[n].shape
+    Q = out[n].reshape(Rp * I, Rn)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(Rn), atol=1e-13)
+    T0, T1 = ring.tr_full(cores), ring.tr_full(out)
+    assert np.linalg.norm(T1 - T0) <= 1e-12 * np.linalg.norm(T0)
+    nx = (n + 1) % 4
+    for m in (n, nx):
+        a, _ = leverage_scores(ring.core_unfolding(cores[m]))
+        b, _ = leverage_scores(ring.core_unfolding(out[m]))
+        np.testing.assert_allclose(b, a, atol=1e-12)
+    # R = Q^T G_n is upper triangular with a positive diagonal
+    R = Q.T @ cores[n].reshape(Rp * I, Rn)
+    assert np.all(np.diag(R) > 0) and np.allclose(np.tril(R, -1), 0, atol=1e-9 * np.abs(R).max())
+
+
+def test_normalized_als_follows_the_same_iterates():
+    # a gauge change leaves the LS optimum, the draws and hence TR(G) after every update unchanged
+    dims, ranks = (18, 20, 22), (2, 3, 2)
+    X = rng_for(62, 0).standard_normal(dims)
+    init = random_cores(dims, ranks, rng_for(62, 3))
+    a = als.tr_als_sampled(X, init, 120, 3, seed=1)
+    b = als.tr_als_sampled(X, init, 120, 3, seed=1, normalize=True)
+    Ta, Tb = ring.tr_full(a), ring.tr_full(b)
+    assert np.linalg.norm(Ta - Tb) <= 1e-9 * np.linalg.norm(Ta)
+    e = als.tr_als_exact(X, init, 2)
+    f = als.tr_als_exact(X, init, 2, normalize=True)
+    assert np.linalg.norm(ring.tr_full(e) - ring.tr_full(f)) <= 1e-9 * np.linalg.norm(ring.tr_full(e))
