@@ -125,7 +125,9 @@ def method_forms(args, X, init, cfg):
 def oscillatory_form():
     """Section 4.1.2 workload: 10-way 4^10 tensors of three oscillatory functions, ranks 10, the
     paper's protocol (exact TR-ALS until the error changes by less than 1e-3, at most 100
-    sweeps; J from 2R^2 in steps of 100 until the sampled error is below 1.1x the exact one)."""
+    sweeps; J from 2R^2 in steps of 100 until the sampled error is below 1.1x the exact one),
+    both methods with the normalisation step (these runs are long enough for the unnormalised
+    core scales to drift apart)."""
     import torch
     import synth
     from paper_2010_08581_amd import protocol
@@ -136,7 +138,7 @@ def oscillatory_form():
         init = synth.random_cores(X.shape, R10, synth.rng_for(0, 3))
         Xt = torch.from_numpy(X).to("cuda:0")
         res = protocol.compare(Xt, R10, init, precision="f64", tol=1e-3, max_sweeps=100, factor=1.1,
-                               J0=200, step=100, J_max=5000)
+                               J0=200, step=100, J_max=100000, normalize=True)
         out[name] = res
         log(f"oscillatory {name}: {res}")
         del Xt

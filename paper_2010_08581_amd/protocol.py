@@ -5,14 +5,17 @@ supplement's experiment details), run on the GPU.
    error changes by less than ``tol`` of its value between two sweeps (|e_k - e_{k-1}| < tol
    e_k), or ``max_sweeps`` sweeps have run.  The sweep count S and the final error E fix the
    reference.
-2. Sampled TR-ALS (Algorithm 2) from the same initial cores for S sweeps, with J starting at
-   ``J0`` and increased by ``step`` until its error is below ``factor`` * E.  A J whose sampled
-   system turns out rank deficient (too few rows for the design's coherence) counts as not
-   reaching the target.
+2. Sampled TR-ALS (Algorithm 2) from the same initial cores for S sweeps: the smallest J on the
+   grid J0, J0 + step, ... (at most J_max) whose error is below ``factor`` * E.  A J whose
+   sampled system turns out rank deficient (too few rows for the design's coherence) counts as
+   not reaching the target.  The paper walks the grid upwards one step at a time; here the grid
+   is searched by doubling and then bisection, which finds the same J when the error decreases
+   with J and needs far fewer runs.
 3. Both are timed over their S sweeps (fit evaluations excluded); the speedup is the ratio.
 
 Everything runs through the library's handles; the sampled runs reuse one handle (the sample
-count, cores and update counter are reset between candidates).
+count, cores and update counter are reset between candidates).  ``normalize`` applies the
+optional normalisation step to both methods.
 """
 from __future__ import annotations
 
@@ -31,9 +34,9 @@ def _timed_sweeps(h, sweeps):
     return time.perf_counter() - t0
 
 
-def exact_reference(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=100):
+def exact_reference(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=100, normalize=False):
     """(sweeps S, error E, seconds of the S sweeps) of exact TR-ALS."""
-    h = TRALS(X, ranks, 0, precision=precision, init_cores=init_cores, method="exact")
+    h = TRALS(X, ranks, 0, precision=precision, init_cores=init_cores, method="exact", normalize=normalize)
     prev = h.fit_error()
     secs = 0.0
     for s in range(1, max_sweeps + 1):
@@ -47,47 +50,68 @@ def exact_reference(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=
 
 
 def find_sample_size(X, ranks, init_cores, sweeps, target, J0, step, J_max, precision="f64", seed=0,
-                     method="leverage"):
-    """Smallest J = J0 + k * step (<= J_max) whose S-sweep error is below target.
+                     method="leverage", normalize=False):
+    """Smallest J = J0 + k * step (<= J_max) whose S-sweep error is below target (doubling,
+    then bisection on the grid).
 
-    Returns (J, error, seconds of the S sweeps), or (None, best error, None) if no J up to
-    J_max reaches the target."""
-    h = TRALS(X, ranks, J_max, seed=seed, precision=precision, init_cores=init_cores, method=method)
-    best = float("inf")
-    J = J0
-    try:
-        while J <= J_max:
+    Returns (J, error, seconds of the S sweeps, runs), or (None, best error, None, runs) if no
+    J up to J_max reaches the target."""
+    h = TRALS(X, ranks, J_max, seed=seed, precision=precision, init_cores=init_cores, method=method,
+              normalize=normalize)
+    tried = {}
+
+    def run(J):
+        if J not in tried:
             h.update_counter = 0  # first: the tables of modes 1..N-1 are then rebuilt
             h.set_cores(init_cores)
             h.set_samples(J)
             try:
                 secs = _timed_sweeps(h, sweeps)
+                tried[J] = (h.fit_error(), secs)
             except TralsError as err:
                 if err.code != TRALS_ESINGULAR:
                     raise
-                J += step  # rank-deficient sample; set_cores clears the failed state
-                continue
-            e = h.fit_error()
-            best = min(best, e)
-            if e < target:
-                return J, e, secs
-            J += step
-        return None, best, None
+                tried[J] = (float("inf"), None)  # rank-deficient sample; set_cores clears the state
+        return tried[J]
+
+    try:
+        k_lo, k = -1, 0  # grid index k <-> J0 + k * step; k_lo: largest index known to fail
+        k_max = (J_max - J0) // step
+        while True:
+            if run(J0 + k * step)[0] < target:
+                break
+            k_lo = k
+            if k == k_max:
+                best = min(e for e, _ in tried.values())
+                return None, best, None, len(tried)
+            k = min(2 * k + 1, k_max)
+        k_hi = k
+        while k_hi - k_lo > 1:
+            mid = (k_lo + k_hi) // 2
+            if run(J0 + mid * step)[0] < target:
+                k_hi = mid
+            else:
+                k_lo = mid
+        J = J0 + k_hi * step
+        e, secs = tried[J]
+        return J, e, secs, len(tried)
     finally:
         h.close()
 
 
 def compare(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=100, factor=1.1, J0=None, step=100,
-            J_max=None, seed=0, method="leverage"):
+            J_max=None, seed=0, method="leverage", normalize=False):
     """The full protocol; returns a dict of the reference, the J found and the speedup."""
     N = len(ranks)
     P = max(ranks[(n - 1) % N] * ranks[n] for n in range(N))
     J0 = 2 * P if J0 is None else J0
     J_max = 100 * P if J_max is None else J_max
-    S, E, t_ex = exact_reference(X, ranks, init_cores, precision, tol, max_sweeps)
-    J, e, t_s = find_sample_size(X, ranks, init_cores, S, factor * E, J0, step, J_max, precision, seed, method)
+    S, E, t_ex = exact_reference(X, ranks, init_cores, precision, tol, max_sweeps, normalize)
+    J, e, t_s, runs = find_sample_size(X, ranks, init_cores, S, factor * E, J0, step, J_max, precision, seed,
+                                       method, normalize)
     return {
         "sweeps": S, "exact_error": E, "exact_s": t_ex,
         "samples": J, "sampled_error": e, "sampled_s": t_s,
-        "speedup": (t_ex / t_s) if t_s else None, "factor": factor,
+        "speedup": (t_ex / t_s) if t_s else None, "factor": factor, "J_max": J_max, "runs": runs,
+        "normalize": bool(normalize),
     }
