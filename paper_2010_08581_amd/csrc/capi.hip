@@ -130,7 +130,9 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   p->prec = d->precision;
   // storage of the sketch (FP64 or FP32) and of the data panels (FP64, FP32 or BF16), and the
   // arithmetic of the normal-equation products; the cores (tiny) are FP64 throughout
-  p->sk_dt = p->prec == TRALS_F64 ? 0 : 1;
+  // sketch: FP64 rows, FP32 rows, or (BF16 form) two transposed BF16 copies of the same size as
+  // the FP32 rows
+  p->sk_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
   p->sk_sz = p->sk_dt == 0 ? 8 : 4;
   p->panel_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
   p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
@@ -383,6 +385,10 @@ int run_update(trals_ctx* h) {
   da.idx = h->at<int32_t>(h->L.idx);
   da.w = h->at<double>(h->L.w);
   da.A = h->at<void>(h->L.A);
+  if (p.sk_dt == 2) {
+    da.ldt = (Jn + 63) / 64 * 64;
+    da.A2 = h->at<char>(h->L.A) + (size_t)P * da.ldt * 2;
+  }
   da.status = h->status();
   da.weights = p.tables_as_weights ? 1 : 0;
   da.draw = exact ? 0 : 1;
@@ -428,6 +434,8 @@ int run_update(trals_ctx* h) {
   NormalEqArgs na;
   memset(&na, 0, sizeof(na));
   na.A = da.A;
+  na.A2 = da.A2;
+  na.ld = da.ldt;
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
   // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the
   // panel's rows: row r of the sketch pairs with fiber row r

@@ -25,6 +25,8 @@
 // then thread (s, b) carries row b of M_s through the chain, the slices of all jb samples
 // staged in LDS (loads batched, one round trip per eight per thread), and the finished rows
 // leave through LDS as one contiguous store.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace trals {
@@ -219,17 +221,41 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   const int Rp = rin;
   const int P = Rn * Rp;
   __syncthreads();
-  TA* out = (TA*)S;  // jb x P staging (jb * P <= 256 * RM < jb * kSlice doubles)
-  if (live) {
-    const double w = s_w[sj];
-#pragma unroll
-    for (int c = 0; c < RM; ++c)
-      if (c < Rp) out[sj * P + c * Rn + b] = (TA)(w * row[c]);
-  }
-  __syncthreads();
   const int64_t rows = a.J - j0 < jb ? a.J - j0 : jb;
-  TA* A = (TA*)a.A + j0 * P;
-  for (int64_t e = tid; e < rows * P; e += kThreads) A[e] = out[e];
+  if constexpr (std::is_same<TA, __bf16>::value) {
+    // BF16 pair, transposed: column col = c R_n + b holds its jb samples contiguously
+    __bf16* o1 = (__bf16*)S;  // P x jb each (2 P jb bf16 <= jb * kSlice doubles)
+    __bf16* o2 = o1 + P * jb;
+    if (live) {
+      const double w = s_w[sj];
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < Rp) {
+          const int col = c * Rn + b;
+          o1[col * jb + sj] = (__bf16)(w * row[c]);
+          o2[col * jb + sj] = (__bf16)(w * (w * row[c]));
+        }
+    }
+    __syncthreads();
+    __bf16* T1 = (__bf16*)a.A + j0;
+    __bf16* T2 = (__bf16*)a.A2 + j0;
+    for (int64_t e = tid; e < rows * P; e += kThreads) {
+      const int col = (int)(e / rows), q = (int)(e - (int64_t)col * rows);
+      T1[col * a.ldt + q] = o1[col * jb + q];
+      T2[col * a.ldt + q] = o2[col * jb + q];
+    }
+  } else {
+    TA* out = (TA*)S;  // jb x P staging (jb * P <= 256 * RM < jb * kSlice doubles)
+    if (live) {
+      const double w = s_w[sj];
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < Rp) out[sj * P + c * Rn + b] = (TA)(w * row[c]);
+    }
+    __syncthreads();
+    TA* A = (TA*)a.A + j0 * P;
+    for (int64_t e = tid; e < rows * P; e += kThreads) A[e] = out[e];
+  }
 }
 
 template <typename TA>
@@ -267,6 +293,10 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
 hipError_t launch_draw(const DrawArgs& a, int sketch_dtype, hipStream_t s) {
   if (sketch_dtype == 0) return draw_dispatch<double>(a, s);
   if (sketch_dtype == 1) return draw_dispatch<float>(a, s);
+  if (sketch_dtype == 2) {
+    if (!a.A2 || a.ldt < a.J || a.ldt % 64) return hipErrorInvalidValue;
+    return draw_dispatch<__bf16>(a, s);
+  }
   return hipErrorInvalidValue;
 }
 

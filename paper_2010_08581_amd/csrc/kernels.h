@@ -34,7 +34,10 @@ struct DrawArgs {
   PerMode<const double> cores;  // slice-major FP64 cores
   int32_t* idx;
   double* w;
-  void* A;                      // sketch type: FP64 (0) or FP32 (1)
+  void* A;                      // sketch type: FP64 (0) or FP32 (1): J x P rows; BF16 pair (2):
+                                // bf16(w M) transposed, P x ldt (samples contiguous per column)
+  void* A2;                     // BF16 pair only: bf16(w^2 M), same layout
+  int64_t ldt;                  // BF16 pair only: row length (a multiple of 64 samples)
   const int* status;
   int weights;                  // 1: cdf holds the weights Q (scanned in LDS); 0: inclusive sums C
   int draw;                     // 1: draw the samples; 0: take idx as given, rows without weights
@@ -51,7 +54,9 @@ hipError_t launch_draw(const DrawArgs& a, int sketch_dtype, hipStream_t s);
 
 // Fused normal equations [H | B] = A^T [A | X~] on matrix cores (split-K partials).
 struct NormalEqArgs {
-  const void* A;              // J x P sketched rows (compute type)
+  const void* A;              // J x P sketched rows (compute type); BF16: bf16(w M), P x ld
+  const void* A2;             // BF16 only: bf16(w^2 M), P x ld
+  int64_t ld;                 // BF16 only: row length of A, A2 (a multiple of 64)
   const void* panel;          // mode-n panel (compute type)
   const int32_t* idx;         // J x (N-1)
   const double* w;

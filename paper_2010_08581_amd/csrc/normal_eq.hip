@@ -202,29 +202,24 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   }
 }
 
-// BF16 form of the same products on v_mfma_f32_16x16x32_bf16: operands rounded to BF16
-// (round to nearest even), products accumulated in FP32 within a sample chunk, partial tiles
-// written in FP64.  Gram tiles use bf16(A) on both sides; data tiles use bf16(w_j A_j) against
-// the raw BF16 panel rows (w_j folded into the sketch side, so the gathered fibers feed the
-// matrix cores unmodified).  LDS tiles are stored k-major ([column][sample]) so that each lane
-// reads its 8 consecutive k values of an operand with one 16-byte load.
+// BF16 form of the same products on v_mfma_f32_16x16x32_bf16.  The draw kernel writes the sketch
+// twice in BF16 and transposed (column c's samples contiguous): bf16(w_j M_j) for the Gram tiles
+// and bf16(w_j^2 M_j) for the data tiles, so that B = sum_j w_j^2 M_j^T x_j meets the raw BF16
+// panel rows (x~_j = w_j x_j, Definition 5) unmodified.  Products are accumulated in FP32 within
+// a split and the partial tiles written in FP64.  Each lane feeds the matrix cores 8 consecutive
+// samples of one operand row: a 16-byte load from a transposed sketch, or, for the data side, 8
+// gathered 2-byte panel entries (16 lanes read 32 contiguous bytes of each fiber).  No operand
+// passes through LDS.
 //   v_mfma_f32_16x16x32_bf16 layouts: A(i, k) at lane i + 16 (k / 8), element k % 8;
 //   B(k, j) at lane j + 16 (k / 8), element k % 8; D(i, j) at lane j + 16 (i / 4), register i % 4.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int kKB16 = 64;  // sample rows per stage (two MFMA k-steps of 32)
-constexpr int kPadK = 8;   // k padding of the LDS rows (bf16 elements)
+constexpr int kKB16 = 64;  // sample rows per split quantum (two MFMA k-steps of 32)
 
 template <int MB>
 __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
-  constexpr int LK = kKB16 + kPadK;
-  constexpr int NA = (kKB16 * RT + 255) / 256;
-  constexpr int NB = (kKB16 * kColTile + 255) / 256;
-  __shared__ __bf16 As[2][RT][LK];
-  __shared__ __bf16 Bs[2][kColTile][LK];
   __shared__ int64_t s_roff[kMaxChunk];
-  __shared__ float s_w[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
   const int s = blockIdx.x / a.tiles, t = blockIdx.x - s * a.tiles;
@@ -233,96 +228,85 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   const bool gram = ct < a.gram_tiles;
   const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
   if (gram && col0 >= row0 + RT) return;
-  const int64_t r0 = (int64_t)s * a.chunk;
+  const int64_t r0 = (int64_t)s * a.chunk;  // a multiple of kKB16
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
   const int nrows = (int)(r1 - r0);
-  const float* A = (const float*)a.A;
-  const __bf16* X = (const __bf16*)a.panel;
+  const int npad = (nrows + kKB16 - 1) / kKB16 * kKB16;  // r0 + npad <= ld
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t ld = a.ld;
+  const __bf16* X = (const __bf16*)a.panel;
   if (!gram) {
-    for (int r = threadIdx.x; r < nrows; r += 256) {
-      int64_t off = 0;
-      if (a.direct) {
-        off = r0 + r;
-      } else {
-        const int32_t* ij = a.idx + (r0 + r) * a.K;
-        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+    for (int r = threadIdx.x; r < npad; r += 256) {
+      int64_t off = 0;  // rows past the split read fiber row 0 (their sketch factor is zero)
+      if (r < nrows) {
+        if (a.direct) {
+          off = r0 + r;
+        } else {
+          const int32_t* ij = a.idx + (r0 + r) * a.K;
+          for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+        }
       }
       s_roff[r] = off * In;
-      s_w[r] = (float)a.w[r0 + r];
     }
     __syncthreads();
   }
-  float ra[NA];
-  __bf16 rb[NB];
-  auto load_stage = [&](int base) {
+  // operand rows of this lane (clamped: rows and columns past P or I_n are computed, not stored)
+  const __bf16* SA = (const __bf16*)(gram ? a.A : a.A2) + r0;
+  const __bf16* arow[MB];
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int r = e / RT, c = e % RT;
-      float v = 0.f;
-      if (e < kKB16 * RT && base + r < nrows && row0 + c < P) {
-        v = A[(r0 + base + r) * P + row0 + c];
-        if (!gram) v *= s_w[base + r];
-      }
-      ra[q] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int r = e / kColTile, c = e % kColTile;
-      __bf16 v = (__bf16)0.f;
-      if (base + r < nrows) {
-        if (gram) {
-          if (col0 + c < P) v = (__bf16)A[(r0 + base + r) * P + col0 + c];
-        } else {
-          if (col0 + c < In) v = X[s_roff[base + r] + col0 + c];
-        }
-      }
-      rb[q] = v;
-    }
-  };
-  auto store_stage = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      if (e < kKB16 * RT) As[buf][e % RT][e / RT] = (__bf16)ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      Bs[buf][e % kColTile][e / kColTile] = rb[q];
-    }
-  };
+  for (int m = 0; m < MB; ++m) {
+    const int rr = row0 + 16 * m + li;
+    arow[m] = SA + (int64_t)(rr < P ? rr : P - 1) * ld;
+  }
+  const int bc = col0 + 16 * wave + li;
+  const __bf16* brow = (const __bf16*)a.A + r0 + (int64_t)(bc < P ? bc : P - 1) * ld;  // Gram side
+  const int bcol = bc < In ? bc : In - 1;                                                // data side
   f4 acc[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
-  const int stages = (nrows + kKB16 - 1) / kKB16;
-  load_stage(0);
-  for (int t = 0; t < stages; ++t) {
-    const int buf = t & 1;
-    store_stage(buf);
-    __syncthreads();
-    if (t + 1 < stages) load_stage((t + 1) * kKB16);
+  // one k-step = 32 samples; the operands of the next step are loaded while the matrix cores
+  // work on the current one (two register buffers, npad / 32 is even)
+  auto load = [&](int base, bf8(&av)[MB], bf8& bv) {
+    const int k0 = base + 8 * lg;  // this lane's 8 samples
 #pragma unroll
-    for (int ks = 0; ks < kKB16 / 32; ++ks) {
-      const int k0 = ks * 32 + 8 * (lane >> 4);
-      const bf8 b = *(const bf8*)&Bs[buf][wave * 16 + (lane & 15)][k0];
+    for (int m = 0; m < MB; ++m) av[m] = *(const bf8*)(arow[m] + k0);
+    if (gram) {
+      bv = *(const bf8*)(brow + k0);
+    } else {
 #pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const bf8 av = *(const bf8*)&As[buf][m * 16 + (lane & 15)][k0];
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[m], 0, 0, 0);
-      }
+      for (int e = 0; e < 8; ++e) bv[e] = X[s_roff[k0 + e] + bcol];
     }
+  };
+  auto step = [&](int base, bf8(&av)[MB], const bf8& bv) {
+    if (base + 32 > nrows) {
+      // samples past the split: their sketch entries may hold an earlier, longer update's rows
+      const int k0 = base + 8 * lg;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (k0 + e >= nrows)
+#pragma unroll
+          for (int m = 0; m < MB; ++m) av[m][e] = (__bf16)0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m], 0, 0, 0);
+  };
+  bf8 a0[MB], a1[MB], b0, b1;
+  load(0, a0, b0);
+  for (int base = 0; base < npad; base += 64) {
+    load(base + 32, a1, b1);
+    step(base, a0, b0);
+    if (base + 64 < npad) load(base + 64, a0, b0);
+    step(base + 32, a1, b1);
   }
-  const int col = col0 + wave * 16 + (lane & 15);
+  const int col = col0 + wave * 16 + li;
   if (gram) {
     double* H = a.Hpart + (int64_t)s * P * P;
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * (lane >> 4) + r;
+        const int row = row0 + m * 16 + 4 * lg + r;
         if (row < P && col < P && col <= row) H[(int64_t)row * P + col] = (double)acc[m][r];
       }
   } else {
@@ -331,7 +315,7 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * (lane >> 4) + r;
+        const int row = row0 + m * 16 + 4 * lg + r;
         if (row < P && col < In) B[(int64_t)row * In + col] = (double)acc[m][r];
       }
   }
@@ -432,7 +416,7 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   // workgroups resident per CU (LDS-bound) and the rows one split must be a multiple of
   int per_cu, quantum;
   if (ne_dtype == 2) {
-    per_cu = 2;
+    per_cu = 2;  // register bound (196 of 512 registers per lane: two waves per SIMD)
     quantum = kKB16;
   } else {
     const int kg = ne_dtype == 1 ? 2 : 1;
@@ -451,7 +435,9 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   if (S < 1) S = 1;
   const int64_t maxchunk = kMaxChunk - quantum;
   if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
-  const int64_t chunk = (J + S - 1) / S;
+  int64_t chunk = (J + S - 1) / S;
+  // the BF16 form reads its transposed sketch in 16-byte groups: splits start on a quantum
+  if (ne_dtype == 2) chunk = (chunk + quantum - 1) / quantum * quantum;
   pl.chunk = chunk;
   pl.splits = (int)((J + chunk - 1) / chunk);
   return pl;

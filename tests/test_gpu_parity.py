@@ -172,3 +172,23 @@ def test_c2_full_size_lockstep():
     del X
     worst = lockstep(t, X64, 3, 8192)
     say(f"c2 worst core rel diff {worst:.3e}")
+
+
+def test_c3_full_size_lockstep():
+    say("case: c3 full size 40^5 R=5 J=4096 fp32 lockstep 5 updates")
+    X, _, init = make_config("c3", dtype=np.float32)
+    t = TR(torch.tensor(X, device="cuda"), (5,) * 5, 4096, precision="f32", init_cores=init)
+    X64 = X.astype(np.float64)
+    del X
+    worst = lockstep(t, X64, 5, 4096)
+    say(f"c3 worst core rel diff {worst:.3e}")
+
+
+def test_c4_full_size_video_lockstep():
+    # 240x320x3x2000 video-shaped tensor, ranks 20 (P = 400), J = 16384: one update per mode
+    say("case: c4 full size video 240x320x3x2000 R=20 J=16384 fp32 lockstep 4 updates")
+    X = video_tensor()
+    init = random_cores(X.shape, (20,) * 4, rng_for(0, 3))
+    t = TR(torch.tensor(X, device="cuda"), (20,) * 4, 16384, precision="f32", init_cores=init)
+    worst = lockstep(t, X, 4, 16384)
+    say(f"c4 worst core rel diff {worst:.3e}")
