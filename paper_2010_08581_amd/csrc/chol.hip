@@ -152,7 +152,12 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
 // apply the trailing update A_ij -= L_iK L_jK^T on matrix cores.  Afterwards the diagonal
 // blocks are inverted (forward substitution per column) and W = L^{-1} is completed block
 // row by block row: W_IK = -W_II sum_{J=K}^{I-1} L_IJ W_JK.
-template <bool kInLds>
+//
+// kRegion = false: the whole P x P matrix (row-major H) in LDS, W to a.W.
+// kRegion = true: the diagonal region of a.nb blocks starting at block a.b0 of the block-packed
+// work matrix a.Lg (the large-P path below), tolerance from a.scal[0]; its inverse goes to the
+// same blocks of a.W.
+template <bool kRegion>
 __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_fail;
@@ -164,13 +169,20 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   const int P = a.P;
   const double* H = a.H;
   double* Wg = a.W;
-  const int nblk = (P + 15) / 16;
+  const int g0 = kRegion ? a.b0 : 0;  // global block index of local block 0
+  const int nblk = kRegion ? a.nb : (P + 15) / 16;
   const int nslots = nblk * (nblk + 1) / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* Ls = kInLds ? lds : Wg;
-  // stage the lower blocks (full diagonal blocks; identity on the padded diagonal), eight
-  // loads in flight per thread
-  {
+  double* Ls = lds;
+  if (kRegion) {
+    for (int e = threadIdx.x; e < nslots * kBlk; e += 1024) {
+      int bi, bj;
+      slot_ij(e / kBlk, bi, bj);
+      Ls[e] = a.Lg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk];
+    }
+  } else {
+    // stage the lower blocks (full diagonal blocks; identity on the padded diagonal), eight
+    // loads in flight per thread
     const int cnt = nslots * 256;
     constexpr int kB = 8;
     for (int base = 0; base < cnt; base += kB * 1024) {
@@ -194,7 +206,12 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
     }
   }
   __syncthreads();
-  if (wave == 0) {
+  if (kRegion) {
+    if (threadIdx.x == 0) {
+      s_tol = a.scal[0];
+      s_fail = 0;
+    }
+  } else if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < P; i += 64) mx = fmax(mx, Ls[slot(i >> 4, i >> 4) * kBlk + (i & 15) * kLd + (i & 15)]);
 #pragma unroll
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
         // rows past P are padding (unit pivots), outside the tolerance test: it is relative to
         // the largest diagonal entry and can exceed 1.  Bitwise flags: no branch per pivot.
         const int ok = (int)(pk > tol) & (int)(pk < __builtin_huge_val());
-        bad |= (int)(16 * K + k < P) & (ok ^ 1);
+        bad |= (int)(16 * (g0 + K) + k < P) & (ok ^ 1);
         const double il = rsqrt_f64(fmax(pk, 1e-300));
         const double t = v[k] * (il * il);
 #pragma unroll
@@ -334,7 +351,126 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
     }
     __syncthreads();
   }
-  if (kInLds) copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, 1024);
+  if (kRegion) {
+    for (int e = threadIdx.x; e < nslots * kBlk; e += 1024) {
+      int bi, bj;
+      slot_ij(e / kBlk, bi, bj);
+      Wg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk] = Ls[e];
+    }
+  } else {
+    copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, 1024);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Large P (more blocks than LDS holds): blocked over 64-column block columns (4 blocks), each
+// step spread over many workgroups.  The block-packed work matrix Lg holds H, then L; W holds
+// the inverse factor.  Step K: (1) k_chol<true> factors and inverts the diagonal region
+// (W_KK); (2) the panel below it, L_iK = A_iK W_KK^T; (3) the trailing update A_ij -= L_iK
+// L_jK^T.  Then the block rows of W follow one 64-row band at a time:
+// W_IJ = -W_II sum_{M=J}^{I-1} L_IM W_MJ.
+
+// Lg <- H in blocks (identity on the padded diagonal); scal[0] <- P eps max_i H_ii
+__global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, int P, double* __restrict__ Lg,
+                                                  double* scal, int* status) {
+  if (*status != kDevOk) return;
+  const int nblk = (P + 15) / 16;
+  const int64_t total = (int64_t)nblk * (nblk + 1) / 2 * kBlk;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int bi, bj;
+    slot_ij((int)(e / kBlk), bi, bj);
+    const int rc = (int)(e % kBlk), r = rc / kLd, c = rc % kLd;
+    const int i = 16 * bi + r, j = 16 * bj + c;
+    double v = 0.0;
+    if (c < 16) v = (i < P && j < P) ? H[(int64_t)i * P + j] : (i == j ? 1.0 : 0.0);
+    Lg[e] = v;
+  }
+  if (blockIdx.x == 0) {
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < P; i += 256) mx = fmax(mx, H[(int64_t)i * P + i]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      mx = red[0];
+      scal[0] = (double)P * 2.220446049250313e-16 * mx;
+      if (!(mx > 0.0) || !isfinite(mx)) *status = kDevSingular;
+    }
+  }
+}
+
+// one wave per block row i >= b0 + nb: L(i, b0 + q) = sum_{c <= q} A(i, b0 + c) W(b0 + q, b0 + c)^T
+__global__ __launch_bounds__(256) void k_big_panel(double* __restrict__ Lg, const double* __restrict__ W, int nblk,
+                                                   int b0, int nb, const int* status) {
+  if (*status != kDevOk) return;
+  const int lane = threadIdx.x & 63;
+  const int i = b0 + nb + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (i >= nblk) return;
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    if (q < nb)
+      for (int c = 0; c <= q; ++c)
+        acc[q] = mma_abt(Lg + (int64_t)slot(i, b0 + c) * kBlk, W + (int64_t)slot(b0 + q, b0 + c) * kBlk, acc[q],
+                         lane, 1.0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q < nb) store_acc(Lg + (int64_t)slot(i, b0 + q) * kBlk, acc[q], lane);
+}
+
+// one wave per trailing block (i, j), b0 + nb <= j <= i: A_ij -= sum_q L(i, b0 + q) L(j, b0 + q)^T
+__global__ __launch_bounds__(256) void k_big_trail(double* __restrict__ Lg, int nblk, int b0, int nb,
+                                                   const int* status) {
+  if (*status != kDevOk) return;
+  const int lane = threadIdx.x & 63;
+  const int q = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int t0 = b0 + nb, rem = nblk - t0;
+  if (q >= rem * (rem + 1) / 2) return;
+  int ii, jj;
+  slot_ij(q, ii, jj);
+  const int i = t0 + ii, j = t0 + jj;
+  double* Aij = Lg + (int64_t)slot(i, j) * kBlk;
+  d4 acc = load_acc(Aij, lane);
+  for (int c = 0; c < nb; ++c)
+    acc = mma_abt(Lg + (int64_t)slot(i, b0 + c) * kBlk, Lg + (int64_t)slot(j, b0 + c) * kBlk, acc, lane, -1.0);
+  store_acc(Aij, acc, lane);
+}
+
+// band I (blocks 4I .. 4I + nbI - 1), one workgroup per band J < I: 16 waves, wave (r, c) the
+// output block (4I + r, 4J + c)
+__global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg, double* __restrict__ W, int nblk,
+                                                   int I, const int* status) {
+  __shared__ double stage[16][16 * kLd];
+  if (*status != kDevOk) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int J = blockIdx.x;
+  const int r = wave >> 2, c = wave & 3;
+  const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
+  const int bi = 4 * I + r, bj = 4 * J + c;
+  d4 sacc = {0.0, 0.0, 0.0, 0.0};
+  if (r < nbI) {
+    for (int M = J; M < I; ++M)
+      for (int m = 0; m < 4; ++m) {
+        const int bm = 4 * M + m;
+        if (bm < bj) continue;  // W(bm, bj) is zero above the diagonal
+        sacc = mma_ab(Lg + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
+      }
+  }
+  store_acc(stage[wave], sacc, lane);
+  __syncthreads();
+  if (r >= nbI) return;
+  d4 w = {0.0, 0.0, 0.0, 0.0};
+  for (int r2 = 0; r2 <= r; ++r2)
+    w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage[4 * r2 + c], w, lane);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = -w[q];
+  store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -484,7 +620,11 @@ size_t chol_factor_doubles(int P) {
   return (size_t)nblk * (nblk + 1) / 2 * kBlk;
 }
 
-size_t chol_work_doubles(int P) { return chol_factor_doubles(P) + (size_t)((P + 15) / 16) * kBlk; }
+size_t chol_work_doubles(int P) {
+  const int nblk = (P + 15) / 16;
+  if (nblk <= kLdsBlocks) return chol_factor_doubles(P) + (size_t)nblk * kBlk;  // W + staging blocks
+  return 2 * chol_factor_doubles(P) + 8;                                        // W, work matrix, tolerance
+}
 
 hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s) {
   const int nblk = (P + 15) / 16;
@@ -493,15 +633,34 @@ hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const
   return hipGetLastError();
 }
 
-hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
-  const int nblk = (a.P + 15) / 16;
+hipError_t launch_chol(const CholArgs& args, hipStream_t s) {
+  const int nblk = (args.P + 15) / 16;
   if (nblk > kMaxBlk) return hipErrorInvalidValue;
   if (nblk <= kLdsBlocks) {
-    const size_t lds = chol_work_doubles(a.P) * sizeof(double);
-    k_chol<true><<<1, 1024, lds, s>>>(a);
-  } else {
-    k_chol<false><<<1, 1024, 0, s>>>(a);
+    const size_t lds = chol_work_doubles(args.P) * sizeof(double);
+    k_chol<false><<<1, 1024, lds, s>>>(args);
+    return hipGetLastError();
   }
+  CholArgs a = args;
+  a.Lg = a.W + chol_factor_doubles(a.P);
+  a.scal = a.W + 2 * chol_factor_doubles(a.P);
+  const int nslots = nblk * (nblk + 1) / 2;
+  k_big_init<<<(unsigned)((nslots * kBlk + 255) / 256 < 1024 ? (nslots * kBlk + 255) / 256 : 1024), 256, 0, s>>>(
+      a.H, a.P, a.Lg, a.scal, a.status);
+  const int nb64 = (nblk + 3) / 4;
+  for (int K = 0; K < nb64; ++K) {
+    a.b0 = 4 * K;
+    a.nb = nblk - a.b0 < 4 ? nblk - a.b0 : 4;
+    const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb) * kBlk * sizeof(double);
+    k_chol<true><<<1, 1024, lds, s>>>(a);
+    const int rows = nblk - a.b0 - a.nb;
+    if (rows > 0) {
+      k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status);
+      const int pairs = rows * (rows + 1) / 2;
+      k_big_trail<<<(unsigned)((pairs + 3) / 4), 256, 0, s>>>(a.Lg, nblk, a.b0, a.nb, a.status);
+    }
+  }
+  for (int I = 1; I < nb64; ++I) k_big_wrow<<<(unsigned)I, 1024, 0, s>>>(a.Lg, a.W, nblk, I, a.status);
   return hipGetLastError();
 }
 

@@ -110,9 +110,13 @@ hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const in
 // block-packed).  A non-positive pivot sets *status = kDevSingular.
 struct CholArgs {
   int P;
-  const double* H;
-  double* W;
+  const double* H;  // P x P, row-major (lower triangle and diagonal read)
+  double* W;        // chol_work_doubles(P): the block-packed inverse factor first
   int* status;
+  // set by launch_chol for large P: work matrix, tolerance, and the diagonal region of a step
+  double* Lg;
+  double* scal;
+  int b0, nb;
 };
 size_t chol_factor_doubles(int P);  // the block-packed factor W
 size_t chol_work_doubles(int P);    // W plus the staging blocks k_chol uses (size of CholArgs.W)

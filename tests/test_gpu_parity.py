@@ -11,7 +11,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import als as oals  # noqa: E402
-from synth import make_config, random_cores, rng_for, video_tensor  # noqa: E402
+from synth import make_config, random_cores, ring_tensor, rng_for, video_tensor  # noqa: E402
 from tests.gpu_helpers import lockstep, rel, say, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -192,3 +192,16 @@ def test_c4_full_size_video_lockstep():
     t = TR(torch.tensor(X, device="cuda"), (20,) * 4, 16384, precision="f32", init_cores=init)
     worst = lockstep(t, X, 4, 16384)
     say(f"c4 worst core rel diff {worst:.3e}")
+
+
+def test_large_P_blocked_cholesky_fp64():
+    # P = 168, 156, 182 (11-12 blocks of 16): the blocked multi-workgroup factorisation, with a
+    # partial last 64-column step, for the normal equations and the (tall) core Grams
+    say("case: fp64 200x190x180 R=(12,13,14) J=600 lockstep 4 updates (large P)")
+    dims, ranks = (200, 190, 180), (12, 13, 14)
+    X = ring_tensor(random_cores(dims, ranks, rng_for(66, 1)))
+    X = X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(66, 2).standard_normal(dims)
+    init = random_cores(dims, ranks, rng_for(66, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 600, precision="f64", init_cores=init)
+    worst = lockstep(t, X, 4, 600, core_tol=1e-8)
+    say(f"worst core rel diff {worst:.3e}")
