@@ -309,6 +309,21 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) Lb[i * kLd + l] = x[i];  // W_DD (lower; zeros above)
     }
+    // ---- phase A: the rest of step K-1's trailing update (block columns K+1 and beyond; its
+    // column K was updated before this panel), on the waves the panel leaves free ----
+    if (K >= 1 && K < nblk && wave >= triples) {
+      const int Kp = K - 1;
+      const int rem = nblk - K - 1;  // rows and columns K+1 .. nblk-1
+      for (int q = wave - triples; q < rem * (rem + 1) / 2; q += kCholWaves - triples) {
+        int ii, jj;
+        slot_ij(q, ii, jj);
+        const int i = K + 1 + ii, j = K + 1 + jj;
+        double* Aij = Ls + slot(i, j) * kBlk;
+        d4 acc = load_acc(Aij, lane);
+        acc = mma_abt(Ls + slot(i, Kp) * kBlk, Ls + slot(j, Kp) * kBlk, acc, lane, -1.0);
+        store_acc(Aij, acc, lane);
+      }
+    }
     // ---- phase A: off-diagonal blocks of W's block row I = K-2 (into the staging blocks) ----
     const int I = K - 2;
     if (hw >= 1 && I >= 1) {
@@ -332,12 +347,10 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
       // factored diagonal block into place (no one reads slot (K, K) during the trailing update)
       double* DK = Ls + slot(K, K) * kBlk;
       for (int e = threadIdx.x; e < 16 * kLd; e += 1024) DK[e] = s_diag[e];
-      // trailing update: A_ij -= L_iK L_jK^T for K < j <= i
-      const int pairs = below * (below + 1) / 2;
-      for (int q = wave; q < pairs; q += kCholWaves) {
-        int ii, jj;
-        slot_ij(q, ii, jj);
-        const int i = K + 1 + ii, j = K + 1 + jj;
+      // trailing update A_ij -= L_iK L_jK^T, block column K+1 only (the next panel); the
+      // columns beyond it are updated during the next panel
+      for (int ii = wave; ii < below; ii += kCholWaves) {
+        const int i = K + 1 + ii, j = K + 1;
         double* Aij = Ls + slot(i, j) * kBlk;
         d4 acc = load_acc(Aij, lane);
         acc = mma_abt(Ls + slot(i, K) * kBlk, Ls + slot(j, K) * kBlk, acc, lane, -1.0);
