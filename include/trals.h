@@ -129,6 +129,9 @@ int trals_create(const trals_desc* desc, const void* X_dev, int32_t x_dtype, voi
                  size_t ws_bytes, void* stream, trals_handle* out);
 
 /* As trals_workspace_bytes / trals_create, for a generated data source (no X, no panels).
+ * trals_create_generated returns once its work is enqueued (it does not synchronise the
+ * stream): an unusable source (||TR(G*)||_F zero or not finite) or a failed initial table is
+ * reported as TRALS_ESINGULAR by the next call that synchronises or by trals_query.
  * trals_fit_error of such a handle returns ||TR(G) - TR(G*)||_F / ||TR(G*)||_F (the error
  * against the noise-free tensor, by transfer matrices).  The sizing call reads only the ranks,
  * dtype and noise level of src (true_cores may be NULL there); trals_create_generated needs
@@ -158,12 +161,17 @@ int trals_sweep_until(trals_handle h, int32_t max_sweeps, double rel_tol, int32_
                       double* last_change);
 
 /* Enqueue n_sweeps like trals_sweep and return without synchronising the stream (several
- * handles on different streams then overlap on the device).  trals_query reports completion:
- * TRALS_PENDING while the stream still runs the enqueued work, TRALS_OK once it finished
- * successfully, TRALS_ESINGULAR if a solve failed; it never blocks.  trals_destroy waits for
- * pending work before it returns. */
-int trals_sweep_async(trals_handle h, int32_t n_sweeps);
-int trals_query(trals_handle h);
+ * handles on different streams then overlap on the device).  flags: 0 or TRALS_ASYNC_FIT, which
+ * also enqueues the relative error (trals_fit_error's value: the clean-ring fit of a generated
+ * source, a full pass over X otherwise) after the sweeps.  The status word and that error are
+ * copied into pinned host memory (a slot of a block the library allocates once per process)
+ * before the completion event, so that trals_query never waits: it returns TRALS_PENDING while
+ * the stream still runs the enqueued work, TRALS_OK once it finished, TRALS_ESINGULAR if a solve
+ * failed; on TRALS_OK *fit (if fit is not NULL) receives the error when TRALS_ASYNC_FIT was given,
+ * NaN otherwise.  trals_destroy waits for pending work before it returns. */
+#define TRALS_ASYNC_FIT 1
+int trals_sweep_async(trals_handle h, int32_t n_sweeps, int32_t flags);
+int trals_query(trals_handle h, double* fit);
 
 /* Run n_updates single core updates (inner iterations of Algorithm 2),
  * continuing from the update counter; core n = counter mod N is updated next. */

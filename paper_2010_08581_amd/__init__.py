@@ -96,8 +96,12 @@ class TRALS:
         self.precision = precision
         self.device = dev
         self.stream = torch.cuda.current_stream(dev) if stream is None else stream
-        self._true_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
-                                    .to(device=dev, dtype=torch.float64).reshape(-1) for c in tc])
+        if all(not isinstance(c, torch.Tensor) for c in tc):
+            flat = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in tc])
+            self._true_buf = torch.from_numpy(flat).to(device=dev)
+        else:
+            self._true_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+                                        .to(device=dev, dtype=torch.float64).reshape(-1) for c in tc])
         true_ranks = [int(c.shape[2]) for c in tc]
         init_ptr, init_buf = None, None
         if init_cores is not None:
@@ -125,16 +129,21 @@ class TRALS:
     def sweep(self, n=1):
         _lib.check(self.lib.trals_sweep(self.h, int(n)), "trals_sweep")
 
-    def sweep_async(self, n=1):
-        """Enqueue n sweeps on the handle's stream without waiting (see query)."""
-        _lib.check(self.lib.trals_sweep_async(self.h, int(n)), "trals_sweep_async")
+    def sweep_async(self, n=1, fit=False):
+        """Enqueue n sweeps on the handle's stream without waiting (see query); fit=True also
+        enqueues the relative error, available from async_fit once query() is True."""
+        flags = _lib.TRALS_ASYNC_FIT if fit else 0
+        _lib.check(self.lib.trals_sweep_async(self.h, int(n), flags), "trals_sweep_async")
+        self.async_fit = None
 
     def query(self) -> bool:
         """True once the enqueued work has finished (raises if a solve failed)."""
-        rc = self.lib.trals_query(self.h)
+        out = C.c_double(0.0)
+        rc = self.lib.trals_query(self.h, C.byref(out))
         if rc == _lib.TRALS_PENDING:
             return False
         _lib.check(rc, "trals_query")
+        self.async_fit = float(out.value)
         return True
 
     def step(self, n=1):

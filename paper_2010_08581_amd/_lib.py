@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libtrals.so")
 
 TRALS_OK, TRALS_EINVAL, TRALS_ENOMEM, TRALS_ESINGULAR, TRALS_EHIP, TRALS_ESTATE = 0, -1, -2, -3, -4, -5
 TRALS_PENDING = 1
+TRALS_ASYNC_FIT = 1
 TRALS_F64, TRALS_F32, TRALS_BF16 = 0, 1, 2
 TRALS_LEVERAGE, TRALS_UNIFORM, TRALS_EXACT = 0, 1, 2
 
@@ -89,8 +90,8 @@ def load(path: str = LIB_PATH):
         "trals_profile": (C.c_int, [vp, i32]),
         "trals_profile_read": (C.c_int, [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "trals_workspace_bytes_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), C.POINTER(C.c_size_t)]),
-        "trals_sweep_async": (C.c_int, [vp, i32]),
-        "trals_query": (C.c_int, [vp]),
+        "trals_sweep_async": (C.c_int, [vp, i32, i32]),
+        "trals_query": (C.c_int, [vp, C.POINTER(C.c_double)]),
         "trals_set_samples": (C.c_int, [vp, i64]),
         "trals_samples": (i64, [vp]),
         "trals_tr_norm": (C.c_int, [vp, C.POINTER(C.c_double)]),

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -191,7 +192,8 @@ void plan(const Problem& p, Layout* L) {
       w = ring_inner_doubles(rr, rt) > w ? ring_inner_doubles(rr, rt) : w;
       w = ring_inner_doubles(rt, rt) > w ? ring_inner_doubles(rt, rt) : w;
     }
-    L->inner = take((w + 4) * 8);  // work area, then 4 result doubles
+    // work area, then the result doubles: [0] <G,G>, [1] <G,G*>, [2] <G*,G*>, [3] sigma, [4] fit
+    L->inner = take((w + 8) * 8);
     L->inner_res = L->inner + w * 8;
   }
   for (int n = 0; n < p.N; ++n) L->core[n] = take((size_t)p.dims[n] * P_of(p, n) * 8);
@@ -245,8 +247,14 @@ struct trals_ctx {
   bool have_last = false;
   hipEvent_t done = nullptr;  // end of the last asynchronous sweep
   bool pending = false;
+  struct HostResult {         // pinned host copy of the status word and fit, written by the stream
+    int status;
+    int fit_valid;
+    double fit;
+  };
+  HostResult* host_res = nullptr;
+  bool async_fit = false;
   double xnorm2 = 0.0;   // ||X||_F^2, or ||TR(G*)||_F^2 for a generated source
-  double sigma = 0.0;    // noise level of a generated source
   hipError_t last_hip = hipSuccess;
 
   template <typename T>
@@ -421,7 +429,7 @@ int run_update(trals_ctx* h) {
     for (int k = 0; k < N - 1; ++k) fa.lin_stride[k] = cstride((n + 1 + k) % N);
     fa.lin_stride_n = cstride(n);
     fa.true_core = h->at<const double>(h->L.tcore[n]);
-    fa.sigma = h->sigma;
+    fa.sigma = h->at<const double>(h->L.inner_res) + 3;
     fa.noise_seed = p.noise_seed;
     fa.noise_stream = p.noise_stream;
     fa.out = h->at<void>(h->L.Xg);
@@ -525,7 +533,7 @@ int sync_status(trals_ctx* h) {
 int load_cores(trals_ctx* h, const void* src, int dtype);
 
 // initial cores (given, or N(0,1) from the seed) and the sampling tables of cores 1..N-1
-int init_cores_and_tables(trals_ctx* h, const trals_desc* desc) {
+int init_cores_and_tables(trals_ctx* h, const trals_desc* desc, bool wait = true) {
   const Problem& p = h->p;
   if (desc->init_cores) {
     const int r2 = load_cores(h, desc->init_cores, desc->init_dtype);
@@ -540,7 +548,7 @@ int init_cores_and_tables(trals_ctx* h, const trals_desc* desc) {
     const int r3 = compute_table(h, m);
     if (r3) return r3;
   }
-  return sync_status(h);
+  return wait ? sync_status(h) : TRALS_OK;
 }
 
 int load_cores(trals_ctx* h, const void* src, int dtype) {
@@ -554,6 +562,79 @@ int load_cores(trals_ctx* h, const void* src, int dtype) {
                               Rp, I, Rn, h->stream));
     off += (size_t)Rp * I * Rn * esz;
   }
+  return TRALS_OK;
+}
+
+// Pinned host slots for the results of asynchronous sweeps: one block allocated on first use
+// and kept for the life of the process, handed out one slot per handle.
+struct PinnedPool {
+  std::mutex mu;
+  char* base = nullptr;
+  bool tried = false;
+  std::vector<int> free_slots;
+};
+PinnedPool& pinned_pool() {
+  static PinnedPool pool;
+  return pool;
+}
+constexpr int kPinnedSlots = 4096;
+constexpr size_t kPinnedSlotBytes = 64;
+
+void* pinned_get() {
+  PinnedPool& pool = pinned_pool();
+  std::lock_guard<std::mutex> lock(pool.mu);
+  if (!pool.tried) {
+    pool.tried = true;
+    void* b = nullptr;
+    if (hipHostMalloc(&b, (size_t)kPinnedSlots * kPinnedSlotBytes, hipHostMallocDefault) == hipSuccess) {
+      pool.base = (char*)b;
+      for (int i = kPinnedSlots - 1; i >= 0; --i) pool.free_slots.push_back(i);
+    }
+  }
+  if (pool.free_slots.empty()) return nullptr;
+  const int i = pool.free_slots.back();
+  pool.free_slots.pop_back();
+  return pool.base + (size_t)i * kPinnedSlotBytes;
+}
+
+void pinned_put(void* ptr) {
+  if (!ptr) return;
+  PinnedPool& pool = pinned_pool();
+  std::lock_guard<std::mutex> lock(pool.mu);
+  pool.free_slots.push_back((int)(((char*)ptr - pool.base) / kPinnedSlotBytes));
+}
+
+// the clean-ring fit of a generated source into inner_res[4] (enqueued)
+int enqueue_clean_fit(trals_ctx* h) {
+  const Problem& p = h->p;
+  const Ring rr = make_ring(p), rt = ring_of(p, p.tranks);
+  PerMode<const double> G, T;
+  for (int n = 0; n < p.N; ++n) {
+    G.p[n] = h->at<const double>(h->L.core[n]);
+    T.p[n] = h->at<const double>(h->L.tcore[n]);
+  }
+  double* work = h->at<double>(h->L.inner);
+  double* res = h->at<double>(h->L.inner_res);
+  HIPTRY(launch_ring_inner(rr, G, rr, G, work, res, h->stream));
+  HIPTRY(launch_ring_inner(rr, G, rt, T, work, res + 1, h->stream));
+  HIPTRY(launch_clean_fit(res, res + 4, h->stream));
+  return TRALS_OK;
+}
+
+// the fit of a dense tensor (one pass over X) into inner_res[4] (enqueued)
+int enqueue_dense_fit(trals_ctx* h) {
+  const Problem& p = h->p;
+  FitArgs fa;
+  memset(&fa, 0, sizeof(fa));
+  fa.ring = make_ring(p);
+  for (int m = 0; m < p.N; ++m) fa.cores.p[m] = h->at<const void>(h->L.core[m]);
+  fa.X = h->at<const void>(h->L.fitx);
+  fa.rows = p.E / p.dims[p.N - 1];
+  fa.partial = h->at<double>(h->L.partial);
+  int nb = 0;
+  HIPTRY(launch_fit(fa, 0, p.panel_dt == 2 ? 1 : p.panel_dt, &nb, h->stream));
+  HIPTRY(launch_sum_partials(fa.partial, nb, h->scal_d(), h->stream));
+  HIPTRY(launch_dense_fit(h->scal_d(), h->xnorm2, h->at<double>(h->L.inner_res) + 4, h->stream));
   return TRALS_OK;
 }
 
@@ -683,17 +764,13 @@ int trals_create_generated(const trals_desc* desc, const trals_source* src, void
     const Ring rt = ring_of(p, p.tranks);
     PerMode<const double> T;
     for (int n = 0; n < p.N; ++n) T.p[n] = h->at<const double>(L.tcore[n]);
+    // kept on the device (no host round trip): <G*, G*> in inner_res[2], sigma in inner_res[3]
     double* res = h->at<double>(L.inner_res);
-    HIPTRY(launch_ring_inner(rt, T, rt, T, h->at<double>(L.inner), res, h->stream));
-    double x2 = 0.0;
-    HIPTRY(hipMemcpyAsync(&x2, res, 8, hipMemcpyDeviceToHost, h->stream));
-    HIPTRY(hipStreamSynchronize(h->stream));
-    if (!(x2 > 0.0) || !isfinite(x2)) return TRALS_EINVAL;
-    h->xnorm2 = x2;
+    HIPTRY(launch_ring_inner(rt, T, rt, T, h->at<double>(L.inner), res + 2, h->stream));
     double entries = 1.0;
     for (int n = 0; n < p.N; ++n) entries *= (double)p.dims[n];
-    h->sigma = p.noise_rel * sqrt(x2 / entries);
-    return init_cores_and_tables(h, desc);
+    HIPTRY(launch_source_scale(res + 2, p.noise_rel, entries, res + 3, h->status(), h->stream));
+    return init_cores_and_tables(h, desc, /*wait=*/false);
   }();
   if (rc) {
     delete h;
@@ -722,8 +799,8 @@ int trals_sweep(trals_handle h, int32_t n_sweeps) {
   return run_updates(h, (int64_t)n_sweeps * h->p.N);
 }
 
-int trals_sweep_async(trals_handle h, int32_t n_sweeps) {
-  if (!h || n_sweeps < 0) return TRALS_EINVAL;
+int trals_sweep_async(trals_handle h, int32_t n_sweeps, int32_t flags) {
+  if (!h || n_sweeps < 0 || (flags & ~TRALS_ASYNC_FIT)) return TRALS_EINVAL;
   if (h->failed) return TRALS_ESTATE;
   const int64_t count = (int64_t)n_sweeps * h->p.N;
   for (int64_t u = 0; u < count; ++u) {
@@ -733,21 +810,50 @@ int trals_sweep_async(trals_handle h, int32_t n_sweeps) {
       return rc;
     }
   }
+  const bool fit = (flags & TRALS_ASYNC_FIT) != 0;
+  if (fit) {
+    const int rc = h->p.generated ? enqueue_clean_fit(h) : enqueue_dense_fit(h);
+    if (rc) return rc;
+  }
+  if (!h->host_res) h->host_res = (trals_ctx::HostResult*)pinned_get();
+  if (h->host_res) {
+    // status and fit to pinned host memory, in stream order before the completion event
+    h->host_res->fit_valid = fit ? 1 : 0;
+    HIPTRY(hipMemcpyAsync(&h->host_res->status, h->status(), sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    if (fit)
+      HIPTRY(hipMemcpyAsync(&h->host_res->fit, h->at<double>(h->L.inner_res) + 4, sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+  }
   if (!h->done) HIPTRY(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
   HIPTRY(hipEventRecord(h->done, h->stream));
   h->pending = true;
+  h->async_fit = fit;
   return TRALS_OK;
 }
 
-int trals_query(trals_handle h) {
+int trals_query(trals_handle h, double* fit) {
   if (!h) return TRALS_EINVAL;
+  if (fit) *fit = NAN;
   if (h->failed) return TRALS_ESTATE;
   if (!h->pending) return TRALS_OK;
   const hipError_t q = hipEventQuery(h->done);
   if (q == hipErrorNotReady) return TRALS_PENDING;
   HIPTRY(q);
   h->pending = false;
-  return sync_status(h);  // the stream is idle: copies the status word and returns at once
+  if (h->host_res) {
+    if (h->host_res->status != kDevOk) {
+      h->failed = true;
+      return TRALS_ESINGULAR;
+    }
+    if (fit && h->host_res->fit_valid) *fit = h->host_res->fit;
+    return TRALS_OK;
+  }
+  // no pinned slot: the stream is idle, so this copies the status word and returns at once
+  const int rc = sync_status(h);
+  if (rc == TRALS_OK && fit && h->async_fit) {
+    HIPTRY(hipMemcpy(fit, h->at<double>(h->L.inner_res) + 4, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return rc;
 }
 
 int trals_step(trals_handle h, int32_t n_updates) { return run_updates(h, n_updates); }
@@ -768,11 +874,12 @@ int trals_fit_error(trals_handle h, double* rel_err) {
     double* res = h->at<double>(h->L.inner_res);
     HIPTRY(launch_ring_inner(rr, G, rr, G, work, res, h->stream));
     HIPTRY(launch_ring_inner(rr, G, rt, T, work, res + 1, h->stream));
-    double r[2] = {0.0, 0.0};
-    HIPTRY(hipMemcpyAsync(r, res, 16, hipMemcpyDeviceToHost, h->stream));
-    HIPTRY(hipStreamSynchronize(h->stream));
-    const double d2 = r[0] - 2.0 * r[1] + h->xnorm2;
-    *rel_err = sqrt((d2 > 0.0 ? d2 : 0.0) / h->xnorm2);
+    double r[3] = {0.0, 0.0, 0.0};
+    HIPTRY(hipMemcpyAsync(r, res, 24, hipMemcpyDeviceToHost, h->stream));
+    const int st = sync_status(h);
+    if (st) return st;
+    const double d2 = r[0] - 2.0 * r[1] + r[2];
+    *rel_err = sqrt((d2 > 0.0 ? d2 : 0.0) / r[2]);
     return TRALS_OK;
   }
   FitArgs fa;
@@ -796,6 +903,7 @@ int trals_destroy(trals_handle h) {
   if (!h) return TRALS_OK;
   if (h->pending) (void)hipStreamSynchronize(h->stream);  // work may still use the workspace
   if (h->done) (void)hipEventDestroy(h->done);
+  pinned_put(h->host_res);
   for (auto& v : h->prof.ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   delete h;

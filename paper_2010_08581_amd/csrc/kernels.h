@@ -150,12 +150,19 @@ struct FiberArgs {
   int64_t lin_stride[kMaxOrder];
   int64_t lin_stride_n;
   const double* true_core;    // slice-major I_n x P, FP64
-  double sigma;
+  const double* sigma;        // device scalar
   uint64_t noise_seed, noise_stream;
   void* out;                  // J x I_n, panel type
   const int* status;
 };
 hipError_t launch_fibers(const FiberArgs& a, int out_dtype, hipStream_t s);
+// *sigma = noise_rel sqrt(*t2 / entries) (*status = kDevSingular if *t2 is not positive and finite)
+hipError_t launch_source_scale(const double* t2, double noise_rel, double entries, double* sigma, int* status,
+                               hipStream_t s);
+// *fit = sqrt(max(0, r[0] - 2 r[1] + r[2]) / r[2]) (distance of two rings relative to the second)
+hipError_t launch_clean_fit(const double* r, double* fit, hipStream_t s);
+// *fit = sqrt(*r2 / x2)
+hipError_t launch_dense_fit(const double* r2, double x2, double* fit, hipStream_t s);
 // *out = <TR(A), TR(B)> for two rings with equal mode sizes (FP64 slice-major cores); work:
 // ring_inner_doubles(ra, rb) doubles.
 size_t ring_inner_doubles(const Ring& ra, const Ring& rb);

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
   __shared__ int64_t s_base[kFiberSamples];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In, K = a.K;
+  const double sigma = *a.sigma;
   const int64_t j0 = (int64_t)blockIdx.x * kFiberSamples;
   const int ns = a.J - j0 < kFiberSamples ? (int)(a.J - j0) : kFiberSamples;
   for (int e = threadIdx.x; e < ns * P; e += 256) s_t[e] = a.T[j0 * P + e];
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
     double v = 0.0;
     for (int p = 0; p < P; ++p) v = fma(g[p], t[p], v);
     const int64_t lin = s_base[s] + (int64_t)i * a.lin_stride_n;
-    v += a.sigma * philox_normal((uint64_t)lin, a.noise_seed, a.noise_stream);
+    v += sigma * philox_normal((uint64_t)lin, a.noise_seed, a.noise_stream);
     out[(j0 + s) * In + i] = cvt_out<Tout>(v);
   }
 }
@@ -114,7 +115,43 @@ __global__ __launch_bounds__(256) void k_trace(const double* __restrict__ M, int
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// sigma = noise_rel sqrt(<G*, G*> / prod I); a zero or non-finite norm marks the source unusable
+__global__ void k_source_scale(const double* t2, double noise_rel, double entries, double* sigma, int* status) {
+  if (*status != kDevOk) return;
+  const double x = *t2;
+  if (!(x > 0.0) || !isfinite(x)) {
+    *status = kDevSingular;
+    return;
+  }
+  *sigma = noise_rel * sqrt(x / entries);
+}
+
+// fit = sqrt(max(0, <G,G> - 2 <G,G*> + <G*,G*>) / <G*,G*>), r = {<G,G>, <G,G*>, <G*,G*>}
+__global__ void k_clean_fit(const double* r, double* fit) {
+  const double d2 = r[0] - 2.0 * r[1] + r[2];
+  *fit = sqrt((d2 > 0.0 ? d2 : 0.0) / r[2]);
+}
+
+// fit = sqrt(r2 / x2) for the residual sum r2 of a full pass
+__global__ void k_dense_fit(const double* r2, double x2, double* fit) { *fit = sqrt(*r2 / x2); }
+
 }  // namespace
+
+hipError_t launch_source_scale(const double* t2, double noise_rel, double entries, double* sigma, int* status,
+                               hipStream_t s) {
+  k_source_scale<<<1, 1, 0, s>>>(t2, noise_rel, entries, sigma, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_clean_fit(const double* r, double* fit, hipStream_t s) {
+  k_clean_fit<<<1, 1, 0, s>>>(r, fit);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_fit(const double* r2, double x2, double* fit, hipStream_t s) {
+  k_dense_fit<<<1, 1, 0, s>>>(r2, x2, fit);
+  return hipGetLastError();
+}
 
 hipError_t launch_fibers(const FiberArgs& a, int out_dtype, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.J + kFiberSamples - 1) / kFiberSamples);

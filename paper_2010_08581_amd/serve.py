@@ -190,10 +190,12 @@ class TralsEngine:
     """GPU engine: one generated-source TRALS handle per running request.
 
     Request fields: id, dims, ranks, samples, sweeps, seed, and optionally
-    noise_rel (default the engine's).  The true cores come from
-    ``true_cores(req)`` (host arrays of shapes (R[n-1], I[n], R[n])); the
-    noise is keyed (seed, id), the initial cores and the sampler
-    (seed, stream id = id).
+    noise_rel (default the engine's) and true_cores (the data the request
+    carries: host arrays of shapes (R[n-1], I[n], R[n])); without them the
+    engine calls ``true_cores(req)``.  The noise is keyed (seed, id), the
+    initial cores and the sampler (seed, stream id = id).  A request's work
+    is enqueued without waiting (handle creation, sweeps and the error
+    against the clean ring); completion is polled.
     """
 
     def __init__(self, true_cores, precision="f32", noise_rel=0.01, device=None, keep_cores=True):
@@ -229,21 +231,27 @@ class TralsEngine:
 
     def start(self, req, slot):
         stream = self._stream(slot)
+        cores = req.get("true_cores")
+        if cores is None:
+            cores = self.true_cores(req)
         with self.torch.cuda.stream(stream):
-            h = TRALS.generated(self.true_cores(req), req["ranks"], req["samples"],
+            h = TRALS.generated(cores, req["ranks"], req["samples"],
                                 noise_rel=req.get("noise_rel", self.noise_rel), noise_seed=req["seed"],
                                 noise_stream=req["id"], seed=req["seed"], stream_id=req["id"],
                                 precision=self.precision, stream=stream, device=self.device)
-            h.sweep_async(req["sweeps"])
+            h.sweep_async(req["sweeps"], fit=True)
         return h
 
     def poll(self, job) -> bool:
         return job.query()
 
     def finish(self, job) -> dict:
-        with self.torch.cuda.stream(job.stream):
-            fit = job.fit_error()
-            cores = [c.cpu().numpy() for c in job.get_cores()] if self.keep_cores else None
+        # the fit came back with the completion (no synchronisation); the cores need a copy
+        cores = None
+        if self.keep_cores:
+            with self.torch.cuda.stream(job.stream):
+                cores = [c.cpu().numpy() for c in job.get_cores()]
+        fit = job.async_fit
         job.close()
         return dict(fit=fit, cores=cores)
 

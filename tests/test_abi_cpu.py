@@ -111,8 +111,8 @@ def test_null_handles_of_new_entries(lib):
     assert lib.trals_samples(None) == -1
     assert lib.trals_tr_norm(None, None) == _lib.TRALS_EINVAL
     assert lib.trals_sweep_until(None, 1, 0.0, None, None) == _lib.TRALS_EINVAL
-    assert lib.trals_sweep_async(None, 1) == _lib.TRALS_EINVAL
-    assert lib.trals_query(None) == _lib.TRALS_EINVAL
+    assert lib.trals_sweep_async(None, 1, 0) == _lib.TRALS_EINVAL
+    assert lib.trals_query(None, None) == _lib.TRALS_EINVAL
 
 
 def test_normalize_flag_validated(lib):
