@@ -153,8 +153,7 @@ def serving_form(args):
     from paper_2010_08581_amd.serve import TralsEngine, run, summarize
     eng = TralsEngine(synth.serving_true_cores, precision="f32", noise_rel=0.01, keep_cores=False)
     budget = 16 << 30
-    warm = synth.serving_requests(8, rate=1e9, seed=99)
-    run(eng, warm, slots=args.serve_slots, mem_budget=budget)
+    eng.warmup(args.serve_slots)
     # each request carries its tensor's data (the true cores), made by the client beforehand
     reqs = [dict(r, true_cores=synth.serving_true_cores(r))
             for r in synth.serving_requests(args.serve_requests, rate=200.0, seed=0)]

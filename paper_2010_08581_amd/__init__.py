@@ -23,6 +23,10 @@ def _torch():
     return torch
 
 
+def torch_device(d):
+    return _torch().device(d)
+
+
 class TRALS:
     """One sampled TR-ALS problem held on the GPU.
 
@@ -37,11 +41,12 @@ class TRALS:
     """
 
     def __init__(self, X, ranks, samples, seed=0, stream_id=0, precision="f32", init_cores=None,
-                 stream=None, source=None, method="leverage", normalize=False):
+                 stream=None, source=None, method="leverage", normalize=False, workspace=None):
         torch = _torch()
         self.lib = _lib.load()
         self.method = method
         self.normalize = bool(normalize)
+        self._arena = workspace  # optional preallocated uint8 CUDA tensor for the workspace
         if source is not None:
             self._init_generated(source, ranks, samples, seed, stream_id, precision, init_cores, stream)
             return
@@ -65,7 +70,7 @@ class TRALS:
                                           init_ptr, init_dt, _METHOD[method], self.normalize)
         nbytes = C.c_size_t(0)
         _lib.check(self.lib.trals_workspace_bytes(C.byref(desc), C.byref(nbytes)), "trals_workspace_bytes")
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=X.device)
+        self.workspace = self._take_workspace(int(nbytes.value), X.device)
         h = C.c_void_p(0)
         _lib.check(self.lib.trals_create(C.byref(desc), C.c_void_p(X.data_ptr()), xdt,
                                          C.c_void_p(self.workspace.data_ptr()), nbytes,
@@ -76,13 +81,14 @@ class TRALS:
     @classmethod
     def generated(cls, true_cores, ranks, samples, noise_rel=0.0, noise_seed=0, noise_stream=0,
                   seed=0, stream_id=0, precision="f32", init_cores=None, stream=None, device=None,
-                  method="leverage", normalize=False):
+                  method="leverage", normalize=False, workspace=None):
         """Handle whose data is TR(true_cores) + noise, generated fiber by fiber on the GPU
         (never materialised).  true_cores: list of N arrays/tensors (R[n-1], I[n], R[n])."""
         src = dict(true_cores=true_cores, noise_rel=noise_rel, noise_seed=noise_seed,
                    noise_stream=noise_stream, device=device)
         return cls(None, ranks, samples, seed=seed, stream_id=stream_id, precision=precision,
-                   init_cores=init_cores, stream=stream, source=src, method=method, normalize=normalize)
+                   init_cores=init_cores, stream=stream, source=src, method=method, normalize=normalize,
+                   workspace=workspace)
 
     def _init_generated(self, source, ranks, samples, seed, stream_id, precision, init_cores, stream):
         torch = _torch()
@@ -96,12 +102,6 @@ class TRALS:
         self.precision = precision
         self.device = dev
         self.stream = torch.cuda.current_stream(dev) if stream is None else stream
-        if all(not isinstance(c, torch.Tensor) for c in tc):
-            flat = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in tc])
-            self._true_buf = torch.from_numpy(flat).to(device=dev)
-        else:
-            self._true_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
-                                        .to(device=dev, dtype=torch.float64).reshape(-1) for c in tc])
         true_ranks = [int(c.shape[2]) for c in tc]
         init_ptr, init_buf = None, None
         if init_cores is not None:
@@ -110,20 +110,48 @@ class TRALS:
             init_ptr = init_buf.data_ptr()
         desc, keep = _lib.make_desc(self.dims, self.ranks, self.J, seed, stream_id, _PREC[precision],
                                     init_ptr, TRALS_F64, _METHOD[self.method], self.normalize)
-        src, keep2 = _lib.make_source(self._true_buf.data_ptr(), TRALS_F64, true_ranks, source["noise_rel"],
-                                      source["noise_seed"], source["noise_stream"])
-        self._keep = (keep, keep2, init_buf)
+        sizing, keep2 = _lib.make_source(None, TRALS_F64, true_ranks, source["noise_rel"], source["noise_seed"],
+                                         source["noise_stream"])
         nbytes = C.c_size_t(0)
-        _lib.check(self.lib.trals_workspace_bytes_generated(C.byref(desc), C.byref(src), C.byref(nbytes)),
+        _lib.check(self.lib.trals_workspace_bytes_generated(C.byref(desc), C.byref(sizing), C.byref(nbytes)),
                    "trals_workspace_bytes_generated")
         self.workspace_bytes = int(nbytes.value)
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        # true cores (FP64, concatenated): behind the workspace in the arena when it has room
+        n_true = sum(int(np.prod(c.shape)) for c in tc)
+        off = (self.workspace_bytes + 255) // 256 * 256
+        a = self._arena
+        if a is not None and a.device == torch_device(dev) and a.numel() >= off + 8 * n_true:
+            self.workspace = a[:self.workspace_bytes]
+            self._true_buf = a[off:off + 8 * n_true].view(torch.float64)
+            if all(not isinstance(c, torch.Tensor) for c in tc):
+                flat = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in tc])
+                self._true_buf.copy_(torch.from_numpy(flat))
+            else:
+                self._true_buf.copy_(torch.cat([torch.as_tensor(c).to(device=dev, dtype=torch.float64).reshape(-1)
+                                                for c in tc]))
+        else:
+            self.workspace = self._take_workspace(self.workspace_bytes, dev)
+            if all(not isinstance(c, torch.Tensor) for c in tc):
+                flat = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in tc])
+                self._true_buf = torch.from_numpy(flat).to(device=dev)
+            else:
+                self._true_buf = torch.cat([torch.as_tensor(np.asarray(c) if not isinstance(c, torch.Tensor) else c)
+                                            .to(device=dev, dtype=torch.float64).reshape(-1) for c in tc])
+        src, keep3 = _lib.make_source(self._true_buf.data_ptr(), TRALS_F64, true_ranks, source["noise_rel"],
+                                      source["noise_seed"], source["noise_stream"])
+        self._keep = (keep, keep2, keep3, init_buf)
         h = C.c_void_p(0)
         _lib.check(self.lib.trals_create_generated(C.byref(desc), C.byref(src), C.c_void_p(self.workspace.data_ptr()),
                                                    nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)),
                    "trals_create_generated")
         self.h = h
         self.core_shapes = [(self.ranks[(n - 1) % self.N], self.dims[n], self.ranks[n]) for n in range(self.N)]
+
+    def _take_workspace(self, nbytes, device):
+        a = self._arena
+        if a is not None and a.numel() >= nbytes and a.device == torch_device(device):
+            return a[:nbytes]
+        return _torch().empty(nbytes, dtype=_torch().uint8, device=device)
 
     # -- driving the iteration --
     def sweep(self, n=1):
