@@ -257,6 +257,10 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
       for (int c = 0; c < 16; ++c) v[c] = src[c];
       int bad = 0;
       double myil = 0.0;
+      // l re-read here: keeps the sixteen lane == k masks from being hoisted out of the step
+      // loop, where they would hold 32 scalar registers for the whole kernel
+      int lme = l;
+      asm volatile("" : "+v"(lme));
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const double pk = lane_bcast(v[k], k);
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) v[j] = fma(-t, lane_bcast(v[k], j), v[j]);
         v[k] *= il;
-        if (l == k) myil = il;
+        if (lme == k) myil = il;
         // keep the update right-looking: each column is final when its pivot step starts, so
         // the compiler cannot defer the updates into a dependent chain at the pivot
 #pragma unroll
@@ -297,8 +301,10 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) s_lt[c * 16 + l] = Lb[l * kLd + c];
       double x[16];
+      int lme = l;  // (as in the panel: no hoisted masks)
+      asm volatile("" : "+v"(lme));
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = i == l ? 1.0 : 0.0;
+      for (int i = 0; i < 16; ++i) x[i] = i == lme ? 1.0 : 0.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         x[k] *= s_rdiag[16 * D + k];
