@@ -182,27 +182,31 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
     }
   } else {
     // stage the lower blocks (full diagonal blocks; identity on the padded diagonal), eight
-    // loads in flight per thread
-    const int cnt = nslots * 256;
+    // loads in flight per thread.  A wave covers four rows of one block: the block (bi, bj) is
+    // wave-uniform and walks four slots per load (no per-element index arithmetic).
     constexpr int kB = 8;
-    for (int base = 0; base < cnt; base += kB * 1024) {
+    const int r = (threadIdx.x >> 4) & 15, c = threadIdx.x & 15;
+    for (int base = 0; base < nslots; base += 4 * kB) {
+      int sl = __builtin_amdgcn_readfirstlane(base + ((int)threadIdx.x >> 8));
+      int bi, bj;
+      slot_ij(sl, bi, bj);
       double v[kB];
-      int dst[kB];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + 1024 * q;
-        const int sl = e >> 8, rc = e & 255;
-        int bi, bj;
-        slot_ij(sl, bi, bj);
-        const int r = rc >> 4, c = rc & 15;
         const int i = 16 * bi + r, j = 16 * bj + c;
-        const bool in = e < cnt && i < P && j < P;
+        const bool in = sl < nslots && i < P && j < P;
         v[q] = in ? H[(int64_t)i * P + j] : (i == j ? 1.0 : 0.0);
-        dst[q] = sl * kBlk + r * kLd + c;
+        bj += 4;  // next slot of this wave: four slots on
+        while (bj > bi) {
+          bj -= bi + 1;
+          ++bi;
+        }
+        sl += 4;
       }
+      sl -= 4 * kB;
 #pragma unroll
       for (int q = 0; q < kB; ++q)
-        if (base + (int)threadIdx.x + 1024 * q < cnt) Ls[dst[q]] = v[q];
+        if (sl + 4 * q < nslots) Ls[(sl + 4 * q) * kBlk + r * kLd + c] = v[q];
     }
   }
   __syncthreads();
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg
 // Workgroups [solve_groups, +lev_groups) take 16 rows each of a core unfolding G_(2) and
 // write the table weights Q_i = floor(||W g_i||^2 / P * 2^52).  Each wave takes the 16-row
 // blocks K = wave, wave + 4, ...
-template <bool kWInLds, int T>
+template <int T>
 __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   extern __shared__ double lds[];
   __shared__ double s_red[4][16];
@@ -506,56 +510,39 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   constexpr int kLdB = 17;
   const int P = a.P;
   const int nblk = (P + 15) / 16;
-  const int nslots = nblk * (nblk + 1) / 2;
   const bool lev = (int)blockIdx.x >= a.solve_groups;
   const int grp = lev ? (int)blockIdx.x - a.solve_groups : (int)blockIdx.x;
-  const double* Wg = lev ? a.Wlev : a.Wsol;
+  const double* W = lev ? a.Wlev : a.Wsol;
   const double* Bsrc = lev ? a.Blev : a.Bsol;
   const int In = lev ? a.In_lev : a.In_sol;
   const int i0 = 16 * grp;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
   double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
-  double* Ws = lds + nblk * 16 * kLdB;
   {
-    // right-hand sides (transposed into Bs) and, when staged, W: all loads of a round are
-    // issued before any store, so that the staging costs one memory round trip when it fits
-    // in one round (16 x 16 nblk <= 8 x 256 elements, W <= 16 x 256 double2)
+    // right-hand sides, transposed into Bs; all loads of a round are issued before any store.
+    // W is read from memory by the products below: every workgroup shares it through L2, and
+    // staging a copy per workgroup in LDS was measured slower (an extra round trip of up to 61 KB)
     const int cnt = 16 * nblk * 16;
-    const int64_t wcnt = kWInLds ? (int64_t)nslots * kBlk / 2 : 0;
-    constexpr int kB = 8, kBW = 16;
-    for (int64_t base = 0, wbase = 0; base < cnt || wbase < wcnt; base += kB * 256, wbase += kBW * 256) {
+    constexpr int kB = 8;
+    for (int base = 0; base < cnt; base += kB * 256) {
       double v[kB];
-      double2 wv[kBW];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = (int)base + (int)threadIdx.x + 256 * q;
+        const int e = base + (int)threadIdx.x + 256 * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         const bool ok = e < cnt && i0 + j < In && p < P;
         v[q] = ok ? Bsrc[(int64_t)(i0 + j) * P + p] : 0.0;
       }
-      if (kWInLds)
-#pragma unroll
-        for (int q = 0; q < kBW; ++q) {
-          const int64_t e = wbase + threadIdx.x + 256 * q;
-          wv[q] = ((const double2*)Wg)[e < wcnt ? e : wcnt - 1];
-        }
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = (int)base + (int)threadIdx.x + 256 * q;
+        const int e = base + (int)threadIdx.x + 256 * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         if (e < cnt) Bs[p * kLdB + j] = v[q];
       }
-      if (kWInLds)
-#pragma unroll
-        for (int q = 0; q < kBW; ++q) {
-          const int64_t e = wbase + threadIdx.x + 256 * q;
-          if (e < wcnt) ((double2*)Ws)[e] = wv[q];
-        }
     }
   }
   __syncthreads();
-  const double* W = kWInLds ? Ws : Wg;
   // Y_K = sum_{J <= K} W_KJ B_J
   d4 Y[T];
 #pragma unroll
@@ -622,13 +609,12 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   }
 }
 
-template <bool kWInLds>
 hipError_t trisolve_dispatch(const TriArgs& a, int nblk, unsigned grid, size_t lds, hipStream_t s) {
-  if (nblk <= 4) k_trisolve<kWInLds, 1><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 8) k_trisolve<kWInLds, 2><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 16) k_trisolve<kWInLds, 4><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 32) k_trisolve<kWInLds, 8><<<grid, 256, lds, s>>>(a);
-  else k_trisolve<kWInLds, 16><<<grid, 256, lds, s>>>(a);
+  if (nblk <= 4) k_trisolve<1><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 8) k_trisolve<2><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 16) k_trisolve<4><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 32) k_trisolve<8><<<grid, 256, lds, s>>>(a);
+  else k_trisolve<16><<<grid, 256, lds, s>>>(a);
   return hipGetLastError();
 }
 
@@ -691,11 +677,8 @@ hipError_t launch_trisolve(const TriArgs& args, hipStream_t s) {
   a.lev_groups = a.Wlev ? (a.In_lev + 15) / 16 : 0;
   const unsigned grid = (unsigned)(a.solve_groups + a.lev_groups);
   if (grid == 0) return hipSuccess;
-  const size_t bbytes = (size_t)nblk * 16 * 17 * sizeof(double);
-  const bool w_in_lds = nblk <= kLdsBlocks;
-  const size_t lds = bbytes + (w_in_lds ? chol_factor_doubles(a.P) * sizeof(double) : 0);
-  if (w_in_lds) return trisolve_dispatch<true>(a, nblk, grid, lds, s);
-  return trisolve_dispatch<false>(a, nblk, grid, lds, s);
+  const size_t lds = (size_t)nblk * 16 * 17 * sizeof(double);
+  return trisolve_dispatch(a, nblk, grid, lds, s);
 }
 
 }  // namespace trals
