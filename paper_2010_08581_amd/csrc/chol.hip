@@ -519,8 +519,27 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
   double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
+  // W operands.  Up to 8 blocks per row (P <= 128), all operands of a wave's products are held
+  // in registers: the Y operands are loaded before the right-hand sides are staged and the Z
+  // operands before Y is exchanged, so that their memory latency overlaps that work.  Larger P
+  // streams them one block ahead of the matrix cores.
+  constexpr bool kHeld = T <= 2;
+  constexpr int kHB = kHeld ? 4 * T : 1;
+  double wo[T][kHB][4];
+  auto load_y_operands = [&]() {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int K = wave + 4 * t;
+      const double* Wr = W + (int64_t)slot(K < nblk ? K : 0, 0) * kBlk + r16 * kLd + k4;
+#pragma unroll
+      for (int J = 0; J < kHB; ++J)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wo[t][J][ks] = (K < nblk && J <= K) ? Wr[(J <= K ? J : 0) * kBlk + 4 * ks] : 0.0;
+    }
+  };
   {
-    // right-hand sides, transposed into Bs; all loads of a round are issued before any store.
+    // right-hand sides, transposed into Bs (one round of eight loads per thread up to P = 128);
+    // all loads of a round are issued before any store.
     // W is read from memory by the products below: every workgroup shares it through L2, and
     // staging a copy per workgroup in LDS was measured slower (an extra round trip of up to 61 KB)
     const int cnt = 16 * nblk * 16;
@@ -534,6 +553,10 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
         const bool ok = e < cnt && i0 + j < In && p < P;
         v[q] = ok ? Bsrc[(int64_t)(i0 + j) * P + p] : 0.0;
       }
+      // (one round when the operands are held: issued after the right-hand sides, whose
+      // stores below then wait for those loads only)
+      if constexpr (kHeld)
+        if (base == 0) load_y_operands();
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
         const int e = base + (int)threadIdx.x + 256 * q;
@@ -543,18 +566,33 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     }
   }
   __syncthreads();
-  // Y_K = sum_{J <= K} W_KJ B_J
+  // Y_K = sum_{J <= K} W_KJ B_J (blocks (K, 0 .. K) are consecutive slots)
   d4 Y[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int K = wave + 4 * t;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    if (K < nblk) {
-      for (int J = 0; J <= K; ++J) {
-        const double* WKJ = W + slot(K, J) * kBlk;
+    if (kHeld) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          acc = mfma(WKJ[r16 * kLd + 4 * ks + k4], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+      for (int J = 0; J < kHB; ++J)
+        if (J <= K && K < nblk)
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) acc = mfma(wo[t][J][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+    } else if (K < nblk) {
+      const double* Wr = W + (int64_t)slot(K, 0) * kBlk + r16 * kLd + k4;
+      double wc[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) wc[ks] = Wr[4 * ks];
+      for (int J = 0; J <= K; ++J) {
+        const int Jn = J < K ? J + 1 : K;
+        double wn[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wn[ks] = Wr[Jn * kBlk + 4 * ks];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          acc = mfma(wc[ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+          wc[ks] = wn[ks];
+        }
       }
     }
     Y[t] = acc;
@@ -577,7 +615,23 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     }
     return;
   }
-  // Z_K = sum_{J >= K} W_JK^T Y_J
+  // Z_K = sum_{J >= K} W_JK^T Y_J; blocks (J, K), J = K .. nblk-1, at slot(J + 1, K) =
+  // slot(J, K) + J + 1
+  const double* Wc = W + k4 * kLd + r16;
+  if constexpr (kHeld) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int K = wave + 4 * t;
+      int sl = slot(K < nblk ? K : 0, K < nblk ? K : 0);
+#pragma unroll
+      for (int m = 0; m < kHB; ++m) {
+        const bool in = K + m < nblk;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wo[t][m][ks] = in ? Wc[(int64_t)sl * kBlk + 4 * ks * kLd] : 0.0;
+        if (in) sl += K + m + 1;
+      }
+    }
+  }
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -594,11 +648,30 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     const int K = wave + 4 * t;
     if (K < nblk) {
       d4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int J = K; J < nblk; ++J) {
-        const double* WJK = W + slot(J, K) * kBlk;
+      if (kHeld) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks)
-          acc = mfma(WJK[(4 * ks + k4) * kLd + r16], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+        for (int m = 0; m < kHB; ++m)
+          if (K + m < nblk)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+              acc = mfma(wo[t][m][ks], Bs[(16 * (K + m) + 4 * ks + k4) * kLdB + r16], acc);
+      } else {
+      int sl = slot(K, K);
+      double wc[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) wc[ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
+      for (int J = K; J < nblk; ++J) {
+        const int sn = J + 1 < nblk ? sl + J + 1 : sl;
+        double wn[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wn[ks] = Wc[(int64_t)sn * kBlk + 4 * ks * kLd];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          acc = mfma(wc[ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+          wc[ks] = wn[ks];
+        }
+        sl = sn;
+      }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
