@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
   if (*status != kDevOk) return;
   int bi, bj;
   slot_ij(blockIdx.x, bi, bj);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   const int r16 = lane & 15, k4 = lane >> 4;
   const int ci = 16 * bi + r16, cj = 16 * bj + r16;
   const int cic = ci < P ? ci : P - 1, cjc = cj < P ? cj : P - 1;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   const int g0 = kRegion ? a.b0 : 0;  // global block index of local block 0
   const int nblk = kRegion ? a.nb : (P + 15) / 16;
   const int nslots = nblk * (nblk + 1) / 2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   double* Ls = lds;
   if (kRegion) {
     for (int e = threadIdx.x; e < nslots * kBlk; e += 1024) {
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg
                                                    int I, const int* status) {
   __shared__ double stage[16][16 * kLd];
   if (*status != kDevOk) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   const int J = blockIdx.x;
   const int r = wave >> 2, c = wave & 3;
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   const double* Bsrc = lev ? a.Blev : a.Bsol;
   const int In = lev ? a.In_lev : a.In_sol;
   const int i0 = 16 * grp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   const int r16 = lane & 15, k4 = lane >> 4;
   double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
   // W operands.  Up to 8 blocks per row (P <= 128), all operands of a wave's products are held

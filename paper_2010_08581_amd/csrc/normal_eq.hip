@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   const int npad = rounds * KG * kKB;
   const Real* A = (const Real*)a.A;
   const Real* X = (const Real*)a.panel;
-  const int g = threadIdx.x >> 8, tl = threadIdx.x & 255;
-  const int lane = tl & 63, wave = tl >> 6;
+  const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 8), tl = threadIdx.x & 255;
+  const int lane = tl & 63, wave = __builtin_amdgcn_readfirstlane(tl >> 6);  // uniform per wave
   Real* As = (Real*)ne_smem + (size_t)g * 2 * (kStageA + kStageB);
   Real* Bs = As + 2 * kStageA;
   // per chunk row: panel-row offset (data tiles) and the row factor (w_j for data tiles, 1 for
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
   const int nrows = (int)(r1 - r0);
   const int npad = (nrows + kKB16 - 1) / kKB16 * kKB16;  // r0 + npad <= ld
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int li = lane & 15, lg = lane >> 4;
   const int64_t ld = a.ld;
   const __bf16* X = (const __bf16*)a.panel;
