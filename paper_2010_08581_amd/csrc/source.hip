@@ -69,18 +69,46 @@ __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
   }
 }
 
-// E[(a a') x (b b')] = sum_i A(a, i, b) B(a', i, b'); A, B slice-major (I, Ra0, Ra1), (I, Rb0, Rb1)
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// E[(a a') x (b b')] = sum_i A(a, i, b) B(a', i, b'); A, B slice-major (I, Ra0, Ra1), (I, Rb0, Rb1).
+// As a product: E is M = Ahat^T Bhat with its index pairs regrouped, where row i of Ahat is
+// slice i of A flattened ((a b), Ra0 Ra1 entries) and row i of Bhat slice i of B.  One wave per
+// 16 x 16 tile of M on v_mfma_f64_16x16x4 (A(r, k) in lane r + 16 k, B(k, c) in lane c + 16 k,
+// D(r, c) in lane c + 16 (r % 4), register r / 4): four slices per instruction, alternate steps
+// into two accumulators; the result is written to E in the regrouped order.
 __global__ __launch_bounds__(256) void k_transfer(const double* __restrict__ A, const double* __restrict__ B, int I,
-                                                  int Ra0, int Ra1, int Rb0, int Rb1, double* __restrict__ E) {
-  const int rows = Ra0 * Rb0, cols = Ra1 * Rb1;
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)rows * cols) return;
-  const int r = (int)(e / cols), c = (int)(e - (int64_t)r * cols);
-  const int a = r / Rb0, a2 = r - a * Rb0, b = c / Rb1, b2 = c - b * Rb1;
+                                                  int Ra0, int Ra1, int Rb0, int Rb1, double* __restrict__ E,
+                                                  int tiles_n, int ntiles) {
+  const int lane = threadIdx.x & 63;
+  const int tile = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
   const int pa = Ra0 * Ra1, pb = Rb0 * Rb1;
-  double s = 0.0;
-  for (int i = 0; i < I; ++i) s = fma(A[(int64_t)i * pa + a * Ra1 + b], B[(int64_t)i * pb + a2 * Rb1 + b2], s);
-  E[e] = s;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int m = 16 * tm + r16, n = 16 * tn + r16;
+  const int mc = m < pa ? m : pa - 1, nc = n < pb ? n : pb - 1;  // clamped: loads stay in bounds
+  const double fm = m < pa ? 1.0 : 0.0;
+  d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < I; i0 += 8) {
+    const int i1 = i0 + k4, i2 = i0 + 4 + k4;
+    const int i1c = i1 < I ? i1 : I - 1, i2c = i2 < I ? i2 : I - 1;
+    const double a1 = (i1 < I ? fm : 0.0) * A[(int64_t)i1c * pa + mc];
+    const double b1 = B[(int64_t)i1c * pb + nc];
+    const double a2 = (i2 < I ? fm : 0.0) * A[(int64_t)i2c * pa + mc];
+    const double b2 = B[(int64_t)i2c * pb + nc];
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc1, 0, 0, 0);
+  }
+  const int cols = Ra1 * Rb1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int mm = 16 * tm + 4 * r + k4, nn = 16 * tn + r16;
+    if (mm < pa && nn < pb) {
+      const int a = mm / Ra1, b = mm - a * Ra1, a2 = nn / Rb1, b2 = nn - a2 * Rb1;
+      E[(int64_t)(a * Rb0 + a2) * cols + b * Rb1 + b2] = acc0[r] + acc1[r];
+    }
+  }
 }
 
 // C = A (m x k) B (k x n), row-major FP64, 16 x 16 tiles through LDS
@@ -190,8 +218,9 @@ hipError_t launch_ring_inner(const Ring& ra, PerMode<const double> A, const Ring
     const int Ra0 = rank_before(ra, n), Ra1 = ra.ranks[n], Rb0 = rank_before(rb, n), Rb1 = rb.ranks[n];
     const int rows = Ra0 * Rb0, cols = Ra1 * Rb1;
     double* dst = n == 0 ? C0 : E;
-    const int64_t cnt = (int64_t)rows * cols;
-    k_transfer<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(A.p[n], B.p[n], ra.dims[n], Ra0, Ra1, Rb0, Rb1, dst);
+    const int tiles_n = (Rb0 * Rb1 + 15) / 16, ntiles = (Ra0 * Ra1 + 15) / 16 * tiles_n;
+    k_transfer<<<(unsigned)((ntiles + 3) / 4), 256, 0, s>>>(A.p[n], B.p[n], ra.dims[n], Ra0, Ra1, Rb0, Rb1, dst,
+                                                             tiles_n, ntiles);
     if (n == 0) {
       cur = C0;
       cur_rows = rows;
