@@ -520,9 +520,9 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   const int r16 = lane & 15, k4 = lane >> 4;
   double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
   // W operands.  Up to 8 blocks per row (P <= 128), all operands of a wave's products are held
-  // in registers: the Y operands are loaded before the right-hand sides are staged and the Z
-  // operands before Y is exchanged, so that their memory latency overlaps that work.  Larger P
-  // streams them one block ahead of the matrix cores.
+  // in registers: the Y operands are loaded while the right-hand sides are staged (right after
+  // their loads) and the Z operands before Y is exchanged, so that their memory latency overlaps
+  // that work.  Larger P streams them one block ahead of the matrix cores.
   constexpr bool kHeld = T <= 2;
   constexpr int kHB = kHeld ? 4 * T : 1;
   double wo[T][kHB][4];
