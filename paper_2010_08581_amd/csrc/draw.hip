@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     }
     __syncthreads();
     if (live) {
-      // rin, rout are uniform: the guards below are scalar branches
+      // rin, rout are uniform (the copy's guard is a scalar branch)
       const double* Sj = S + sj * kSlice;
       if (k == 0) {
 #pragma unroll
@@ -202,14 +202,15 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
         double nr[RM];
 #pragma unroll
         for (int co = 0; co < RM; ++co) nr[co] = 0.0;
+        // Rows and columns past rin x rout read an element of the slice (finite) and add 0, or
+        // land in entries of nr that are never read: no branches, so the LDS reads of every
+        // step can be in flight together.
 #pragma unroll
         for (int ci = 0; ci < RM; ++ci) {
-          if (ci < rin) {
-            const double v = row[ci];
+          const double v = ci < rin ? row[ci] : 0.0;
+          const double* Sr = Sj + (ci < rin ? ci : rin - 1) * rout;
 #pragma unroll
-            for (int co = 0; co < RM; ++co)
-              if (co < rout) nr[co] = fma(v, Sj[ci * rout + co], nr[co]);
-          }
+          for (int co = 0; co < RM; ++co) nr[co] = fma(v, Sr[co < rout ? co : rout - 1], nr[co]);
         }
 #pragma unroll
         for (int c = 0; c < RM; ++c) row[c] = nr[c];
