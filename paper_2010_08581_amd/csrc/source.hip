@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
   const int64_t j0 = (int64_t)blockIdx.x * kFiberSamples;
   const int ns = a.J - j0 < kFiberSamples ? (int)(a.J - j0) : kFiberSamples;
   for (int e = threadIdx.x; e < ns * P; e += 256) s_t[e] = a.T[j0 * P + e];
-  if (threadIdx.x < ns) {
+  if ((int)threadIdx.x < ns) {
     const int32_t* ij = a.idx + (j0 + threadIdx.x) * K;
     int64_t b = 0;
     for (int k = 0; k < K; ++k) b += (int64_t)ij[k] * a.lin_stride[k];
