@@ -36,18 +36,22 @@ __device__ __forceinline__ float cvt_out<float>(double v) { return (float)v; }
 template <>
 __device__ __forceinline__ __bf16 cvt_out<__bf16>(double v) { return (__bf16)(float)v; }
 
-// one workgroup per 8 samples: their products T_j staged in LDS, one thread per (sample, i)
-constexpr int kFiberSamples = 8;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// The fibers of 16 samples are the product F = T G^T (16 x P times P x I_n, T the samples'
+// true-core chains, G the true core n's slices): one wave per 16 x 16 tile of F on
+// v_mfma_f64_16x16x4 (A(s, k) in lane s + 16 k, B(k, i) in lane i + 16 k, D(s, i) in lane
+// i + 16 (s % 4), register s / 4), four waves per workgroup along i (they share the T rows
+// through the cache).  The operands of twelve k-steps are loaded at once, without branches (past
+// P the A operand is 0), so a round costs one memory latency.  The noise term is added per entry.
+constexpr int kFiberSamples = 16;
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
-  extern __shared__ double s_t[];  // kFiberSamples x P
   __shared__ int64_t s_base[kFiberSamples];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In, K = a.K;
-  const double sigma = *a.sigma;
   const int64_t j0 = (int64_t)blockIdx.x * kFiberSamples;
   const int ns = a.J - j0 < kFiberSamples ? (int)(a.J - j0) : kFiberSamples;
-  for (int e = threadIdx.x; e < ns * P; e += 256) s_t[e] = a.T[j0 * P + e];
   if ((int)threadIdx.x < ns) {
     const int32_t* ij = a.idx + (j0 + threadIdx.x) * K;
     int64_t b = 0;
@@ -55,21 +59,39 @@ __global__ __launch_bounds__(256) void k_fibers(FiberArgs a) {
     s_base[threadIdx.x] = b;
   }
   __syncthreads();
-  const double* G = a.true_core;  // slice-major I_n x P
+  const int lane = threadIdx.x & 63;
+  const int i0 = ((int)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 16;
+  if (i0 >= In) return;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  // operand rows (clamped: rows past the samples or I_n are computed, not stored)
+  const double* Trow = a.T + (j0 + (r16 < ns ? r16 : ns - 1)) * (int64_t)P;
+  const double* Grow = a.true_core + (int64_t)(i0 + r16 < In ? i0 + r16 : In - 1) * P;
+  constexpr int kSteps = 12;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int p0 = 0; p0 < P; p0 += 4 * kSteps) {
+    double tv[kSteps], gv[kSteps];
+#pragma unroll
+    for (int q = 0; q < kSteps; ++q) {
+      const int p = p0 + 4 * q + k4;
+      const int pc = p < P ? p : P - 1;
+      tv[q] = (p < P ? 1.0 : 0.0) * Trow[pc];
+      gv[q] = Grow[pc];
+    }
+#pragma unroll
+    for (int q = 0; q < kSteps; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[q], gv[q], acc, 0, 0, 0);
+  }
+  const double sigma = *a.sigma;
   Tout* out = (Tout*)a.out;
-  for (int e = threadIdx.x; e < ns * In; e += 256) {
-    const int s = e / In, i = e - s * In;
-    const double* t = s_t + s * P;
-    const double* g = G + (int64_t)i * P;
-    double v = 0.0;
-    for (int p = 0; p < P; ++p) v = fma(g[p], t[p], v);
-    const int64_t lin = s_base[s] + (int64_t)i * a.lin_stride_n;
-    v += sigma * philox_normal((uint64_t)lin, a.noise_seed, a.noise_stream);
-    out[(j0 + s) * In + i] = cvt_out<Tout>(v);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int sm = 4 * r + k4, i = i0 + r16;
+    if (sm < ns && i < In) {
+      const int64_t lin = s_base[sm] + (int64_t)i * a.lin_stride_n;
+      const double v = acc[r] + sigma * philox_normal((uint64_t)lin, a.noise_seed, a.noise_stream);
+      out[(j0 + sm) * In + i] = cvt_out<Tout>(v);
+    }
   }
 }
-
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 // E[(a a') x (b b')] = sum_i A(a, i, b) B(a', i, b'); A, B slice-major (I, Ra0, Ra1), (I, Rb0, Rb1).
 // As a product: E is M = Ahat^T Bhat with its index pairs regrouped, where row i of Ahat is
@@ -182,11 +204,11 @@ hipError_t launch_dense_fit(const double* r2, double x2, double* fit, hipStream_
 }
 
 hipError_t launch_fibers(const FiberArgs& a, int out_dtype, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.J + kFiberSamples - 1) / kFiberSamples);
-  const size_t lds = (size_t)kFiberSamples * a.P * sizeof(double);
-  if (out_dtype == 0) k_fibers<double><<<blocks, 256, lds, s>>>(a);
-  else if (out_dtype == 1) k_fibers<float><<<blocks, 256, lds, s>>>(a);
-  else if (out_dtype == 2) k_fibers<__bf16><<<blocks, 256, lds, s>>>(a);
+  if (a.J < 1 || a.P < 1 || a.In < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.J + kFiberSamples - 1) / kFiberSamples), (unsigned)((a.In + 63) / 64));
+  if (out_dtype == 0) k_fibers<double><<<grid, 256, 0, s>>>(a);
+  else if (out_dtype == 1) k_fibers<float><<<grid, 256, 0, s>>>(a);
+  else if (out_dtype == 2) k_fibers<__bf16><<<grid, 256, 0, s>>>(a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
