@@ -199,7 +199,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the method runs on one GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(the method runs on one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
