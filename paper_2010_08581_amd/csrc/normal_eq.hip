@@ -149,19 +149,26 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
     const int buf = u & 1;
     const int base = (u * KG + g) * kKB;
     __syncthreads();
+    // A last round holding a single stage (group 0's; the other groups' would be padding) is
+    // shared: group 0 takes its first half of k-steps, group 1 the second half from group 0's
+    // buffer (the groups' sums are added below).
+    const bool lone = KG == 2 && u == rounds - 1 && (stages & 1);
+    const int sbase = lone ? u * KG * kKB : base;  // rows of the stage this group works on
     const Real* as = As + buf * kStageA;
     const Real* bs = Bs + buf * kStageB;
+    const Real* as2 = lone ? (const Real*)ne_smem + buf * kStageA : as;
+    const Real* bs2 = lone ? (const Real*)ne_smem + 2 * kStageA + buf * kStageB : bs;
     double wv[kKB / 4];
 #pragma unroll
-    for (int ks = 0; ks < kKB / 4; ++ks) wv[ks] = s_w[base + ks * 4 + k4];
-    mfma_steps(as, bs, wv, 0);
+    for (int ks = 0; ks < kKB / 4; ++ks) wv[ks] = s_w[sbase + ks * 4 + k4];
+    if (!lone || g == 0) mfma_steps(as, bs, wv, 0);
     __builtin_amdgcn_sched_barrier(0);
     if (u + 1 < rounds) {
       store_stage(buf ^ 1);
       if (u + 2 < rounds) load_stage(base + 2 * KG * kKB);
     }
     __builtin_amdgcn_sched_barrier(0);
-    mfma_steps(as, bs, wv, kKB / 8);
+    if (!lone || g == 1) mfma_steps(as2, bs2, wv, kKB / 8);
   }
   if constexpr (KG > 1) {
     // fixed-order sum of the groups' accumulators (group 0 + group 1 + ...)
