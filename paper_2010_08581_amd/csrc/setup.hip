@@ -12,10 +12,6 @@ template <typename T>
 __device__ __forceinline__ double to_f64(T v) {
   return static_cast<double>(v);
 }
-template <>
-__device__ __forceinline__ double to_f64<__hip_bfloat16>(__hip_bfloat16 v) {
-  return static_cast<double>(__bfloat162float(v));
-}
 template <typename T>
 __device__ __forceinline__ T from_f64(double v) {
   return static_cast<T>(v);
