@@ -194,6 +194,20 @@ def test_c4_full_size_video_lockstep():
     say(f"c4 worst core rel diff {worst:.3e}")
 
 
+def test_rank32_instances_fp64():
+    # ranks 26-30 (the 32-rank draw instance), P = 728-840 (the blocked factorisation over 46-53
+    # blocks, the widest triangular-solve instance) and a tall mode-0 core (800 x 728: its table
+    # from the blocked factorisation of the core Gram); the other cores are wide (uniform tables)
+    say("case: fp64 800x40x40 R=(26,30,28) J=3000 lockstep 3 updates (ranks up to 32)")
+    dims, ranks = (800, 40, 40), (26, 30, 28)
+    X = ring_tensor(random_cores(dims, ranks, rng_for(67, 1)))
+    X = X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(67, 2).standard_normal(dims)
+    init = random_cores(dims, ranks, rng_for(67, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 3000, precision="f64", init_cores=init)
+    worst = lockstep(t, X, 3, 3000, core_tol=1e-8)
+    say(f"worst core rel diff {worst:.3e}")
+
+
 def test_large_P_blocked_cholesky_fp64():
     # P = 168, 156, 182 (11-12 blocks of 16): the blocked multi-workgroup factorisation, with a
     # partial last 64-column step, for the normal equations and the (tall) core Grams
