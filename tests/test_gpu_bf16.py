@@ -59,6 +59,24 @@ def test_bf16_converged_fit_within_1e2_of_oracle(cfg, dims, ranks, J, sweeps):
     assert abs(fb - fo) <= 1e-2 * fo
 
 
+def test_bf16_lockstep_rank20():
+    # P = 400 (the BF16 contraction's 80-row tiles, the blocked factorisation, the 24-rank draw
+    # instance writing the transposed BF16 pair) on a 4-way tensor with a C = 3 mode like the
+    # video workload, built from rank-20 cores plus 1% noise; every core unfolding is wide
+    # (uniform tables).  Lockstep keeps each system at the oracle's conditioning: an
+    # over-parameterised free run (rank 20 on a small tensor of four blobs) drives the sampled
+    # systems to cond(A)^2 2^-9 > 1, beyond what BF16 operands resolve.
+    from synth import random_cores, ring_tensor, rng_for
+    say("case: bf16 lockstep 30x32x3x36 R=20 J=1500, 4 updates")
+    dims, ranks = (30, 32, 3, 36), (20,) * 4
+    X = ring_tensor(random_cores(dims, ranks, rng_for(68, 1)))
+    X = (X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(68, 2).standard_normal(dims)).astype(np.float32)
+    init = random_cores(dims, ranks, rng_for(68, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 1500, precision="bf16", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 4, 1500, core_tol=1e-2)
+    say(f"bf16 worst core rel diff {worst:.3e}")
+
+
 def test_bf16_fit_is_measured_against_fp32_x():
     # the BF16 form keeps an FP32 copy of X for the fit: with the same cores the fit equals the FP32 path's
     say("case: bf16 fit uses fp32 X")
