@@ -81,22 +81,44 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   // ---- draws ----
   int off[kMaxOrder];
   if (a.draw && a.tables_in_lds) {
-    int o = 0;
+    // The K tables are concatenated in LDS (table k at off[k]).  A wave copies 64-entry pieces,
+    // table and offset wave-uniform, eight pieces in flight, so all tables cost about one
+    // memory round trip.  With weights, one inclusive scan over the concatenation gives every
+    // table's sums offset by the total of the tables before it (exact in integers); the search
+    // below subtracts that base.
+    int o = 0, pieces = 0;
+    int first_piece[kMaxOrder];
     for (int k = 0; k < K; ++k) {
       int m = n + 1 + k;
       if (m >= N) m -= N;
       off[k] = o;
-      const int I = a.ring.dims[m];
-      copy_batched<kB>(tab + o, a.cdf.p[m], I, tid, kThreads);
-      o += I;
+      first_piece[k] = pieces;
+      o += a.ring.dims[m];
+      pieces += (a.ring.dims[m] + 63) / 64;
     }
-    __syncthreads();
-    if (a.weights)
-      for (int k = 0; k < K; ++k) {
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int kQ = 8;
+    for (int p0 = wave; p0 < pieces; p0 += 4 * kQ) {
+      uint64_t v[kQ];
+      int dst[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int pc = p0 + 4 * q;
+        int k = 0;
+        while (k + 1 < K && pc >= first_piece[k + 1]) ++k;
         int m = n + 1 + k;
         if (m >= N) m -= N;
-        lds_scan_u64(tab + off[k], a.ring.dims[m], s_wsum);
+        const int e = (pc - first_piece[k]) * 64 + lane;
+        const bool ok = pc < pieces && e < a.ring.dims[m];
+        v[q] = ok ? a.cdf.p[m][ok ? e : 0] : 0ull;
+        dst[q] = ok ? off[k] + e : -1;
       }
+#pragma unroll
+      for (int q = 0; q < kQ; ++q)
+        if (dst[q] >= 0) tab[dst[q]] = v[q];
+    }
+    __syncthreads();
+    if (a.weights) lds_scan_u64(tab, o, s_wsum);
   }
   if (tid < jb && !a.draw) {
     // given samples (same rows, no rescaling), or every index tuple in panel-row order
@@ -134,16 +156,18 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
         int m = n + 1 + k;
         if (m >= N) m -= N;
         const uint64_t* C = a.tables_in_lds ? tab + off[k] : a.cdf.p[m];
+        // base: the total of the tables before table k in the concatenated scan (else 0)
+        const uint64_t base = (a.tables_in_lds && a.weights && k > 0) ? C[-1] : 0ull;
         const int I = a.ring.dims[m];
-        const uint64_t T = C[I - 1];
-        const uint64_t t = __umul64hi(r, T);
+        const uint64_t T = C[I - 1] - base;
+        const uint64_t t = __umul64hi(r, T) + base;
         int lo = 0, hi = I - 1;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (C[mid] > t) hi = mid;
           else lo = mid + 1;
         }
-        const uint64_t Qi = C[lo] - (lo > 0 ? C[lo - 1] : 0ull);
+        const uint64_t Qi = C[lo] - (lo > 0 ? C[lo - 1] : base);
         q = q * ((double)Qi / (double)T);
         s_idx[tid * K + k] = lo;
         a.idx[j * K + k] = lo;
