@@ -196,23 +196,26 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     const int ssz = rin * rout;
     const double* core = a.cores.p[m];
     __syncthreads();  // draws visible / previous slices consumed
-    // stage the jb slices (rin x rout each, contiguous in slice-major storage)
+    // stage the jb slices (rin x rout each, contiguous in slice-major storage).  Element e is
+    // sample e / ssz, entry e mod ssz; the quotient comes from a float reciprocal, exact here
+    // (e < 256 ssz: the rounding stays below 1/(2 ssz), the distance of (e + 1/2)/ssz from an
+    // integer; checked for every ssz <= 32^2)
     const int tot = jb * ssz;
+    const float rs = 1.0f / (float)ssz;
     for (int base = 0; base < tot; base += kB * kThreads) {
       double v[kB];
+      int dst[kB];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
         const int e = base + tid + kThreads * q;
         const int ec = e < tot ? e : tot - 1;  // clamped: every load is in bounds
-        const int s = ec / ssz, o = ec - s * ssz;
-        v[q] = core[(int64_t)s_idx[s * K + k] * ssz + o];
+        const int smp = (int)(((float)ec + 0.5f) * rs), o = ec - smp * ssz;
+        v[q] = core[(int64_t)s_idx[smp * K + k] * ssz + o];
+        dst[q] = e < tot ? smp * kSlice + o : -1;
       }
 #pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const int e = base + tid + kThreads * q;
-        const int s = e / ssz, o = e - s * ssz;
-        if (e < tot) S[s * kSlice + o] = v[q];
-      }
+      for (int q = 0; q < kB; ++q)
+        if (dst[q] >= 0) S[dst[q]] = v[q];
     }
     __syncthreads();
     if (live) {
