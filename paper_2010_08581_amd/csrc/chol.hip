@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
 // work matrix a.Lg (the large-P path below), tolerance from a.scal[0]; its inverse goes to the
 // same blocks of a.W.
 template <bool kRegion>
-__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
+__device__ __forceinline__ void chol_body(const CholArgs& a) {
   extern __shared__ double lds[];
   __shared__ int s_fail;
   __shared__ double s_tol;
@@ -385,13 +385,20 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   }
 }
 
+template <bool kRegion>
+__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
+  chol_body<kRegion>(a);
+}
+
 // ---------------------------------------------------------------------------------------
 // Large P (more blocks than LDS holds): blocked over 64-column block columns (4 blocks), each
 // step spread over many workgroups.  The block-packed work matrix Lg holds H, then L; W holds
 // the inverse factor.  Step K: (1) k_chol<true> factors and inverts the diagonal region
 // (W_KK); (2) the panel below it, L_iK = A_iK W_KK^T; (3) the trailing update A_ij -= L_iK
-// L_jK^T.  Then the block rows of W follow one 64-row band at a time:
-// W_IJ = -W_II sum_{M=J}^{I-1} L_IM W_MJ.
+// L_jK^T.  The block rows of W follow one 64-row band at a time,
+// W_IJ = -W_II sum_{M=J}^{I-1} L_IM W_MJ; band I needs W_II and the bands above it only, so
+// it runs beside the factorisation of diagonal region I + 1 (extra workgroups of that launch),
+// and only the last band after the factorisation.
 
 // Lg <- H in blocks (identity on the padded diagonal); scal[0] <- P eps max_i H_ii
 __global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, int P, double* __restrict__ Lg,
@@ -467,12 +474,10 @@ __global__ __launch_bounds__(256) void k_big_trail(double* __restrict__ Lg, int 
 
 // band I (blocks 4I .. 4I + nbI - 1), one workgroup per band J < I: 16 waves, wave (r, c) the
 // output block (4I + r, 4J + c)
-__global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg, double* __restrict__ W, int nblk,
-                                                   int I, const int* status) {
+__device__ __forceinline__ void wrow_body(const double* __restrict__ Lg, double* __restrict__ W, int nblk, int I,
+                                          int J) {
   __shared__ double stage[16][16 * kLd];
-  if (*status != kDevOk) return;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
-  const int J = blockIdx.x;
   const int r = wave >> 2, c = wave & 3;
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
   const int bi = 4 * I + r, bj = 4 * J + c;
@@ -494,6 +499,22 @@ __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg
 #pragma unroll
   for (int q = 0; q < 4; ++q) w[q] = -w[q];
   store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
+}
+
+__global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg, double* __restrict__ W, int nblk,
+                                                   int I, const int* status) {
+  if (*status != kDevOk) return;
+  wrow_body(Lg, W, nblk, I, blockIdx.x);
+}
+
+// workgroup 0: step a.b0 / 4 of the factorisation (diagonal region); workgroups 1 .. I: band I
+// of W.  The band's workgroups do not read the status word: the factorisation workgroup may
+// set it meanwhile, and their indexing does not depend on the data.
+__global__ __launch_bounds__(1024) void k_chol_wrow(CholArgs a, int I) {
+  if (blockIdx.x == 0)
+    chol_body<true>(a);
+  else
+    wrow_body(a.Lg, a.W, (a.P + 15) / 16, I, (int)blockIdx.x - 1);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -730,7 +751,10 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s) {
     a.b0 = 4 * K;
     a.nb = nblk - a.b0 < 4 ? nblk - a.b0 : 4;
     const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb) * kBlk * sizeof(double);
-    k_chol<true><<<1, 1024, lds, s>>>(a);
+    if (K >= 2)
+      k_chol_wrow<<<(unsigned)K, 1024, lds, s>>>(a, K - 1);  // with band K - 1 (K - 1 workgroups)
+    else
+      k_chol<true><<<1, 1024, lds, s>>>(a);
     const int rows = nblk - a.b0 - a.nb;
     if (rows > 0) {
       k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status);
@@ -738,7 +762,7 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s) {
       k_big_trail<<<(unsigned)((pairs + 3) / 4), 256, 0, s>>>(a.Lg, nblk, a.b0, a.nb, a.status);
     }
   }
-  for (int I = 1; I < nb64; ++I) k_big_wrow<<<(unsigned)I, 1024, 0, s>>>(a.Lg, a.W, nblk, I, a.status);
+  if (nb64 >= 2) k_big_wrow<<<(unsigned)(nb64 - 1), 1024, 0, s>>>(a.Lg, a.W, nblk, nb64 - 1, a.status);
   return hipGetLastError();
 }
 
