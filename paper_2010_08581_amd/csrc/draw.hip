@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   double* S = lds;                                    // jb * kSlice
   double* s_w = S + (size_t)jb * kSlice;              // jb
   int32_t* s_idx = (int32_t*)(s_w + jb);              // jb * K (padded to even)
-  uint64_t* tab = (uint64_t*)(s_w + jb + (jb * K + 1) / 2);
+  double* s_p = s_w + jb + (jb * K + 1) / 2;          // jb * K: probability of each draw
+  uint64_t* tab = (uint64_t*)(s_p + jb * K);
   const int64_t j0 = (int64_t)blockIdx.x * jb;
   const int tid = threadIdx.x;
 
@@ -138,20 +139,21 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     }
     s_w[tid] = j < a.J ? 1.0 : 0.0;
     if (a.enumerate && j < a.J) a.w[j] = 1.0;
-  } else if (tid < jb) {
-    const int64_t j = j0 + tid;
-    if (j < a.J) {
-      uint64_t x[4] = {0, 0, 0, 0};
-      double q = 1.0;
-      for (int k = 0; k < K; ++k) {
+  } else if (a.draw) {
+    // one thread per (sample, table), consecutive threads on consecutive samples of one table:
+    // draw k of sample j is word k mod 4 of Philox block (j, k / 4); its probability goes to
+    // s_p, and the weight is formed after the next barrier, in table order
+    for (int e = tid; e < jb * K; e += kThreads) {
+      const int sl = e % jb, k = e / jb;
+      const int64_t j = j0 + sl;
+      if (j >= a.J) {
+        s_idx[sl * K + k] = 0;
+        continue;
+      }
+      {
+        uint64_t x[4] = {(uint64_t)j, (uint64_t)(k >> 2), a.u, 0};
+        philox4x64_10(x, a.seed, a.stream_id);
         const int word = k & 3;
-        if (word == 0) {
-          x[0] = (uint64_t)j;
-          x[1] = (uint64_t)(k >> 2);
-          x[2] = a.u;
-          x[3] = 0;
-          philox4x64_10(x, a.seed, a.stream_id);
-        }
         const uint64_t r = word == 0 ? x[0] : word == 1 ? x[1] : word == 2 ? x[2] : x[3];
         int m = n + 1 + k;
         if (m >= N) m -= N;
@@ -168,16 +170,10 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
           else lo = mid + 1;
         }
         const uint64_t Qi = C[lo] - (lo > 0 ? C[lo - 1] : base);
-        q = q * ((double)Qi / (double)T);
-        s_idx[tid * K + k] = lo;
+        s_p[sl * K + k] = (double)Qi / (double)T;
+        s_idx[sl * K + k] = lo;
         a.idx[j * K + k] = lo;
       }
-      const double w = 1.0 / sqrt((double)a.J * q);
-      s_w[tid] = w;
-      a.w[j] = w;
-    } else {
-      for (int k = 0; k < K; ++k) s_idx[tid * K + k] = 0;
-      s_w[tid] = 0.0;
     }
   }
 
@@ -196,6 +192,16 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     const int ssz = rin * rout;
     const double* core = a.cores.p[m];
     __syncthreads();  // draws visible / previous slices consumed
+    if (k == 0 && a.draw && tid < jb) {
+      // w = 1 / sqrt(J q), q the product of the sample's draw probabilities in table order
+      // (s_w is read by the sketch store only)
+      const int64_t j = j0 + tid;
+      double q = 1.0;
+      for (int kk = 0; kk < K; ++kk) q = q * s_p[tid * K + kk];
+      const double w = j < a.J ? 1.0 / sqrt((double)a.J * q) : 0.0;
+      s_w[tid] = w;
+      if (j < a.J) a.w[j] = w;
+    }
     // stage the jb slices (rin x rout each, contiguous in slice-major storage).  Element e is
     // sample e / ssz, entry e mod ssz; the quotient comes from a float reciprocal, exact here
     // (e < 256 ssz: the rounding stays below 1/(2 ssz), the distance of (e + 1/2)/ssz from an
@@ -304,7 +310,7 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   for (int k = 0; k < K; ++k) tbytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
   a.tables_in_lds = tbytes <= kDrawTableBytes;
   if (a.draw && a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
-  const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2) * sizeof(double);
+  const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2 + (size_t)jb * K) * sizeof(double);
   const size_t lds = head + (a.draw && a.tables_in_lds ? tbytes : 0);
   const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);
   switch (RM) {
