@@ -21,10 +21,10 @@
 // core in slice-major storage.)  Products run in FP64 from the FP64 cores; the row is
 // rounded once to the sketch type.
 //
-// One workgroup handles jb samples: jb threads draw (tables staged in LDS when they fit),
-// then thread (s, b) carries row b of M_s through the chain, the slices of all jb samples
-// staged in LDS (loads batched, one round trip per eight per thread), and the finished rows
-// leave through LDS as one contiguous store.
+// One workgroup handles jb samples: one thread per sample and table draws (tables staged in
+// LDS when they fit), then thread (s, b) carries row b of M_s through the chain, the slices
+// of all jb samples staged in LDS (loads batched, one round trip per kB per thread), and the
+// finished rows leave through LDS as one contiguous store.
 #include <type_traits>
 
 #include "kernels.h"
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   const int n = a.n;
   const int jb = a.jb;
   constexpr int kSlice = RM * RM + 1;  // odd stride in doubles: samples fall on distinct banks
-  constexpr int kB = 8;                // loads in flight per thread while staging
+  constexpr int kB = 16;               // loads in flight per thread while staging
   double* S = lds;                                    // jb * kSlice
   double* s_w = S + (size_t)jb * kSlice;              // jb
   int32_t* s_idx = (int32_t*)(s_w + jb);              // jb * K (padded to even)
@@ -213,11 +213,16 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       int dst[kB];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + tid + kThreads * q;
-        const int ec = e < tot ? e : tot - 1;  // clamped: every load is in bounds
-        const int smp = (int)(((float)ec + 0.5f) * rs), o = ec - smp * ssz;
-        v[q] = core[(int64_t)s_idx[smp * K + k] * ssz + o];
-        dst[q] = e < tot ? smp * kSlice + o : -1;
+        v[q] = 0.0;
+        dst[q] = -1;
+        // a sub-round wholly past the end is skipped (the test is uniform across the workgroup)
+        if (base + kThreads * q < tot) {
+          const int e = base + tid + kThreads * q;
+          const int ec = e < tot ? e : tot - 1;  // clamped: every load is in bounds
+          const int smp = (int)(((float)ec + 0.5f) * rs), o = ec - smp * ssz;
+          v[q] = core[(int64_t)s_idx[smp * K + k] * ssz + o];
+          dst[q] = e < tot ? smp * kSlice + o : -1;
+        }
       }
 #pragma unroll
       for (int q = 0; q < kB; ++q)
