@@ -471,9 +471,13 @@ int run_update(trals_ctx* h) {
   double* M = h->at<double>(h->L.M);
   double* F = h->at<double>(h->L.F);
   double* Bred = h->at<double>(h->L.Bred);  // I_n x P: row i = b_i
+  // H first; the right-hand sides are needed only by the solve, so for a single-workgroup
+  // factorisation they are reduced by extra workgroups of the factorisation's launch
+  const ReduceJob jobH{na.Hpart, (int64_t)P * P, 1, M}, jobB{na.Bpart, (int64_t)P * In, 2, Bred};
+  const bool b_beside = chol_single_workgroup(P);
   PROF_BEGIN(TRALS_K_REDUCE);
-  HIPTRY(launch_reduce_parts(ReduceJob{na.Hpart, (int64_t)P * P, 1, M}, ReduceJob{na.Bpart, (int64_t)P * In, 2, Bred},
-                             pl.splits, P, h->status(), h->stream));
+  HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, h->status(),
+                             h->stream));
   PROF_END(TRALS_K_REDUCE);
   CholArgs ca;
   memset(&ca, 0, sizeof(ca));
@@ -482,7 +486,7 @@ int run_update(trals_ctx* h) {
   ca.W = F;
   ca.status = h->status();
   PROF_BEGIN(TRALS_K_FACTOR);
-  HIPTRY(launch_chol(ca, h->stream));
+  HIPTRY(launch_chol(ca, h->stream, b_beside ? &jobB : nullptr, pl.splits));
   PROF_END(TRALS_K_FACTOR);
   TriArgs ta;
   memset(&ta, 0, sizeof(ta));

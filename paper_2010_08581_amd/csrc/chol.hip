@@ -17,6 +17,7 @@
 // D(i, j) in lane j + 16 (i % 4), register i / 4.  Register r of an accumulator therefore holds
 // exactly the B operand of k-step r of a following product.
 #include "kernels.h"
+#include "reduce.h"
 
 namespace trals {
 
@@ -390,6 +391,20 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   chol_body<kRegion>(a);
 }
 
+// workgroup 0: the factorisation (whole matrix in LDS); workgroups 1 ..: the fixed-order
+// reduction of job jb (the right-hand sides, read by the solve after this launch), four
+// 256-thread reduction blocks per workgroup.  The reduction does not read the status word:
+// the factorisation may set it meanwhile, and its indexing does not depend on the data.
+__global__ __launch_bounds__(1024) void k_chol_reduce(CholArgs a, ReduceJob jb, int nparts) {
+  __shared__ double red[4][4][kRedElems];
+  if (blockIdx.x == 0) {
+    chol_body<false>(a);
+    return;
+  }
+  const int sub = threadIdx.x >> 8;
+  reduce_block(jb, ((int64_t)blockIdx.x - 1) * 4 + sub, nparts, a.P, threadIdx.x & 255, red[sub]);
+}
+
 // ---------------------------------------------------------------------------------------
 // Large P (more blocks than LDS holds): blocked over 64-column block columns (4 blocks), each
 // step spread over many workgroups.  The block-packed work matrix Lg holds H, then L; W holds
@@ -732,12 +747,20 @@ hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const
   return hipGetLastError();
 }
 
-hipError_t launch_chol(const CholArgs& args, hipStream_t s) {
+bool chol_single_workgroup(int P) { return (P + 15) / 16 <= kLdsBlocks; }
+
+hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* beside, int nparts) {
   const int nblk = (args.P + 15) / 16;
   if (nblk > kMaxBlk) return hipErrorInvalidValue;
+  if (beside && !chol_single_workgroup(args.P)) return hipErrorInvalidValue;
   if (nblk <= kLdsBlocks) {
     const size_t lds = chol_work_doubles(args.P) * sizeof(double);
-    k_chol<false><<<1, 1024, lds, s>>>(args);
+    if (beside && beside->count > 0) {
+      const int64_t nred = (beside->count + kRedElems - 1) / kRedElems;
+      k_chol_reduce<<<(unsigned)(1 + (nred + 3) / 4), 1024, lds, s>>>(args, *beside, nparts);
+    } else {
+      k_chol<false><<<1, 1024, lds, s>>>(args);
+    }
     return hipGetLastError();
   }
   CholArgs a = args;

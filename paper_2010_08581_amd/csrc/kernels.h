@@ -120,7 +120,10 @@ struct CholArgs {
 };
 size_t chol_factor_doubles(int P);  // the block-packed factor W
 size_t chol_work_doubles(int P);    // W plus the staging blocks k_chol uses (size of CholArgs.W)
-hipError_t launch_chol(const CholArgs& a, hipStream_t s);
+// beside (optional, single-workgroup factorisations only): a reduction run by extra
+// workgroups of the same launch, independent of the factorisation
+hipError_t launch_chol(const CholArgs& a, hipStream_t s, const ReduceJob* beside = nullptr, int nparts = 0);
+bool chol_single_workgroup(int P);  // the factorisation runs as one workgroup (P <= 144)
 
 // With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
 // table weights Q_i = floor(||W g_i||^2 / P * 2^52) of the rows of Blev (In_lev x P, a core

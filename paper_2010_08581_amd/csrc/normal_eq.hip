@@ -22,6 +22,7 @@
 #include <hip/hip_ext.h>
 
 #include "kernels.h"
+#include "reduce.h"
 
 namespace trals {
 
@@ -328,47 +329,13 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   }
 }
 
-// out = sum over s of parts[s * count + e], in a fixed order: four threads per element sum the
-// partials s = g, g + 4, ... (g = 0..3) and the four sums are added in the order g = 0, 1, 2, 3.
-// mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower triangle,
-// out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n partials are written
-// transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P).
-constexpr int kRedElems = 64;
 // Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
 __global__ __launch_bounds__(256) void k_reduce_parts(ReduceJob j0, ReduceJob j1, int64_t nb0, int nparts, int P,
                                                       const int* status) {
   __shared__ double red[4][kRedElems];
   if (*status != kDevOk) return;
   const bool first = (int64_t)blockIdx.x < nb0;
-  const ReduceJob& jb = first ? j0 : j1;
-  const double* __restrict__ parts = jb.parts;
-  double* __restrict__ out = jb.out;
-  const int64_t count = jb.count;
-  const int mode = jb.mode;
-  const int g = threadIdx.x / kRedElems, el = threadIdx.x % kRedElems;
-  const int64_t e = ((int64_t)blockIdx.x - (first ? 0 : nb0)) * kRedElems + el;
-  double acc = 0.0;
-  if (e < count) {
-    int64_t src = e;
-    if (mode == 1) {
-      const int i = (int)(e / P), j = (int)(e % P);
-      src = i >= j ? e : (int64_t)j * P + i;
-    }
-#pragma unroll 4
-    for (int s = g; s < nparts; s += 4) acc += parts[s * count + src];
-  }
-  red[g][el] = acc;
-  __syncthreads();
-  if (g == 0 && e < count) {
-    const double v = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
-    if (mode == 2) {
-      const int64_t n = count / P;
-      const int64_t p = e / n, i = e - p * n;
-      out[i * P + p] = v;
-    } else {
-      out[e] = v;
-    }
-  }
+  reduce_block(first ? j0 : j1, (int64_t)blockIdx.x - (first ? 0 : nb0), nparts, P, threadIdx.x, red);
 }
 
 // e0/e1 (optional): events the runtime stamps at the kernel's own start and end
