@@ -219,3 +219,16 @@ def test_large_P_blocked_cholesky_fp64():
     t = TR(torch.tensor(X, device="cuda"), ranks, 600, precision="f64", init_cores=init)
     worst = lockstep(t, X, 4, 600, core_tol=1e-8)
     say(f"worst core rel diff {worst:.3e}")
+
+
+def test_single_workgroup_limit_fp64():
+    # P = 132, 144, 132 (9 blocks of 16): the largest factorisations held whole in one
+    # workgroup's LDS, with the right-hand-side reduction run beside them in the same launch
+    say("case: fp64 150x140x130 R=(12,12,11) J=700 lockstep 3 updates (P up to 144)")
+    dims, ranks = (150, 140, 130), (12, 12, 11)
+    X = ring_tensor(random_cores(dims, ranks, rng_for(68, 1)))
+    X = X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(68, 2).standard_normal(dims)
+    init = random_cores(dims, ranks, rng_for(68, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 700, precision="f64", init_cores=init)
+    worst = lockstep(t, X, 3, 700, core_tol=1e-8)
+    say(f"worst core rel diff {worst:.3e}")
