@@ -216,6 +216,19 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
       s_tol = a.scal[0];
       s_fail = 0;
     }
+    // the previous step's trailing update of this region, A_ij -= sum_c L(i, pb0 + c)
+    // L(j, pb0 + c)^T: the same products in the same order as for the blocks below the region
+    if (a.pnb > 0)
+      for (int sl = wave; sl < nslots; sl += kCholWaves) {
+        int bi, bj;
+        slot_ij(sl, bi, bj);
+        double* Ab = Ls + sl * kBlk;
+        d4 acc = load_acc(Ab, lane);
+        for (int c = 0; c < a.pnb; ++c)
+          acc = mma_abt(a.Lg + (int64_t)slot(g0 + bi, a.pb0 + c) * kBlk, a.Lg + (int64_t)slot(g0 + bj, a.pb0 + c) * kBlk,
+                        acc, lane, -1.0);
+        store_acc(Ab, acc, lane);
+      }
   } else if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < P; i += 64) mx = fmax(mx, Ls[slot(i >> 4, i >> 4) * kBlk + (i & 15) * kLd + (i & 15)]);
@@ -408,9 +421,11 @@ __global__ __launch_bounds__(1024) void k_chol_reduce(CholArgs a, ReduceJob jb, 
 // ---------------------------------------------------------------------------------------
 // Large P (more blocks than LDS holds): blocked over 64-column block columns (4 blocks), each
 // step spread over many workgroups.  The block-packed work matrix Lg holds H, then L; W holds
-// the inverse factor.  Step K: (1) k_chol<true> factors and inverts the diagonal region
+// the inverse factor.  Step K: (1) one workgroup factors and inverts the diagonal region
 // (W_KK); (2) the panel below it, L_iK = A_iK W_KK^T; (3) the trailing update A_ij -= L_iK
-// L_jK^T.  The block rows of W follow one 64-row band at a time,
+// L_jK^T, applied in the launch of step K + 1: to region K + 1 by its factorisation
+// workgroup before it factors, to the blocks below by extra workgroups.  The block rows of W
+// follow one 64-row band at a time,
 // W_IJ = -W_II sum_{M=J}^{I-1} L_IM W_MJ; band I needs W_II and the bands above it only, so
 // it runs beside the factorisation of diagonal region I + 1 (extra workgroups of that launch),
 // and only the last band after the factorisation.
@@ -469,17 +484,9 @@ __global__ __launch_bounds__(256) void k_big_panel(double* __restrict__ Lg, cons
     if (q < nb) store_acc(Lg + (int64_t)slot(i, b0 + q) * kBlk, acc[q], lane);
 }
 
-// one wave per trailing block (i, j), b0 + nb <= j <= i: A_ij -= sum_q L(i, b0 + q) L(j, b0 + q)^T
-__global__ __launch_bounds__(256) void k_big_trail(double* __restrict__ Lg, int nblk, int b0, int nb,
-                                                   const int* status) {
-  if (*status != kDevOk) return;
-  const int lane = threadIdx.x & 63;
-  const int q = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int t0 = b0 + nb, rem = nblk - t0;
-  if (q >= rem * (rem + 1) / 2) return;
-  int ii, jj;
-  slot_ij(q, ii, jj);
-  const int i = t0 + ii, j = t0 + jj;
+// trailing block (i, j) after the step on blocks b0 .. b0 + nb - 1 (b0 + nb <= j <= i), by one
+// wave: A_ij -= sum_q L(i, b0 + q) L(j, b0 + q)^T
+__device__ __forceinline__ void trail_block(double* __restrict__ Lg, int i, int j, int b0, int nb, int lane) {
   double* Aij = Lg + (int64_t)slot(i, j) * kBlk;
   d4 acc = load_acc(Aij, lane);
   for (int c = 0; c < nb; ++c)
@@ -522,14 +529,28 @@ __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg
   wrow_body(Lg, W, nblk, I, blockIdx.x);
 }
 
-// workgroup 0: step a.b0 / 4 of the factorisation (diagonal region); workgroups 1 .. I: band I
-// of W.  The band's workgroups do not read the status word: the factorisation workgroup may
-// set it meanwhile, and their indexing does not depend on the data.
-__global__ __launch_bounds__(1024) void k_chol_wrow(CholArgs a, int I) {
-  if (blockIdx.x == 0)
+// Step a.b0 / 4 > 0 of the factorisation in one launch.  Workgroup 0 applies the previous
+// step's trailing update to the diagonal region, then factors and inverts it; workgroups
+// 1 .. I take band I of W (I = 0: none); the rest apply the previous step's trailing update
+// to the blocks below the region, one block per wave.  Only workgroup 0 reads the status word:
+// it may set it meanwhile, and the others' indexing does not depend on the data.
+__global__ __launch_bounds__(1024) void k_chol_step(CholArgs a, int I) {
+  const int nblk = (a.P + 15) / 16;
+  if (blockIdx.x == 0) {
     chol_body<true>(a);
-  else
-    wrow_body(a.Lg, a.W, (a.P + 15) / 16, I, (int)blockIdx.x - 1);
+    return;
+  }
+  if ((int)blockIdx.x <= I) {
+    wrow_body(a.Lg, a.W, nblk, I, (int)blockIdx.x - 1);
+    return;
+  }
+  const int q = ((int)blockIdx.x - 1 - I) * kCholWaves + (int)(threadIdx.x >> 6);
+  const int rem = nblk - a.b0;  // the previous step's trailing blocks start at this region
+  if (q >= rem * (rem + 1) / 2) return;
+  int ii, jj;
+  slot_ij(q, ii, jj);
+  if (ii < a.nb) return;  // inside the region: workgroup 0 applies it
+  trail_block(a.Lg, a.b0 + ii, a.b0 + jj, a.pb0, a.pnb, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -773,17 +794,19 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
   for (int K = 0; K < nb64; ++K) {
     a.b0 = 4 * K;
     a.nb = nblk - a.b0 < 4 ? nblk - a.b0 : 4;
+    a.pb0 = K > 0 ? a.b0 - 4 : 0;  // every region but the last has four blocks
+    a.pnb = K > 0 ? 4 : 0;
     const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb) * kBlk * sizeof(double);
-    if (K >= 2)
-      k_chol_wrow<<<(unsigned)K, 1024, lds, s>>>(a, K - 1);  // with band K - 1 (K - 1 workgroups)
-    else
+    if (K == 0) {
       k_chol<true><<<1, 1024, lds, s>>>(a);
-    const int rows = nblk - a.b0 - a.nb;
-    if (rows > 0) {
-      k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status);
-      const int pairs = rows * (rows + 1) / 2;
-      k_big_trail<<<(unsigned)((pairs + 3) / 4), 256, 0, s>>>(a.Lg, nblk, a.b0, a.nb, a.status);
+    } else {
+      const int band = K >= 2 ? K - 1 : 0;  // band K - 1 of W: K - 1 workgroups
+      const int rem = nblk - a.b0;
+      const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
+      k_chol_step<<<(unsigned)(1 + band + tgroups), 1024, lds, s>>>(a, band);
     }
+    const int rows = nblk - a.b0 - a.nb;
+    if (rows > 0) k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status);
   }
   if (nb64 >= 2) k_big_wrow<<<(unsigned)(nb64 - 1), 1024, 0, s>>>(a.Lg, a.W, nblk, nb64 - 1, a.status);
   return hipGetLastError();

@@ -117,6 +117,8 @@ struct CholArgs {
   double* Lg;
   double* scal;
   int b0, nb;
+  int pb0, pnb;  // the previous step's region (pnb = 0: none), whose trailing update of this
+                 // region the step applies first
 };
 size_t chol_factor_doubles(int P);  // the block-packed factor W
 size_t chol_work_doubles(int P);    // W plus the staging blocks k_chol uses (size of CholArgs.W)
