@@ -301,7 +301,8 @@ template <typename TA>
 hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   int rmax = 0;
   for (int m = 0; m < a.ring.N; ++m) rmax = a.ring.ranks[m] > rmax ? a.ring.ranks[m] : rmax;
-  const int RM = rmax <= 4 ? 4 : rmax <= 8 ? 8 : rmax <= 12 ? 12 : rmax <= 16 ? 16 : rmax <= 20 ? 20 : rmax <= 24 ? 24 : 32;
+  const int RM = rmax <= 4 ? 4 : rmax <= 6 ? 6 : rmax <= 8 ? 8 : rmax <= 10 ? 10 : rmax <= 12 ? 12 : rmax <= 16 ? 16
+                 : rmax <= 20 ? 20 : rmax <= 24 ? 24 : 32;
   if (rmax > 32) return hipErrorInvalidValue;
   const int Rn = a.ring.ranks[a.n];
   // samples per workgroup: one thread per (sample, row b); slice staging within 64 KB
@@ -320,7 +321,9 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);
   switch (RM) {
     case 4: k_draw<TA, 4><<<blocks, kThreads, lds, s>>>(a); break;
+    case 6: k_draw<TA, 6><<<blocks, kThreads, lds, s>>>(a); break;
     case 8: k_draw<TA, 8><<<blocks, kThreads, lds, s>>>(a); break;
+    case 10: k_draw<TA, 10><<<blocks, kThreads, lds, s>>>(a); break;
     case 12: k_draw<TA, 12><<<blocks, kThreads, lds, s>>>(a); break;
     case 16: k_draw<TA, 16><<<blocks, kThreads, lds, s>>>(a); break;
     case 20: k_draw<TA, 20><<<blocks, kThreads, lds, s>>>(a); break;
