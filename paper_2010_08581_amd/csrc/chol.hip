@@ -158,8 +158,9 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
 // kRegion = true: the diagonal region of a.nb blocks starting at block a.b0 of the block-packed
 // work matrix a.Lg (the large-P path below), tolerance from a.scal[0]; its inverse goes to the
 // same blocks of a.W.
-template <bool kRegion>
+template <bool kRegion, int kW>
 __device__ __forceinline__ void chol_body(const CholArgs& a) {
+  constexpr int kThr = 64 * kW, kGroups = kThr / 256;  // threads; 256-thread groups
   extern __shared__ double lds[];
   __shared__ int s_fail;
   __shared__ double s_tol;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   double* Ls = lds;
   if (kRegion) {
-    for (int e = threadIdx.x; e < nslots * kBlk; e += 1024) {
+    for (int e = threadIdx.x; e < nslots * kBlk; e += kThr) {
       int bi, bj;
       slot_ij(e / kBlk, bi, bj);
       Ls[e] = a.Lg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk];
@@ -187,7 +188,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     // wave-uniform and walks four slots per load (no per-element index arithmetic).
     constexpr int kB = 8;
     const int r = (threadIdx.x >> 4) & 15, c = threadIdx.x & 15;
-    for (int base = 0; base < nslots; base += 4 * kB) {
+    for (int base = 0; base < nslots; base += kGroups * kB) {
       int sl = __builtin_amdgcn_readfirstlane(base + ((int)threadIdx.x >> 8));
       int bi, bj;
       slot_ij(sl, bi, bj);
@@ -197,17 +198,17 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         const int i = 16 * bi + r, j = 16 * bj + c;
         const bool in = sl < nslots && i < P && j < P;
         v[q] = in ? H[(int64_t)i * P + j] : (i == j ? 1.0 : 0.0);
-        bj += 4;  // next slot of this wave: four slots on
+        bj += kGroups;  // next slot of this wave: kGroups slots on
         while (bj > bi) {
           bj -= bi + 1;
           ++bi;
         }
-        sl += 4;
+        sl += kGroups;
       }
-      sl -= 4 * kB;
+      sl -= kGroups * kB;
 #pragma unroll
       for (int q = 0; q < kB; ++q)
-        if (sl + 4 * q < nslots) Ls[(sl + 4 * q) * kBlk + r * kLd + c] = v[q];
+        if (sl + kGroups * q < nslots) Ls[(sl + kGroups * q) * kBlk + r * kLd + c] = v[q];
     }
   }
   __syncthreads();
@@ -219,7 +220,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     // the previous step's trailing update of this region, A_ij -= sum_c L(i, pb0 + c)
     // L(j, pb0 + c)^T: the same products in the same order as for the blocks below the region
     if (a.pnb > 0)
-      for (int sl = wave; sl < nslots; sl += kCholWaves) {
+      for (int sl = wave; sl < nslots; sl += kW) {
         int bi, bj;
         slot_ij(sl, bi, bj);
         double* Ab = Ls + sl * kBlk;
@@ -255,8 +256,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
   // of column K and copies the block row of W into place from its staging blocks (nothing else
   // reads row K-2 any more).  Steps nblk and nblk+1 finish the last inverse and the last two
   // block rows.
-  constexpr int kHelpers = kCholWaves - 1;  // waves taking W block-row tasks (stride)
-  const int hw = kCholWaves - 1 - wave;     // 0: the inverse wave, 1.. : W block-row tasks
+  constexpr int kHelpers = kW - 1;  // waves taking W block-row tasks (stride)
+  const int hw = kW - 1 - wave;     // 0: the inverse wave, 1.. : W block-row tasks
   double* Stg = Ls + nslots * kBlk;         // nblk staging blocks for one block row of W
   for (int K = 0; K <= nblk + 1; ++K) {
     const bool factor = K < nblk;
@@ -265,7 +266,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     // ---- phase A: panel K ----
     // The diagonal block stays unmodified in memory during the panel (each pass loads its own
     // copy); the factored block goes to s_diag and is stored after the panel barrier.
-    for (int tri = wave; tri < triples; tri += kCholWaves) {
+    for (int tri = wave; tri < triples; tri += kW) {
       int bi = grp == 0 ? K : K + 3 * tri + grp;
       const bool held = grp == 0 || bi < nblk;
       if (!held) bi = K;
@@ -338,7 +339,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     if (K >= 1 && K < nblk && wave >= triples) {
       const int Kp = K - 1;
       const int rem = nblk - K - 1;  // rows and columns K+1 .. nblk-1
-      for (int q = wave - triples; q < rem * (rem + 1) / 2; q += kCholWaves - triples) {
+      for (int q = wave - triples; q < rem * (rem + 1) / 2; q += kW - triples) {
         int ii, jj;
         slot_ij(q, ii, jj);
         const int i = K + 1 + ii, j = K + 1 + jj;
@@ -370,10 +371,10 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     if (factor) {
       // factored diagonal block into place (no one reads slot (K, K) during the trailing update)
       double* DK = Ls + slot(K, K) * kBlk;
-      for (int e = threadIdx.x; e < 16 * kLd; e += 1024) DK[e] = s_diag[e];
+      for (int e = threadIdx.x; e < 16 * kLd; e += kThr) DK[e] = s_diag[e];
       // trailing update A_ij -= L_iK L_jK^T, block column K+1 only (the next panel); the
       // columns beyond it are updated during the next panel
-      for (int ii = wave; ii < below; ii += kCholWaves) {
+      for (int ii = wave; ii < below; ii += kW) {
         const int i = K + 1 + ii, j = K + 1;
         double* Aij = Ls + slot(i, j) * kBlk;
         d4 acc = load_acc(Aij, lane);
@@ -384,38 +385,39 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     if (I >= 1) {
       // blocks (I, 0 .. I-1) are contiguous slots: one flat copy
       double* dst = Ls + slot(I, 0) * kBlk;
-      for (int e = threadIdx.x; e < I * kBlk; e += 1024) dst[e] = Stg[e];
+      for (int e = threadIdx.x; e < I * kBlk; e += kThr) dst[e] = Stg[e];
     }
     __syncthreads();
   }
   if (kRegion) {
-    for (int e = threadIdx.x; e < nslots * kBlk; e += 1024) {
+    for (int e = threadIdx.x; e < nslots * kBlk; e += kThr) {
       int bi, bj;
       slot_ij(e / kBlk, bi, bj);
       Wg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk] = Ls[e];
     }
   } else {
-    copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, 1024);
+    copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, kThr);
   }
 }
 
-template <bool kRegion>
-__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
-  chol_body<kRegion>(a);
+template <bool kRegion, int kW>
+__global__ __launch_bounds__(64 * kW) void k_chol(CholArgs a) {
+  chol_body<kRegion, kW>(a);
 }
 
 // workgroup 0: the factorisation (whole matrix in LDS); workgroups 1 ..: the fixed-order
-// reduction of job jb (the right-hand sides, read by the solve after this launch), four
+// reduction of job jb (the right-hand sides, read by the solve after this launch), kW / 4
 // 256-thread reduction blocks per workgroup.  The reduction does not read the status word:
 // the factorisation may set it meanwhile, and its indexing does not depend on the data.
-__global__ __launch_bounds__(1024) void k_chol_reduce(CholArgs a, ReduceJob jb, int nparts) {
-  __shared__ double red[4][4][kRedElems];
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void k_chol_reduce(CholArgs a, ReduceJob jb, int nparts) {
+  __shared__ double red[kW / 4][4][kRedElems];
   if (blockIdx.x == 0) {
-    chol_body<false>(a);
+    chol_body<false, kW>(a);
     return;
   }
   const int sub = threadIdx.x >> 8;
-  reduce_block(jb, ((int64_t)blockIdx.x - 1) * 4 + sub, nparts, a.P, threadIdx.x & 255, red[sub]);
+  reduce_block(jb, ((int64_t)blockIdx.x - 1) * (kW / 4) + sub, nparts, a.P, threadIdx.x & 255, red[sub]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg
 __global__ __launch_bounds__(1024) void k_chol_step(CholArgs a, int I) {
   const int nblk = (a.P + 15) / 16;
   if (blockIdx.x == 0) {
-    chol_body<true>(a);
+    chol_body<true, kCholWaves>(a);
     return;
   }
   if ((int)blockIdx.x <= I) {
@@ -776,11 +778,19 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
   if (beside && !chol_single_workgroup(args.P)) return hipErrorInvalidValue;
   if (nblk <= kLdsBlocks) {
     const size_t lds = chol_work_doubles(args.P) * sizeof(double);
+    // eight waves for up to four blocks (the panel steps dominate; fewer waves share a SIMD
+    // with the panel wave), sixteen above
+    const bool small = nblk <= 4;
     if (beside && beside->count > 0) {
       const int64_t nred = (beside->count + kRedElems - 1) / kRedElems;
-      k_chol_reduce<<<(unsigned)(1 + (nred + 3) / 4), 1024, lds, s>>>(args, *beside, nparts);
+      if (small)
+        k_chol_reduce<8><<<(unsigned)(1 + (nred + 1) / 2), 512, lds, s>>>(args, *beside, nparts);
+      else
+        k_chol_reduce<16><<<(unsigned)(1 + (nred + 3) / 4), 1024, lds, s>>>(args, *beside, nparts);
+    } else if (small) {
+      k_chol<false, 8><<<1, 512, lds, s>>>(args);
     } else {
-      k_chol<false><<<1, 1024, lds, s>>>(args);
+      k_chol<false, 16><<<1, 1024, lds, s>>>(args);
     }
     return hipGetLastError();
   }
@@ -798,7 +808,7 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     a.pnb = K > 0 ? 4 : 0;
     const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb) * kBlk * sizeof(double);
     if (K == 0) {
-      k_chol<true><<<1, 1024, lds, s>>>(a);
+      k_chol<true, kCholWaves><<<1, 1024, lds, s>>>(a);
     } else {
       const int band = K >= 2 ? K - 1 : 0;  // band K - 1 of W: K - 1 workgroups
       const int rem = nblk - a.b0;
