@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
 }
 
 // ---------------------------------------------------------------------------------------
-// Cholesky factorisation and inverse factor, one workgroup of 16 waves.
+// Cholesky factorisation and inverse factor, one workgroup of kW waves (8 or 16).
 //
 // Right-looking over 16-column panels.  Panel K: the panel waves each hold the 16 rows of the
 // diagonal block (lanes 0-15, identical copies) and three sub-diagonal block rows (lanes
