@@ -144,7 +144,7 @@ int trals_create_generated(const trals_desc* desc, const trals_source* src, void
  * order), continuing from the handle's update counter. */
 int trals_sweep(trals_handle h, int32_t n_sweeps);
 
-/* Sample count of the following updates (Section 3.5: J may change between updates at no
+/* Sample count of the following updates (Section 3.2, Adaptive Sample Size: J may change between updates at no
  * cost).  Sampled methods only; samples in [max_n R[n-1]*R[n], the J given at creation] (the
  * workspace was sized for that J).  trals_samples returns the current J (-1 for NULL). */
 int trals_set_samples(trals_handle h, int64_t samples);
@@ -154,7 +154,7 @@ int64_t trals_samples(trals_handle h);
  * G_n(:,i,:), O(sum_n I_n R^4) work, no pass over X).  Synchronises the stream. */
 int trals_tr_norm(trals_handle h, double* norm);
 
-/* Termination by the change of ||TR(G)||_F (Section 3.4): run whole sweeps until
+/* Termination by the change of ||TR(G)||_F (Section 3.1, Termination Criteria): run whole sweeps until
  * |n_k - n_{k-1}| / n_k < rel_tol after sweep k, or max_sweeps sweeps.  Reports the sweeps run
  * and the last relative change (-1 if none).  Synchronises once per sweep. */
 int trals_sweep_until(trals_handle h, int32_t max_sweeps, double rel_tol, int32_t* sweeps_done,

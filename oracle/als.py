@@ -133,7 +133,7 @@ def tr_als_sampled(X, init_cores, J, sweeps, seed=0, stream_id=0, record=None, u
     """Algorithm 2 with a fixed number of sweeps (the paper's experiments fix
     the iteration count, Section 4.1).  ``record`` (a list) receives
     (u, n, idx, w) for every update.  ``J`` may be a function of the update
-    number u (the sample size can change between updates, Section 3.5).
+    number u (the sample size can change between updates, Section 3.2).
     ``uniform`` draws from uniform distributions instead of eq. (3);
     ``normalize`` applies ``normalize_core`` after every update.
     Returns the list of cores."""
@@ -179,6 +179,6 @@ def tr_als_exact(X, init_cores, sweeps, normalize=False):
 
 
 def fit_error(cores, X):
-    """Relative error ||TR(cores) - X||_F / ||X||_F (Section 3.2, Section 4.1)."""
+    """Relative error ||TR(cores) - X||_F / ||X||_F (Section 3.1, Section 4.1)."""
     X = np.asarray(X, dtype=np.float64)
     return float(np.linalg.norm((tr_full(cores) - X).ravel()) / np.linalg.norm(X.ravel()))

@@ -30,7 +30,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, gauge, partial, scal, total;
+  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -217,11 +217,21 @@ void plan(const Problem& p, Layout* L) {
   L->F = take(chol_work_doubles(p.Pmax) * 8);
   L->F2 = take(chol_work_doubles(p.Pmax) * 8);
   L->gauge = take(gauge_work_doubles() * 8);
+  {
+    // pivoted-QR work copy of the largest core unfolding (rank-revealing table path)
+    size_t qr = 0;
+    if (p.method == TRALS_LEVERAGE)
+      for (int n = 0; n < p.N; ++n) {
+        const size_t c = (size_t)p.dims[n] * P_of(p, n);
+        qr = c > qr ? c : qr;
+      }
+    L->qr = take(qr * 8);
+  }
   const int64_t fit_rows = p.generated ? 0 : p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
-  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status
+  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [20] int table breakdown
   L->total = off;
 }
 
@@ -260,6 +270,7 @@ struct trals_ctx {
   template <typename T>
   T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
   int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
+  int* table_fail() { return reinterpret_cast<int*>(ws + L.scal + 20); }
   double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
   unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
 };
@@ -313,8 +324,13 @@ hipError_t prof_pair(trals_ctx* h, int k, hipEvent_t* e0, hipEvent_t* e1) {
 
 Ring make_ring(const Problem& p) { return ring_of(p, p.ranks); }
 
-// Sampling table of core m from the core itself (creation, set_cores): eq. (3) via the Gram
-// of G_(2), its inverse factor and the leverage rows, scanned in place.
+// Sampling table of core m (eq. (3), Definition 4) from the core itself, scanned in place
+// when the draws take inclusive sums.  The numerical rank decides the reading:
+//  * tall (I > P): the column Gram K = G^T G factored with the table tolerance; if it factors,
+//    G_(2) has full column rank and l_i = ||W g_i||^2 (W = L^{-1}); otherwise the leverage
+//    rows' launch takes the table from the pivoted QR of G_(2) (rank-revealing);
+//  * wide (I <= P): the row Gram G G^T factored likewise; if it factors, G_(2) has full row
+//    rank and p_i = 1/I exactly; otherwise the pivoted-QR table.
 int compute_table(trals_ctx* h, int m) {
   const Problem& p = h->p;
   const int P = P_of(p, m);
@@ -326,16 +342,18 @@ int compute_table(trals_ctx* h, int m) {
     return TRALS_OK;
   }
   PROF_BEGIN(TRALS_K_TABLE);
+  double* M2 = h->at<double>(h->L.M2);
+  double* F2 = h->at<double>(h->L.F2);
   if (p.method == TRALS_LEVERAGE && I > P) {
-    double* M2 = h->at<double>(h->L.M2);
-    double* F2 = h->at<double>(h->L.F2);
-    HIPTRY(launch_syrk(core, I, P, M2, h->status(), h->stream));
+    HIPTRY(launch_syrk(core, I, P, M2, h->status(), h->stream, /*trans=*/false, h->table_fail()));
     CholArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.P = P;
     ca.H = M2;
     ca.W = F2;
     ca.status = h->status();
+    ca.fail = h->table_fail();
+    ca.rel_tol = kTableRelTol;
     HIPTRY(launch_chol(ca, h->stream));
     TriArgs ta;
     memset(&ta, 0, sizeof(ta));
@@ -345,7 +363,23 @@ int compute_table(trals_ctx* h, int m) {
     ta.Blev = core;
     ta.Q = Q;
     ta.status = h->status();
+    ta.lev_fail = h->table_fail();
+    ta.qr_work = h->at<double>(h->L.qr);
     HIPTRY(launch_trisolve(ta, h->stream));
+  } else if (p.method == TRALS_LEVERAGE) {
+    LevWideArgs la;
+    memset(&la, 0, sizeof(la));
+    la.G = core;
+    la.I = I;
+    la.P = P;
+    la.K = M2;
+    la.F = F2;
+    la.qr_work = h->at<double>(h->L.qr);
+    la.Q = Q;
+    la.status = h->status();
+    la.fail = h->table_fail();
+    la.rel_tol = kTableRelTol;
+    HIPTRY(launch_lev_wide(la, h->stream));
   } else {
     HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
   }

@@ -16,7 +16,10 @@
 // v_mfma_f64_16x16x4 layouts (one wave): A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k,
 // D(i, j) in lane j + 16 (i % 4), register i / 4.  Register r of an accumulator therefore holds
 // exactly the B operand of k-step r of a following product.
+#include <string.h>
+
 #include "kernels.h"
+#include "levqr.h"
 #include "reduce.h"
 
 namespace trals {
@@ -100,14 +103,17 @@ __device__ __forceinline__ void store_acc(Ptr C, d4 v, int lane) {
 
 // ---------------------------------------------------------------------------------------
 // K = A^T A (P x P, row-major; the lower blocks including full diagonal blocks are written)
-// for A = rows x P row-major.  One workgroup of 16 waves per lower block; wave w takes the
-// 4-row k-steps w, w + 16, ... (eight loads in flight) and the wave sums are added in the
-// order 0, 1, ..., 15.
+// for A = rows x P, row-major, or column-major when kTrans (element (r, c) at c * rows + r).
+// One workgroup of 16 waves per lower block; wave w takes the 4-row k-steps w, w + 16, ...
+// (eight loads in flight) and the wave sums are added in the order 0, 1, ..., 15.
 constexpr int kSyrkWaves = 16;
+template <bool kTrans>
 __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restrict__ A, int64_t rows, int P,
-                                                          double* __restrict__ Kout, const int* status) {
+                                                          double* __restrict__ Kout, const int* status,
+                                                          int* clear) {
   __shared__ double red[kSyrkWaves - 1][4][64];
   if (*status != kDevOk) return;
+  if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
   int bi, bj;
   slot_ij(blockIdx.x, bi, bj);
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
@@ -123,8 +129,8 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
     for (int u = 0; u < 8; ++u) {
       const int64_t r = 4 * (k0 + (int64_t)u * kSyrkWaves) + k4;
       const int64_t rc = r < rows ? r : rows - 1;
-      va[u] = (r < rows ? mi : 0.0) * A[rc * P + cic];
-      vb[u] = A[rc * P + cjc];
+      va[u] = (r < rows ? mi : 0.0) * (kTrans ? A[cic * rows + rc] : A[rc * P + cic]);
+      vb[u] = kTrans ? A[cjc * rows + rc] : A[rc * P + cjc];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc = mfma(va[u], vb[u], acc);
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
 // work matrix a.Lg (the large-P path below), tolerance from a.scal[0]; its inverse goes to the
 // same blocks of a.W.
 template <bool kRegion, int kW>
-__device__ __forceinline__ void chol_body(const CholArgs& a) {
+__device__ __forceinline__ bool chol_body(const CholArgs& a) {
   constexpr int kThr = 64 * kW, kGroups = kThr / 256;  // threads; 256-thread groups
   extern __shared__ double lds[];
   __shared__ int s_fail;
@@ -167,7 +173,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
   __shared__ double s_rdiag[16 * kMaxBlk];  // 1 / L_ii
   __shared__ double s_diag[16 * kLd];       // factored diagonal block of the current panel
   __shared__ double s_lt[16 * 16];          // transpose of the diagonal block being inverted
-  if (*a.status != kDevOk) return;
+  if (*a.status != kDevOk || (a.fail && *a.fail)) return false;
+  int* const fail_out = a.fail ? a.fail : a.status;
   const int P = a.P;
   const double* H = a.H;
   double* Wg = a.W;
@@ -236,14 +243,14 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     if (lane == 0) {
-      s_tol = (double)P * 2.220446049250313e-16 * mx;
+      s_tol = (a.rel_tol > 0.0 ? a.rel_tol : (double)P * 2.220446049250313e-16) * mx;
       s_fail = !(mx > 0.0) || !isfinite(mx);
     }
   }
   __syncthreads();
   if (s_fail) {
-    if (threadIdx.x == 0) *a.status = kDevSingular;
-    return;
+    if (threadIdx.x == 0) *fail_out = kDevSingular;
+    return false;
   }
   const double tol = s_tol;
   const int l = lane & 15, grp = lane >> 4;
@@ -364,8 +371,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     }
     __syncthreads();
     if (factor && s_fail) {
-      if (threadIdx.x == 0) *a.status = kDevSingular;
-      return;
+      if (threadIdx.x == 0) *fail_out = kDevSingular;
+      return false;
     }
     // ---- phase B ----
     if (factor) {
@@ -398,6 +405,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
   } else {
     copy_batched<4>((double2*)Wg, (const double2*)Ls, (int64_t)nslots * kBlk / 2, threadIdx.x, kThr);
   }
+  return true;
 }
 
 template <bool kRegion, int kW>
@@ -432,9 +440,10 @@ __global__ __launch_bounds__(64 * kW) void k_chol_reduce(CholArgs a, ReduceJob j
 // it runs beside the factorisation of diagonal region I + 1 (extra workgroups of that launch),
 // and only the last band after the factorisation.
 
-// Lg <- H in blocks (identity on the padded diagonal); scal[0] <- P eps max_i H_ii
+// Lg <- H in blocks (identity on the padded diagonal); scal[0] <- tol max_i H_ii (tol = rel_tol,
+// or P eps when rel_tol is 0); a zero or non-finite diagonal is a breakdown (*fail_out)
 __global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, int P, double* __restrict__ Lg,
-                                                  double* scal, int* status) {
+                                                  double* scal, const int* status, int* fail_out, double rel_tol) {
   if (*status != kDevOk) return;
   const int nblk = (P + 15) / 16;
   const int64_t total = (int64_t)nblk * (nblk + 1) / 2 * kBlk;
@@ -459,16 +468,16 @@ __global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, 
     }
     if (threadIdx.x == 0) {
       mx = red[0];
-      scal[0] = (double)P * 2.220446049250313e-16 * mx;
-      if (!(mx > 0.0) || !isfinite(mx)) *status = kDevSingular;
+      scal[0] = (rel_tol > 0.0 ? rel_tol : (double)P * 2.220446049250313e-16) * mx;
+      if (!(mx > 0.0) || !isfinite(mx)) *fail_out = kDevSingular;
     }
   }
 }
 
 // one wave per block row i >= b0 + nb: L(i, b0 + q) = sum_{c <= q} A(i, b0 + c) W(b0 + q, b0 + c)^T
 __global__ __launch_bounds__(256) void k_big_panel(double* __restrict__ Lg, const double* __restrict__ W, int nblk,
-                                                   int b0, int nb, const int* status) {
-  if (*status != kDevOk) return;
+                                                   int b0, int nb, const int* status, const int* fail) {
+  if (*status != kDevOk || (fail && *fail)) return;
   const int lane = threadIdx.x & 63;
   const int i = b0 + nb + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (i >= nblk) return;
@@ -526,8 +535,8 @@ __device__ __forceinline__ void wrow_body(const double* __restrict__ Lg, double*
 }
 
 __global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg, double* __restrict__ W, int nblk,
-                                                   int I, const int* status) {
-  if (*status != kDevOk) return;
+                                                   int I, const int* status, const int* fail) {
+  if (*status != kDevOk || (fail && *fail)) return;
   wrow_body(Lg, W, nblk, I, blockIdx.x);
 }
 
@@ -571,6 +580,12 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   const int nblk = (P + 15) / 16;
   const bool lev = (int)blockIdx.x >= a.solve_groups;
   const int grp = lev ? (int)blockIdx.x - a.solve_groups : (int)blockIdx.x;
+  if (lev && a.lev_fail && *a.lev_fail) {
+    // the core Gram did not factor: the first table workgroup takes the whole table from the
+    // pivoted QR of the core (its dynamic LDS, 16 nblk rows of 17 doubles, holds the scratch)
+    if (grp == 0) lev_qr_table(a.Blev, a.In_lev, P, a.qr_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
+    return;
+  }
   const double* W = lev ? a.Wlev : a.Wsol;
   const double* Bsrc = lev ? a.Blev : a.Bsol;
   const int In = lev ? a.In_lev : a.In_sol;
@@ -741,6 +756,72 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Table of a wide core (I <= P) in one workgroup: the row Gram K = G G^T (lower blocks, into
+// a.K), its factorisation in LDS with the table tolerance, then the uniform table if it
+// factored, else the pivoted-QR table.
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca) {
+  extern __shared__ double lw_smem[];
+  __shared__ int s_wide_fail;
+  if (*a.status != kDevOk) return;
+  const int I = a.I, P = a.P;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int nb = (I + 15) / 16, nslots = nb * (nb + 1) / 2;
+  if (threadIdx.x == 0) s_wide_fail = 0;
+  for (int sl = wave; sl < nslots; sl += kW) {
+    int bi, bj;
+    slot_ij(sl, bi, bj);
+    const int ri = 16 * bi + r16, rj = 16 * bj + r16;
+    const double* gi = a.G + (int64_t)(ri < I ? ri : I - 1) * P;
+    const double* gj = a.G + (int64_t)(rj < I ? rj : I - 1) * P;
+    const double mi = ri < I ? 1.0 : 0.0;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // D(i, j) = sum_p G(16 bi + i, p) G(16 bj + j, p): A(i, k) in lane i + 16 k, B(k, j) in
+    // lane j + 16 k, both read along a row of G
+    for (int p0 = 0; p0 < P; p0 += 4) {
+      const int pp = p0 + k4;
+      const double va = pp < P ? mi * gi[pp] : 0.0;
+      const double vb = pp < P ? gj[pp] : 0.0;
+      acc = mfma(va, vb, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * bi + 4 * q + k4, col = 16 * bj + r16;
+      if (row < I && col < I) a.K[(int64_t)row * I + col] = acc[q];
+    }
+  }
+  __syncthreads();
+  CholArgs c = ca;
+  c.fail = &s_wide_fail;
+  const bool ok = chol_body<false, kW>(c);
+  __syncthreads();
+  if (ok) {
+    const double pr = 1.0 / (double)I;  // full row rank: p_i = l_i / rank = 1 / I
+    const uint64_t q = (uint64_t)floor(pr * 4503599627370496.0);
+    for (int i = threadIdx.x; i < I; i += 64 * kW) a.Q[i] = q;
+  } else {
+    lev_qr_table(a.G, I, P, a.qr_work, a.Q, a.status, (unsigned char*)lw_smem, threadIdx.x, 64 * kW);
+  }
+}
+
+// Table from the breakdown word of a factorisation run before: uniform if it factored (a wide
+// core's row Gram), else the pivoted QR of G.
+__global__ __launch_bounds__(1024) void k_lev_fallback(const double* __restrict__ G, int I, int P,
+                                                       double* __restrict__ qr_work, uint64_t* __restrict__ Q,
+                                                       const int* fail, int* status) {
+  extern __shared__ unsigned char lf_smem[];
+  if (*status != kDevOk) return;
+  if (*fail == 0) {
+    const double pr = 1.0 / (double)I;
+    const uint64_t q = (uint64_t)floor(pr * 4503599627370496.0);
+    for (int i = threadIdx.x; i < I; i += 1024) Q[i] = q;
+    return;
+  }
+  lev_qr_table(G, I, P, qr_work, Q, status, lf_smem, threadIdx.x, 1024);
+}
+
 hipError_t trisolve_dispatch(const TriArgs& a, int nblk, unsigned grid, size_t lds, hipStream_t s) {
   if (nblk <= 4) k_trisolve<1><<<grid, 256, lds, s>>>(a);
   else if (nblk <= 8) k_trisolve<2><<<grid, 256, lds, s>>>(a);
@@ -763,10 +844,15 @@ size_t chol_work_doubles(int P) {
   return 2 * chol_factor_doubles(P) + 8;                                        // W, work matrix, tolerance
 }
 
-hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s) {
+hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s,
+                       bool trans, int* clear) {
   const int nblk = (P + 15) / 16;
   if (nblk > kMaxBlk || rows < 1) return hipErrorInvalidValue;
-  k_syrk<<<(unsigned)(nblk * (nblk + 1) / 2), 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status);
+  const unsigned grid = (unsigned)(nblk * (nblk + 1) / 2);
+  if (trans)
+    k_syrk<true><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear);
+  else
+    k_syrk<false><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear);
   return hipGetLastError();
 }
 
@@ -799,7 +885,7 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
   a.scal = a.W + 2 * chol_factor_doubles(a.P);
   const int nslots = nblk * (nblk + 1) / 2;
   k_big_init<<<(unsigned)((nslots * kBlk + 255) / 256 < 1024 ? (nslots * kBlk + 255) / 256 : 1024), 256, 0, s>>>(
-      a.H, a.P, a.Lg, a.scal, a.status);
+      a.H, a.P, a.Lg, a.scal, a.status, a.fail ? a.fail : a.status, a.rel_tol);
   const int nb64 = (nblk + 3) / 4;
   for (int K = 0; K < nb64; ++K) {
     a.b0 = 4 * K;
@@ -810,16 +896,55 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     if (K == 0) {
       k_chol<true, kCholWaves><<<1, 1024, lds, s>>>(a);
     } else {
-      const int band = K >= 2 ? K - 1 : 0;  // band K - 1 of W: K - 1 workgroups
+      // band K - 1 of W: K - 1 workgroups (none when only the factor's regions are needed)
+      const int band = (K >= 2 && !a.factor_only) ? K - 1 : 0;
       const int rem = nblk - a.b0;
       const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
       k_chol_step<<<(unsigned)(1 + band + tgroups), 1024, lds, s>>>(a, band);
     }
     const int rows = nblk - a.b0 - a.nb;
-    if (rows > 0) k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status);
+    if (rows > 0)
+      k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status, a.fail);
   }
-  if (nb64 >= 2) k_big_wrow<<<(unsigned)(nb64 - 1), 1024, 0, s>>>(a.Lg, a.W, nblk, nb64 - 1, a.status);
+  if (nb64 >= 2 && !a.factor_only)
+    k_big_wrow<<<(unsigned)(nb64 - 1), 1024, 0, s>>>(a.Lg, a.W, nblk, nb64 - 1, a.status, a.fail);
   return hipGetLastError();
+}
+
+hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
+                               int* status, hipStream_t s) {
+  k_lev_fallback<<<1, 1024, lev_qr_smem_bytes(P), s>>>(G, I, P, qr_work, Q, fail, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
+  if (a.I > a.P || a.I < 1 || (a.P + 15) / 16 > kMaxBlk) return hipErrorInvalidValue;
+  CholArgs ca;
+  memset(&ca, 0, sizeof(ca));
+  ca.P = a.I;
+  ca.H = a.K;
+  ca.W = a.F;
+  ca.status = a.status;
+  ca.fail = a.fail;
+  ca.rel_tol = a.rel_tol;
+  ca.factor_only = 1;
+  if (chol_single_workgroup(a.I)) {
+    const size_t need = chol_work_doubles(a.I) * sizeof(double);
+    const size_t qr = lev_qr_smem_bytes(a.P);
+    const size_t lds = need > qr ? need : qr;
+    if ((a.I + 15) / 16 <= 4)
+      k_lev_wide<8><<<1, 512, lds, s>>>(a, ca);
+    else
+      k_lev_wide<16><<<1, 1024, lds, s>>>(a, ca);
+    return hipGetLastError();
+  }
+  // K = G G^T (G's storage read as the column-major P x I matrix G^T), blocked factorisation
+  // with the breakdown word, then the table
+  hipError_t e = launch_syrk(a.G, a.P, a.I, a.K, a.status, s, /*trans=*/true, a.fail);
+  if (e != hipSuccess) return e;
+  e = launch_chol(ca, s);
+  if (e != hipSuccess) return e;
+  return launch_lev_fallback(a.G, a.I, a.P, a.qr_work, a.Q, a.fail, a.status, s);
 }
 
 hipError_t launch_trisolve(const TriArgs& args, hipStream_t s) {

@@ -82,9 +82,10 @@ constexpr int kPlanCUs = 256;  // MI355X compute units (launch sizing)
 // rows of finite padding the sketch buffer keeps past row J (the contraction reads up to one
 // split quantum past the end of a chunk without bounds checks)
 constexpr int kSketchPadRows = 64;
-// ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel (FP32 matrix
-// cores per 32-row stage, FP64 accumulation); 2: BF16 form (FP32 sketch, BF16 panel, BF16
-// matrix cores with FP32 accumulation).
+// ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel, widened
+// exactly to FP64 and multiplied on the FP64 matrix cores (FP64 accumulation); 2: BF16 form
+// (two transposed BF16 sketches, BF16 panel, BF16 matrix cores with FP32 accumulation within
+// a split).
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
 // e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,
@@ -102,17 +103,26 @@ hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int npart
                                hipStream_t s);
 
 // K = A^T A (P x P row-major, lower blocks incl. full diagonal blocks) of an FP64 rows x P
-// row-major matrix A.
-hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const int* status, hipStream_t s);
+// matrix A, row-major (trans = false) or column-major (trans = true: then K = G G^T of the
+// row-major P x rows matrix G that A's storage holds).  clear (optional): a word the launch
+// sets to 0 (the failure word of the factorisation that follows).
+hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const int* status, hipStream_t s,
+                       bool trans = false, int* clear = nullptr);
 
 // Cholesky factorisation of an SPD P x P matrix H (full storage, lower triangle read,
 // P <= 1024) into the inverse factor W = L^{-1} (chol_factor_doubles(P) doubles,
-// block-packed).  A non-positive pivot sets *status = kDevSingular.
+// block-packed).  A pivot of row k < P at or below the tolerance (rel_tol, or P eps when
+// rel_tol is 0, times the largest diagonal entry of H) is a breakdown: it sets *fail if fail is
+// given (the handle goes on: a table factorisation then falls back), else *status.
 struct CholArgs {
   int P;
   const double* H;  // P x P, row-major (lower triangle and diagonal read)
   double* W;        // chol_work_doubles(P): the block-packed inverse factor first
   int* status;
+  int* fail;         // optional breakdown word (kernels after a breakdown skip their work)
+  double rel_tol;    // 0: P eps
+  int factor_only;   // 1: only the factor's diagonal regions of W are needed (large P: the
+                     // off-diagonal bands of W are skipped)
   // set by launch_chol for large P: work matrix, tolerance, and the diagonal region of a step
   double* Lg;
   double* scal;
@@ -129,7 +139,9 @@ bool chol_single_workgroup(int P);  // the factorisation runs as one workgroup (
 
 // With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
 // table weights Q_i = floor(||W g_i||^2 / P * 2^52) of the rows of Blev (In_lev x P, a core
-// unfolding).  Either part is skipped when its W is NULL.
+// unfolding).  Either part is skipped when its W is NULL.  When *lev_fail is set (the core
+// Gram's factorisation broke down) the table comes from the pivoted QR of Blev instead
+// (levqr.h), with qr_work (In_lev * P doubles) as its work memory.
 struct TriArgs {
   int P, In_sol, In_lev;
   const double* Wsol;
@@ -139,9 +151,34 @@ struct TriArgs {
   double* core;
   uint64_t* Q;
   int solve_groups, lev_groups;  // set by launch_trisolve
-  const int* status;
+  int* status;
+  const int* lev_fail;
+  double* qr_work;
 };
 hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
+
+// Sampling table of a wide core (I <= P: G_(2) is I x P, slice-major).  The row Gram G G^T is
+// factored with tolerance rel_tol; if it factors, G_(2) has full row rank and p_i = 1/I
+// exactly; otherwise the table comes from the pivoted QR of G_(2) (levqr.h).  For I <= 144 one
+// launch does all of it (Gram into K, factorisation in LDS, table); above, the Gram and the
+// blocked factorisation are separate launches (CholArgs with fail) and launch_lev_fallback
+// writes the table.  K: I x I doubles, F: chol_work_doubles(I), qr_work: I * P doubles.
+struct LevWideArgs {
+  const double* G;
+  int I, P;
+  double* K;
+  double* F;
+  double* qr_work;
+  uint64_t* Q;
+  int* status;
+  int* fail;
+  double rel_tol;
+};
+hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s);
+// table from *fail: uniform (1/I) if it is clear, else the pivoted QR of G (one workgroup)
+hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
+                               int* status, hipStream_t s);
+constexpr double kTableRelTol = 1e-8;  // pivot tolerance of the table factorisations
 
 // ---- generated data source and transfer-matrix inner products ----
 // Sampled fibers of X = TR(G*) + sigma Z: out[j][i] = sum_p G*_n[i][p] T[j][p] + sigma z(lin),

@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 from oracle import als as oals  # noqa: E402
 from oracle.generated import clean_fit, dense_generated  # noqa: E402
 from synth import random_cores, rng_for  # noqa: E402
-from tests.gpu_helpers import lockstep, rel, say, to_np  # noqa: E402
+from tests.gpu_helpers import assert_core_close, lockstep, rel, say, to_np  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_generated_fp64_free_running_matches_dense_oracle():
         np.testing.assert_allclose(w_g, w_o, rtol=1e-10)
     got = to_np(t.get_cores())
     for n in range(3):
-        assert rel(got[n], ref[n]) < 1e-9
+        assert_core_close(got[n], ref[n], 1e-9, f"core {n}")
     fg = t.fit_error()
     fo = clean_fit(got, true)
     say(f"clean fit gpu={fg:.9e} oracle={fo:.9e}")

@@ -1,0 +1,100 @@
+"""GPU parity of the sampling tables of rank-deficient and ill-conditioned cores.
+
+eq. (3) divides a core's leverage scores by the rank of its unfolding G_(2), and Definition 4
+takes the scores over rank(G_(2)) left singular vectors.  The oracle reads the rank from the
+SVD at the tolerance max(rows, cols) eps sigma_max.  The GPU factors the smaller Gram of G_(2)
+(G^T G for a tall core, G G^T for a wide one) and, when the factorisation is not certain, takes
+the table from a pivoted QR of G_(2) itself.  Each case sets degenerate cores into a handle and
+runs updates that draw from them: sampled indices must match the oracle bit for bit, weights
+to 1e-6 relative, the new cores slice by slice to 1e-9.
+
+Cases: a zero slice and a dependent pair of slices in a square core (rank I - 1), a tall core
+of rank 5 < P, a tall core with cond(G_(2)) = 1e6 (full rank, but its Gram squares that to
+1e12) and a square core with cond 1e7 (full row rank: the uniform table); then the same paths
+at sizes past the single-workgroup factorisation (a 200 x 256 wide core with and without a
+zero slice, a 300 x 168 tall core of rank 100).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from synth import random_cores, rng_for  # noqa: E402
+from tests.gpu_helpers import lockstep, say  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2010_08581_amd import _lib
+    _lib.load()
+
+
+def _from_unfolding(U, Rp, Rn):
+    """Core (Rp, I, Rn) whose unfolding (column a + Rp b holds G(a, i, b)) is U."""
+    return U.reshape(U.shape[0], Rn, Rp).transpose(2, 0, 1).copy()
+
+
+def zero_slice(m, i):
+    def f(c):
+        c[m][:, i, :] = 0.0
+        return c
+    return f
+
+
+def dependent_slice(m, i, j, a):
+    def f(c):
+        c[m][:, j, :] = a * c[m][:, i, :]
+        return c
+    return f
+
+
+def low_rank(m, r, seed):
+    def f(c):
+        Rp, I, Rn = c[m].shape
+        rng = rng_for(seed, 7)
+        c[m] = _from_unfolding(rng.standard_normal((I, r)) @ rng.standard_normal((r, Rp * Rn)), Rp, Rn)
+        return c
+    return f
+
+
+def ill_conditioned(m, log10_cond, seed):
+    def f(c):
+        Rp, I, Rn = c[m].shape
+        P = Rp * Rn
+        rng = rng_for(seed, 8)
+        k = min(I, P)
+        Q1, _ = np.linalg.qr(rng.standard_normal((I, k)))
+        Q2, _ = np.linalg.qr(rng.standard_normal((P, k)))
+        c[m] = _from_unfolding((Q1 * np.logspace(0, -log10_cond, k)) @ Q2.T, Rp, Rn)
+        return c
+    return f
+
+
+CASES = [
+    ("wide zero slice", (8, 9, 10), (3, 3, 3), zero_slice(1, 4), 0, 64),
+    ("wide dependent slices", (8, 9, 10), (3, 3, 3), dependent_slice(1, 2, 7, 2.0), 0, 64),
+    ("tall rank 5 of 9", (40, 9, 10), (3, 3, 3), low_rank(0, 5, 1), 1, 200),
+    ("tall cond 1e6", (40, 9, 10), (3, 3, 3), ill_conditioned(0, 6, 2), 1, 200),
+    ("square cond 1e7", (8, 9, 10), (3, 3, 3), ill_conditioned(1, 7, 3), 0, 64),
+    ("wide 200x256 zero slice", (200, 20, 20), (16, 16, 16), zero_slice(0, 17), 1, 600),
+    ("wide 200x256 full rank", (200, 20, 20), (16, 16, 16), lambda c: c, 1, 600),
+    ("tall 300x168 rank 100", (300, 12, 12), (12, 13, 14), low_rank(0, 100, 4), 1, 800),
+]
+
+
+@pytest.mark.parametrize("name,dims,ranks,mutate,start,J", CASES, ids=[c[0] for c in CASES])
+def test_degenerate_core_tables_match_oracle(name, dims, ranks, mutate, start, J):
+    from paper_2010_08581_amd import TRALS
+    say(f"case: {name}: dims {dims} ranks {ranks} J={J}, updates {start}..{start + 1}")
+    X = rng_for(90, 0).standard_normal(dims)
+    cores = mutate(random_cores(dims, ranks, rng_for(90, 3)))
+    t = TRALS(torch.tensor(X, device="cuda"), ranks, J, precision="f64",
+              init_cores=random_cores(dims, ranks, rng_for(90, 4)))
+    t.update_counter = start
+    t.set_cores(cores)  # every table but that of the next update's core, from these cores
+    worst = lockstep(t, X, 2, J, start=start, core_tol=1e-9)
+    say(f"{name}: worst slice {worst:.3e}")
