@@ -54,6 +54,8 @@ typedef enum {
                             the core being updated is left unchanged */
   TRALS_EHIP = -4,       /* a HIP runtime call failed */
   TRALS_ESTATE = -5,     /* handle is in a failed state (reset it with trals_set_cores) */
+  TRALS_ERANGE = -6,     /* trals_fit_error_noalloc: the problem's scratch exceeds the library's
+                            fixed scratch array (TRALS_NOALLOC_SCRATCH_BYTES) */
   TRALS_PENDING = 1      /* trals_query: work still running on the stream */
 } trals_status;
 
@@ -180,6 +182,27 @@ int trals_step(trals_handle h, int32_t n_updates);
 /* Relative error ||TR(G) - X||_F / ||X||_F (Section 4.1) over every entry of X,
  * with FP64 accumulation.  Synchronises the stream. */
 int trals_fit_error(trals_handle h, double* rel_err);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the relative error ||TR(G) - X||_F / ||X||_F of the
+ * cores G against the dense tensor X, as trals_fit_error computes it for a handle, without a
+ * handle or workspace.  It allocates nothing: its scratch (slice-major FP64 copies of the cores
+ * and the partial sums) is a fixed array of TRALS_NOALLOC_SCRATCH_BYTES per GPU inside the
+ * library, held until the process ends.
+ *   order, dims, ranks: as in trals_desc (host arrays, read during the call).
+ *   cores_dev: device, the N cores one after the other, core n in C order (R[n-1], I[n], R[n]),
+ *     element type cores_dtype (TRALS_F64 or TRALS_F32).
+ *   X_dev: device, prod(I) elements in C order, type x_dtype (TRALS_F64 or TRALS_F32).
+ *   rel_err_dev: device, one double that receives the error.
+ *   stream: hipStream_t the work is enqueued on (NULL = default stream); nothing is synchronised.
+ * The sizes need sum_n I[n] R[n-1] R[n] + ceil(prod_{n<N-1} I[n] / 8) + 1026 doubles of scratch;
+ * a larger problem returns TRALS_ERANGE before any work is enqueued.  Every call on one GPU uses
+ * that GPU's one scratch array: calls that overlap on a GPU (two streams, two host threads) race
+ * and must be serialised by the caller.  A non-finite entry of X gives a NaN error. */
+#define TRALS_NOALLOC_SCRATCH_BYTES (16u << 20)
+int trals_fit_error_noalloc(int32_t order, const int64_t* dims, const int32_t* ranks, const void* cores_dev,
+                            int32_t cores_dtype, const void* X_dev, int32_t x_dtype, double* rel_err_dev,
+                            void* stream);
 
 /* Release the handle (not the workspace).  NULL is a no-op. */
 int trals_destroy(trals_handle h);

@@ -27,6 +27,26 @@ def torch_device(d):
     return _torch().device(d)
 
 
+def fit_error_noalloc(X, cores_flat, ranks, out, stream=None):
+    """trals_fit_error_noalloc: enqueue ||TR(G) - X||_F / ||X||_F into ``out`` (a one-element
+    float64 CUDA tensor) on ``stream`` (default: X's current stream); nothing is allocated or
+    synchronised.  X: float32/float64 CUDA tensor in C order.  cores_flat: contiguous
+    float32/float64 CUDA tensor holding the N cores (R[n-1], I[n], R[n]) one after the other.
+    ranks: R[0..N-1]."""
+    torch = _torch()
+    lib = _lib.load()
+    dims = tuple(int(v) for v in X.shape)
+    N = len(dims)
+    code = {torch.float64: TRALS_F64, torch.float32: TRALS_F32}
+    d_arr = (C.c_int64 * N)(*dims)
+    r_arr = (C.c_int32 * N)(*[int(r) for r in ranks])
+    st = torch.cuda.current_stream(X.device) if stream is None else stream
+    _lib.check(lib.trals_fit_error_noalloc(N, d_arr, r_arr, C.c_void_p(cores_flat.data_ptr()),
+                                           code[cores_flat.dtype], C.c_void_p(X.data_ptr()), code[X.dtype],
+                                           C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)),
+               "trals_fit_error_noalloc")
+
+
 class TRALS:
     """One sampled TR-ALS problem held on the GPU.
 

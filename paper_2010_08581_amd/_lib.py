@@ -12,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtrals.so")
 
 TRALS_OK, TRALS_EINVAL, TRALS_ENOMEM, TRALS_ESINGULAR, TRALS_EHIP, TRALS_ESTATE = 0, -1, -2, -3, -4, -5
+TRALS_ERANGE = -6
+TRALS_NOALLOC_SCRATCH_BYTES = 16 << 20
 TRALS_PENDING = 1
 TRALS_ASYNC_FIT = 1
 TRALS_F64, TRALS_F32, TRALS_BF16 = 0, 1, 2
@@ -24,7 +26,7 @@ EXPORTS = (
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
     "trals_profile_read", "trals_workspace_bytes_generated", "trals_create_generated",
     "trals_sweep_async", "trals_query", "trals_set_samples", "trals_samples", "trals_tr_norm",
-    "trals_sweep_until",
+    "trals_sweep_until", "trals_fit_error_noalloc",
 )
 KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
@@ -97,6 +99,8 @@ def load(path: str = LIB_PATH):
         "trals_tr_norm": (C.c_int, [vp, C.POINTER(C.c_double)]),
         "trals_sweep_until": (C.c_int, [vp, i32, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "trals_create_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "trals_fit_error_noalloc": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), vp, i32, vp, i32,
+                                              vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

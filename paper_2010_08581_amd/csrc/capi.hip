@@ -160,8 +160,6 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   return TRALS_OK;
 }
 
-constexpr int kFitRows = 8;  // rows per block of the fit kernel
-constexpr int kScanBlocks = 1024;
 
 void plan(const Problem& p, Layout* L) {
   size_t off = 0;
@@ -689,6 +687,7 @@ const char* trals_strerror(int code) {
     case TRALS_EHIP: return "HIP runtime error";
     case TRALS_ESTATE: return "handle in a failed or incomplete state";
     case TRALS_PENDING: return "work still running";
+    case TRALS_ERANGE: return "problem exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

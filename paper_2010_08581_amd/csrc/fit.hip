@@ -10,7 +10,7 @@ namespace trals {
 
 namespace {
 
-constexpr int kRows = 8;
+constexpr int kRows = kFitRows;
 
 template <typename Real, typename Tx, int RM>
 __global__ __launch_bounds__(256) void k_fit(FitArgs a) {

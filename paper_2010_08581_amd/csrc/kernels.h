@@ -10,7 +10,8 @@ namespace trals {
 // as panel[a*B + b][i] = X[a][i][b], i.e. mode n contiguous, other modes in C order.
 hipError_t launch_panel(const void* X, int x_dtype, void* panel, int p_dtype, int64_t A, int64_t In,
                         int64_t B, hipStream_t s);
-// sum of squares (FP64) and count of non-finite entries of X; results in out[0] (double bits), out[1].
+// sum of squares (FP64, finite entries) into nblocks partials, and the count of non-finite
+// entries added to *nonfinite (skipped when nonfinite is NULL).
 hipError_t launch_scan_x(const void* X, int x_dtype, int64_t n, double* partial, int nblocks,
                          unsigned long long* nonfinite, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int n, double* out, hipStream_t s);
@@ -205,6 +206,8 @@ hipError_t launch_source_scale(const double* t2, double noise_rel, double entrie
 hipError_t launch_clean_fit(const double* r, double* fit, hipStream_t s);
 // *fit = sqrt(*r2 / x2)
 hipError_t launch_dense_fit(const double* r2, double x2, double* fit, hipStream_t s);
+// *fit = sqrt(*r2 / *x2) (both on the device)
+hipError_t launch_dense_fit_dev(const double* r2, const double* x2, double* fit, hipStream_t s);
 // *out = <TR(A), TR(B)> for two rings with equal mode sizes (FP64 slice-major cores); work:
 // ring_inner_doubles(ra, rb) doubles.
 size_t ring_inner_doubles(const Ring& ra, const Ring& rb);
@@ -222,6 +225,8 @@ hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_
 hipError_t launch_scan_u64(uint64_t* Q, int In, const int* status, hipStream_t s);
 
 // ---- fit error ----
+constexpr int kFitRows = 8;       // rows of X (C order, last mode contiguous) per fit block
+constexpr int kScanBlocks = 1024; // blocks (partial sums) of the ||X||^2 scan
 struct FitArgs {
   Ring ring;
   PerMode<const void> cores;  // slice-major

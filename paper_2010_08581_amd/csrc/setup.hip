@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_scan_x(const Tin* __restrict__ X, int64
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-  if (bad) atomicAdd(nonfinite, bad);
+  if (bad && nonfinite) atomicAdd(nonfinite, bad);
 }
 
 __global__ void k_sum_partials(const double* partial, int n, double* out) {

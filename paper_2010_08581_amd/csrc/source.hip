@@ -184,6 +184,7 @@ __global__ void k_clean_fit(const double* r, double* fit) {
 
 // fit = sqrt(r2 / x2) for the residual sum r2 of a full pass
 __global__ void k_dense_fit(const double* r2, double x2, double* fit) { *fit = sqrt(*r2 / x2); }
+__global__ void k_dense_fit_dev(const double* r2, const double* x2, double* fit) { *fit = sqrt(*r2 / *x2); }
 
 }  // namespace
 
@@ -200,6 +201,11 @@ hipError_t launch_clean_fit(const double* r, double* fit, hipStream_t s) {
 
 hipError_t launch_dense_fit(const double* r2, double x2, double* fit, hipStream_t s) {
   k_dense_fit<<<1, 1, 0, s>>>(r2, x2, fit);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_fit_dev(const double* r2, const double* x2, double* fit, hipStream_t s) {
+  k_dense_fit_dev<<<1, 1, 0, s>>>(r2, x2, fit);
   return hipGetLastError();
 }
 
