@@ -770,27 +770,53 @@ __global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca
   const int r16 = lane & 15, k4 = lane >> 4;
   const int nb = (I + 15) / 16, nslots = nb * (nb + 1) / 2;
   if (threadIdx.x == 0) s_wide_fail = 0;
-  for (int sl = wave; sl < nslots; sl += kW) {
-    int bi, bj;
-    slot_ij(sl, bi, bj);
-    const int ri = 16 * bi + r16, rj = 16 * bj + r16;
-    const double* gi = a.G + (int64_t)(ri < I ? ri : I - 1) * P;
-    const double* gj = a.G + (int64_t)(rj < I ? rj : I - 1) * P;
-    const double mi = ri < I ? 1.0 : 0.0;
+  // Gram blocks: with fewer blocks than waves, kparts waves share a block, each taking every
+  // kparts-th 4-column k-step, and their sums are added in part order
+  const int kparts = nslots >= kW ? 1 : kW / nslots;
+  const int part = wave % kparts, nwork = (kW / kparts) * kparts;
+  double* red = lw_smem;  // kW partial blocks (16 x 17 doubles each)
+  for (int sl0 = 0; sl0 < nslots; sl0 += kW / kparts) {
+    const int sl = sl0 + wave / kparts;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    // D(i, j) = sum_p G(16 bi + i, p) G(16 bj + j, p): A(i, k) in lane i + 16 k, B(k, j) in
-    // lane j + 16 k, both read along a row of G
-    for (int p0 = 0; p0 < P; p0 += 4) {
-      const int pp = p0 + k4;
-      const double va = pp < P ? mi * gi[pp] : 0.0;
-      const double vb = pp < P ? gj[pp] : 0.0;
-      acc = mfma(va, vb, acc);
-    }
+    int bi = 0, bj = 0;
+    if (wave < nwork && sl < nslots) {
+      slot_ij(sl, bi, bj);
+      const int ri = 16 * bi + r16, rj = 16 * bj + r16;
+      const double* gi = a.G + (int64_t)(ri < I ? ri : I - 1) * P;
+      const double* gj = a.G + (int64_t)(rj < I ? rj : I - 1) * P;
+      const double mi = ri < I ? 1.0 : 0.0;
+      // D(i, j) = sum_p G(16 bi + i, p) G(16 bj + j, p): A(i, k) in lane i + 16 k, B(k, j) in
+      // lane j + 16 k, both read along a row of G; four k-steps' loads in flight
+      for (int p0 = 4 * part; p0 < P; p0 += 16 * kparts) {
+        double va[4], vb[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = 16 * bi + 4 * q + k4, col = 16 * bj + r16;
-      if (row < I && col < I) a.K[(int64_t)row * I + col] = acc[q];
+        for (int u = 0; u < 4; ++u) {
+          const int pp = p0 + 4 * kparts * u + k4;
+          va[u] = pp < P ? mi * gi[pp] : 0.0;
+          vb[u] = pp < P ? gj[pp] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma(va[u], vb[u], acc);
+      }
     }
+    if (kparts > 1) {
+      store_acc(red + wave * kBlk, acc, lane);
+      __syncthreads();
+      if (wave < nwork && part == 0 && sl < nslots) {
+        for (int q2 = 1; q2 < kparts; ++q2) {
+          const d4 o = load_acc(red + (wave + q2) * kBlk, lane);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += o[q];
+        }
+      }
+      __syncthreads();
+    }
+    if (wave < nwork && part == 0 && sl < nslots)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * bi + 4 * q + k4, col = 16 * bj + r16;
+        if (row < I && col < I) a.K[(int64_t)row * I + col] = acc[q];
+      }
   }
   __syncthreads();
   CholArgs c = ca;
@@ -929,10 +955,13 @@ hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
   ca.rel_tol = a.rel_tol;
   ca.factor_only = 1;
   if (chol_single_workgroup(a.I)) {
+    const bool small = (a.I + 15) / 16 <= 4;
     const size_t need = chol_work_doubles(a.I) * sizeof(double);
     const size_t qr = lev_qr_smem_bytes(a.P);
-    const size_t lds = need > qr ? need : qr;
-    if ((a.I + 15) / 16 <= 4)
+    const size_t red = (size_t)(small ? 8 : 16) * kBlk * sizeof(double);  // Gram partial blocks
+    size_t lds = need > qr ? need : qr;
+    lds = lds > red ? lds : red;
+    if (small)
       k_lev_wide<8><<<1, 512, lds, s>>>(a, ca);
     else
       k_lev_wide<16><<<1, 1024, lds, s>>>(a, ca);

@@ -56,6 +56,17 @@ __device__ __forceinline__ void copy_batched(T* dst, const T* src, int64_t n, in
   }
 }
 
+// MI355X dispatches the workgroups of a launch to its 8 XCDs (each with its own L2) round
+// robin by workgroup index.  xcd_linear_block renumbers them so that the workgroups one XCD
+// runs form one contiguous range of logical indices (bijective for any grid size): work that
+// shares inputs and has neighbouring logical indices then shares one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_linear_block(int b, int grid) {
+  const int x = b % kXcds, k = b / kXcds;
+  const int per = grid / kXcds, rem = grid % kXcds;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
 // Per-mode view of the ring passed by value to kernels.
 struct Ring {
   int N;

@@ -53,7 +53,9 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   __shared__ double s_w[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
-  const int s = blockIdx.x / a.tiles, t = blockIdx.x - s * a.tiles;
+  // the tiles of one split (same sketch rows) are consecutive logical blocks on one XCD
+  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);
+  const int s = lb / a.tiles, t = lb - s * a.tiles;
   const int ct = t % a.col_tiles, rt = t / a.col_tiles;
   const int row0 = rt * RT;
   const bool gram = ct < a.gram_tiles;
@@ -230,7 +232,8 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   __shared__ int64_t s_roff[kMaxChunk];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
-  const int s = blockIdx.x / a.tiles, t = blockIdx.x - s * a.tiles;
+  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
+  const int s = lb / a.tiles, t = lb - s * a.tiles;
   const int ct = t % a.col_tiles, rt = t / a.col_tiles;
   const int row0 = rt * RT;
   const bool gram = ct < a.gram_tiles;

@@ -3,15 +3,18 @@ supplement's experiment details), run on the GPU.
 
 1. Exact TR-ALS (Algorithm 1) from given initial cores, sweep by sweep, until the relative
    error changes by less than ``tol`` of its value between two sweeps (|e_k - e_{k-1}| < tol
-   e_k), or ``max_sweeps`` sweeps have run.  The sweep count S and the final error E fix the
-   reference.
-2. Sampled TR-ALS (Algorithm 2) from the same initial cores for S sweeps: the smallest J on the
-   grid J0, J0 + step, ... (at most J_max) whose error is below ``factor`` * E.  A J whose
-   sampled system turns out rank deficient (too few rows for the design's coherence) counts as
-   not reaching the target.  The paper walks the grid upwards one step at a time; here the grid
-   is searched by doubling and then bisection, which finds the same J when the error decreases
-   with J and needs far fewer runs.
-3. Both are timed over their S sweeps (fit evaluations excluded); the speedup is the ratio.
+   e_k), or ``max_sweeps`` sweeps have run: S sweeps.
+2. Every method then runs again from the same initial cores for 2 S sweeps without checking
+   convergence.  E is the error of exact TR-ALS after its 2 S sweeps.
+3. TR-ALS-Sampled (Algorithm 2): the sample size J starts at J0 (2 R^2 in the paper) and grows
+   by ``step`` until the error after 2 S sweeps is below ``factor`` * E; the first such J is
+   reported with its error and time.  J_max bounds the walk.  A J whose sampled system turns
+   out rank deficient counts as not reaching the target.
+4. The speedup is the ratio of the two 2 S-sweep times (fit evaluations excluded).
+
+``search="bisect"`` replaces the walk by doubling and bisection on the same grid (far fewer
+runs, but it assumes the error falls with J, which the sampled error after a fixed number of
+sweeps need not do); it is not the paper's rule.
 
 Everything runs through the library's handles; the sampled runs reuse one handle (the sample
 count, cores and update counter are reset between candidates).  ``normalize`` applies the
@@ -35,27 +38,34 @@ def _timed_sweeps(h, sweeps):
 
 
 def exact_reference(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=100, normalize=False):
-    """(sweeps S, error E, seconds of the S sweeps) of exact TR-ALS."""
+    """Sweeps S of the convergence run of exact TR-ALS, then its rerun for 2 S sweeps from the
+    same cores: (S, error E after the 2 S sweeps, seconds of the 2 S sweeps)."""
     h = TRALS(X, ranks, 0, precision=precision, init_cores=init_cores, method="exact", normalize=normalize)
     prev = h.fit_error()
-    secs = 0.0
     for s in range(1, max_sweeps + 1):
-        secs += _timed_sweeps(h, 1)
+        h.sweep(1)
         e = h.fit_error()
         if abs(prev - e) < tol * e:
             break
         prev = e
+    h.update_counter = 0
+    h.set_cores(init_cores)
+    secs = _timed_sweeps(h, 2 * s)
+    E = h.fit_error()
     h.close()
-    return s, e, secs
+    return s, E, secs
 
 
 def find_sample_size(X, ranks, init_cores, sweeps, target, J0, step, J_max, precision="f64", seed=0,
-                     method="leverage", normalize=False):
-    """Smallest J = J0 + k * step (<= J_max) whose S-sweep error is below target (doubling,
-    then bisection on the grid).
+                     method="leverage", normalize=False, search="walk"):
+    """First J = J0 + k * step (<= J_max) whose error after ``sweeps`` sweeps is below target:
+    walking the grid upwards (search="walk", the paper's rule), or by doubling then bisection
+    (search="bisect", equal to the walk when the error falls with J).
 
-    Returns (J, error, seconds of the S sweeps, runs), or (None, best error, None, runs) if no
+    Returns (J, error, seconds of the sweeps, runs), or (None, best error, None, runs) if no
     J up to J_max reaches the target."""
+    if search not in ("walk", "bisect"):
+        raise ValueError("search: 'walk' or 'bisect'")
     h = TRALS(X, ranks, J_max, seed=seed, precision=precision, init_cores=init_cores, method=method,
               normalize=normalize)
     tried = {}
@@ -75,8 +85,16 @@ def find_sample_size(X, ranks, init_cores, sweeps, target, J0, step, J_max, prec
         return tried[J]
 
     try:
-        k_lo, k = -1, 0  # grid index k <-> J0 + k * step; k_lo: largest index known to fail
         k_max = (J_max - J0) // step
+        if search == "walk":
+            for k in range(k_max + 1):
+                J = J0 + k * step
+                e, secs = run(J)
+                if e < target:
+                    return J, e, secs, len(tried)
+            best = min(e for e, _ in tried.values())
+            return None, best, None, len(tried)
+        k_lo, k = -1, 0  # grid index k <-> J0 + k * step; k_lo: largest index known to fail
         while True:
             if run(J0 + k * step)[0] < target:
                 break
@@ -100,18 +118,21 @@ def find_sample_size(X, ranks, init_cores, sweeps, target, J0, step, J_max, prec
 
 
 def compare(X, ranks, init_cores, precision="f64", tol=1e-3, max_sweeps=100, factor=1.1, J0=None, step=100,
-            J_max=None, seed=0, method="leverage", normalize=False):
+            J_max=None, seed=0, method="leverage", normalize=False, search="walk"):
     """The full protocol; returns a dict of the reference, the J found and the speedup."""
     N = len(ranks)
     P = max(ranks[(n - 1) % N] * ranks[n] for n in range(N))
     J0 = 2 * P if J0 is None else J0
     J_max = 100 * P if J_max is None else J_max
     S, E, t_ex = exact_reference(X, ranks, init_cores, precision, tol, max_sweeps, normalize)
-    J, e, t_s, runs = find_sample_size(X, ranks, init_cores, S, factor * E, J0, step, J_max, precision, seed,
-                                       method, normalize)
+    J, e, t_s, runs = find_sample_size(X, ranks, init_cores, 2 * S, factor * E, J0, step, J_max, precision, seed,
+                                       method, normalize, search)
     return {
-        "sweeps": S, "exact_error": E, "exact_s": t_ex,
+        "convergence_sweeps": S, "sweeps": 2 * S, "exact_error": E, "exact_s": t_ex,
         "samples": J, "sampled_error": e, "sampled_s": t_s,
-        "speedup": (t_ex / t_s) if t_s else None, "factor": factor, "J_max": J_max, "runs": runs,
-        "normalize": bool(normalize),
+        "speedup": (t_ex / t_s) if t_s else None, "factor": factor, "J0": J0, "step": step, "J_max": J_max,
+        "search": search, "runs": runs, "normalize": bool(normalize),
+        "outcome": (f"J = {J}: error {e:.4g} < {factor} x {E:.4g} after {2 * S} sweeps" if J is not None else
+                    f"no J in [{J0}, {J_max}] (step {step}) reaches {factor} x the exact error {E:.4g} after "
+                    f"{2 * S} sweeps (best {e:.4g})"),
     }

@@ -69,7 +69,7 @@ def test_protocol_finds_sample_size():
     Xt = torch.tensor(X, device="cuda")
     res = protocol.compare(Xt, ranks, init, tol=1e-4, max_sweeps=30, factor=1.1, step=50)
     say(str(res))
-    assert 1 <= res["sweeps"] <= 30
+    assert 1 <= res["convergence_sweeps"] <= 30 and res["sweeps"] == 2 * res["convergence_sweeps"]
     assert res["samples"] is not None and res["samples"] >= 18
     assert res["sampled_error"] < 1.1 * res["exact_error"]
     # the reported error is reproduced by a fresh handle with the J found
