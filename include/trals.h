@@ -162,6 +162,22 @@ int trals_tr_norm(trals_handle h, double* norm);
 int trals_sweep_until(trals_handle h, int32_t max_sweeps, double rel_tol, int32_t* sweeps_done,
                       double* last_change);
 
+/* Estimate of the relative error ||TR(G) - X||_F / ||X||_F from sampled entries (Section 3.1,
+ * Termination Criteria: the exact error needs every entry of X).  `samples` entries are drawn
+ * uniformly with replacement (entry s: word 0 r of the Philox4x64-10 block with key (seed,
+ * stream_id) and counter (s, tag, 0, 1), C-order linear index floor(r E / 2^64), E = prod I), and
+ * *rel_err = sqrt((E / samples) sum_s (TR(G)(i_s) - X(i_s))^2 / ||X||_F^2); E/samples times the
+ * sum is an unbiased estimate of ||TR(G) - X||_F^2.  O(samples N R^3) work.  Handles with a
+ * dense X only (TRALS_EINVAL for a generated source); samples in [1, 2^40].  Synchronises. */
+int trals_fit_estimate(trals_handle h, int64_t samples, uint64_t tag, double* rel_err);
+
+/* Termination by the change of the sampled error estimate (Section 3.1): run whole sweeps until
+ * |e_k - e_{k-1}| / e_k < rel_tol, e_k = trals_fit_estimate(h, samples, 0) after sweep k (the same
+ * sampled entries every time), or max_sweeps sweeps.  Reports the sweeps run, the last estimate
+ * and the last relative change (-1 if none).  Synchronises once per sweep. */
+int trals_sweep_until_estimate(trals_handle h, int32_t max_sweeps, double rel_tol, int64_t samples,
+                               int32_t* sweeps_done, double* last_estimate, double* last_change);
+
 /* Enqueue n_sweeps like trals_sweep and return without synchronising the stream (several
  * handles on different streams then overlap on the device).  flags: 0 or TRALS_ASYNC_FIT, which
  * also enqueues the relative error (trals_fit_error's value: the clean-ring fit of a generated

@@ -15,12 +15,14 @@ Becker, "A Sampling-Based Method for Tensor Ring Decomposition" (ICML 2021):
 * ``als``      -- Algorithm 4 (sketched subchain), line "sample X" of
                   Algorithm 2, the sampled LS solve, Algorithm 2 itself,
                   Algorithm 1 (exact TR-ALS) and the relative fit error.
+* ``estimate`` -- the relative error estimated from sampled entries
+                  (Section 3.1, Termination Criteria).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
 and never imports it; the product path never calls into it.
 """
-from . import ring, leverage, philox, sampler, als  # noqa: F401
+from . import ring, leverage, philox, sampler, als, estimate  # noqa: F401
 from .ring import tr_full, unfold_classical, unfold_cyclic, core_unfolding, subchain_tensor, \
     subchain_unfolding, lin_index  # noqa: F401
 from .leverage import leverage_scores, mode_distribution, integer_table  # noqa: F401

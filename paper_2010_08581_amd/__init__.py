@@ -216,6 +216,21 @@ class TRALS:
                                               C.byref(change)), "trals_sweep_until")
         return int(done.value), float(change.value)
 
+    def fit_estimate(self, samples, tag=0) -> float:
+        """Relative error estimated from `samples` uniformly drawn entries of X (Section 3.1)."""
+        out = C.c_double(0.0)
+        _lib.check(self.lib.trals_fit_estimate(self.h, int(samples), int(tag), C.byref(out)), "trals_fit_estimate")
+        return float(out.value)
+
+    def sweep_until_estimate(self, max_sweeps, rel_tol, samples):
+        """Sweeps until the relative change of the sampled error estimate falls below rel_tol;
+        returns (sweeps run, last estimate, last relative change)."""
+        done, est, change = C.c_int32(0), C.c_double(0.0), C.c_double(0.0)
+        _lib.check(self.lib.trals_sweep_until_estimate(self.h, int(max_sweeps), float(rel_tol), int(samples),
+                                                       C.byref(done), C.byref(est), C.byref(change)),
+                   "trals_sweep_until_estimate")
+        return int(done.value), float(est.value), float(change.value)
+
     def fit_error(self) -> float:
         out = C.c_double(0.0)
         _lib.check(self.lib.trals_fit_error(self.h, C.byref(out)), "trals_fit_error")

@@ -26,7 +26,7 @@ EXPORTS = (
     "trals_update_counter", "trals_set_update_counter", "trals_strerror", "trals_profile",
     "trals_profile_read", "trals_workspace_bytes_generated", "trals_create_generated",
     "trals_sweep_async", "trals_query", "trals_set_samples", "trals_samples", "trals_tr_norm",
-    "trals_sweep_until", "trals_fit_error_noalloc",
+    "trals_sweep_until", "trals_fit_error_noalloc", "trals_fit_estimate", "trals_sweep_until_estimate",
 )
 KERNELS = {"draw": 0, "contract": 1, "reduce": 2, "factor": 3, "solve": 4, "table": 5}
 
@@ -101,6 +101,9 @@ def load(path: str = LIB_PATH):
         "trals_create_generated": (C.c_int, [C.POINTER(Desc), C.POINTER(Source), vp, C.c_size_t, vp, C.POINTER(vp)]),
         "trals_fit_error_noalloc": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), vp, i32, vp, i32,
                                               vp, vp]),
+        "trals_fit_estimate": (C.c_int, [vp, i64, u64, C.POINTER(C.c_double)]),
+        "trals_sweep_until_estimate": (C.c_int, [vp, i32, C.c_double, i64, C.POINTER(C.c_int32),
+                                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

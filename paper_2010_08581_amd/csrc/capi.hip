@@ -19,6 +19,9 @@ using namespace trals;
 namespace {
 
 constexpr size_t kAlign = 256;
+// FP32 path contraction: false = FP32 operands widened on the FP64 matrix cores, true = three
+// 8-bit slices on the BF16 matrix cores (exact slice products, FP64 block sums)
+constexpr bool kFp32ThreeSlice = false;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -30,7 +33,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, partial, scal, total;
+  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -137,7 +140,9 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   p->sk_sz = p->sk_dt == 0 ? 8 : 4;
   p->panel_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
   p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
-  p->ne_dt = p->panel_dt;
+  // FP32: FP32 sketch and fibers widened exactly on the FP64 matrix cores (ne_dt 1); the
+  // three-slice form on the BF16 matrix cores (ne_dt 3) is selected by kFp32ThreeSlice
+  p->ne_dt = (p->prec == TRALS_F32 && kFp32ThreeSlice) ? 3 : p->panel_dt;
   if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
   if (src) {
     if (src->true_dtype != TRALS_F64 && src->true_dtype != TRALS_F32) return TRALS_EINVAL;
@@ -207,6 +212,12 @@ void plan(const Problem& p, Layout* L) {
   L->idx = take((size_t)p.J * (p.N - 1) * 4);
   L->w = take((size_t)p.J * 8);
   L->A = take((size_t)(p.J + kSketchPadRows) * p.Pmax * p.sk_sz);
+  {
+    // three-slice sketch (BF16) and its block exponents
+    const size_t ld = (size_t)(p.J + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+    L->S3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Pmax * ld * 2 : 0);
+    L->E3 = take(p.ne_dt == 3 ? (size_t)p.Pmax * (ld / kSplitBlock) * 4 : 0);
+  }
   L->Hpart = take(hpart * 8);  // FP64 split-K partials
   L->Bpart = take(bpart * 8);
   L->Bred = take((size_t)p.Pmax * p.Imax * 8);
@@ -468,6 +479,11 @@ int run_update(trals_ctx* h) {
     fa.status = h->status();
     HIPTRY(launch_fibers(fa, p.panel_dt, h->stream));
   }
+  if (p.ne_dt == 3) {
+    const int64_t ld3 = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+    HIPTRY(launch_sketch_split(h->at<const float>(h->L.A), Jn, P, h->at<void>(h->L.S3), ld3, h->at<int>(h->L.E3),
+                               h->status(), h->stream));
+  }
   PROF_END(TRALS_K_DRAW);
 
   const NormalEqPlan pl = plan_normal_eq(P, In, Jn, p.ne_dt, kPlanCUs);
@@ -476,6 +492,11 @@ int run_update(trals_ctx* h) {
   na.A = da.A;
   na.A2 = da.A2;
   na.ld = da.ldt;
+  if (p.ne_dt == 3) {
+    na.S3 = h->at<const void>(h->L.S3);
+    na.E = h->at<const int>(h->L.E3);
+    na.ld = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+  }
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
   // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the
   // panel's rows: row r of the sketch pairs with fiber row r
@@ -1033,6 +1054,58 @@ int trals_set_samples(trals_handle h, int64_t samples) {
 }
 
 int64_t trals_samples(trals_handle h) { return h ? h->p.J : -1; }
+
+int trals_fit_estimate(trals_handle h, int64_t samples, uint64_t tag, double* rel_err) {
+  if (!h || !rel_err || samples < 1 || samples > ((int64_t)1 << 40)) return TRALS_EINVAL;
+  if (h->p.generated) return TRALS_EINVAL;  // the estimate reads entries of a dense X
+  if (h->failed) return TRALS_ESTATE;
+  const Problem& p = h->p;
+  FitSampleArgs fa;
+  memset(&fa, 0, sizeof(fa));
+  fa.ring = make_ring(p);
+  for (int m = 0; m < p.N; ++m) fa.cores.p[m] = h->at<const void>(h->L.core[m]);
+  fa.X = h->at<const void>(h->L.fitx);
+  fa.E = p.E;
+  fa.S = samples;
+  fa.seed = p.seed;
+  fa.stream_id = p.stream_id;
+  fa.tag = tag;
+  fa.partial = h->at<double>(h->L.partial);
+  int nb = 0;
+  HIPTRY(launch_fit_sample(fa, p.panel_dt == 2 ? 1 : p.panel_dt, &nb, h->stream));
+  HIPTRY(launch_sum_partials(fa.partial, nb, h->scal_d(), h->stream));
+  double r2 = 0.0;
+  HIPTRY(hipMemcpyAsync(&r2, h->scal_d(), 8, hipMemcpyDeviceToHost, h->stream));
+  const int st = sync_status(h);
+  if (st) return st;
+  *rel_err = sqrt(((double)p.E / (double)samples) * r2 / h->xnorm2);
+  return TRALS_OK;
+}
+
+int trals_sweep_until_estimate(trals_handle h, int32_t max_sweeps, double rel_tol, int64_t samples,
+                               int32_t* sweeps_done, double* last_estimate, double* last_change) {
+  if (!h || max_sweeps < 1 || !(rel_tol >= 0.0)) return TRALS_EINVAL;
+  if (h->failed) return TRALS_ESTATE;
+  double prev = 0.0, change = -1.0;
+  int rc = trals_fit_estimate(h, samples, 0, &prev);
+  if (rc) return rc;
+  double cur = prev;
+  int32_t done = 0;
+  while (done < max_sweeps) {
+    rc = run_updates(h, h->p.N);
+    if (rc) break;
+    ++done;
+    rc = trals_fit_estimate(h, samples, 0, &cur);
+    if (rc) break;
+    change = cur > 0.0 ? fabs(cur - prev) / cur : 0.0;
+    prev = cur;
+    if (change < rel_tol) break;
+  }
+  if (sweeps_done) *sweeps_done = done;
+  if (last_estimate) *last_estimate = cur;
+  if (last_change) *last_change = change;
+  return rc;
+}
 
 int trals_tr_norm(trals_handle h, double* norm) {
   if (!h || !norm) return TRALS_EINVAL;

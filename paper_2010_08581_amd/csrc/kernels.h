@@ -72,6 +72,11 @@ struct NormalEqArgs {
   double* Bpart;              // splits x P x I_n
   int direct;                 // 1: the fiber of sample j is row j of `panel` (I_n wide)
   const int* status;
+  // FP32 path (ne_dtype 3): the sketch in three BF16 slices per 64-sample block and column,
+  // slice s of column p at S3 + (s P + p) ld (ld samples per column, a multiple of 64), and the
+  // block exponents E[b P + p] (launch_sketch_split writes both)
+  const void* S3;
+  const int* E;
 };
 struct NormalEqPlan {
   int mb;          // row tile = 16 * mb rows of P
@@ -86,11 +91,21 @@ constexpr int kSketchPadRows = 64;
 // ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel, widened
 // exactly to FP64 and multiplied on the FP64 matrix cores (FP64 accumulation); 2: BF16 form
 // (two transposed BF16 sketches, BF16 panel, BF16 matrix cores with FP32 accumulation within
-// a split).
+// a split); 3: FP32 path on BF16 matrix cores with exact products: the FP32 sketch and the
+// weighted FP32 fibers in three 8-bit slices per 64-sample block and column (one exponent
+// each), slice products exact in FP32, block sums added in FP64.
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
 // e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Three-slice form of the FP32 sketch rows A (J x P, row-major) for ne_dtype 3: per block b of
+// 64 samples and column p, E[b P + p] = e with max_j |A(j, p)| < 2^e over the block, and
+// A(j, p) = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2) + r, |r| <= 2^(e-25), with integers |s0| <= 256,
+// |s1|, |s2| <= 128 stored as BF16 (exact): S3[(s P + p) ld + j].  Samples past J are zero.
+hipError_t launch_sketch_split(const float* A, int64_t J, int P, void* S3, int64_t ld, int* E, const int* status,
+                               hipStream_t s);
+constexpr int kSplitBlock = 64;  // samples per exponent block of the three-slice sketch
+
 // out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:
 // symmetrise a P x P matrix from its lower triangle; mode 2: transpose P x (count / P) to
 // (count / P) x P.  Two independent reductions share one launch.
@@ -235,5 +250,19 @@ struct FitArgs {
   double* partial;            // one per block
 };
 hipError_t launch_fit(const FitArgs& a, int real_dtype, int x_dtype, int* nblocks_out, hipStream_t s);
+
+// Sampled squared residual (estimate of the fit error from S uniform entries, Philox counter
+// (s, tag, 0, 1), index floor(r E / 2^64)): per-block sums into partial (at most
+// kFitSampleBlocks of them; *nblocks_out receives the count).  Cores FP64 slice-major.
+struct FitSampleArgs {
+  Ring ring;
+  PerMode<const void> cores;
+  const void* X;  // C order (= panel of mode N-1)
+  int64_t E, S;
+  uint64_t seed, stream_id, tag;
+  double* partial;
+};
+constexpr int kFitSampleBlocks = 256;
+hipError_t launch_fit_sample(const FitSampleArgs& a, int x_dtype, int* nblocks_out, hipStream_t s);
 
 }  // namespace trals

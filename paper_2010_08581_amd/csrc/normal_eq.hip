@@ -332,6 +332,238 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// FP32 path on BF16 matrix cores with exact products (ne_dtype 3).
+//
+// Every operand value v of a 64-sample block is written as v = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2)
+// + r with integers |s0| <= 256, |s1|, |s2| <= 128 (exact in BF16) and |r| <= 2^(e-25), e the
+// block exponent of its column (max |v| < 2^e): a relative truncation of at most 2^-24 of the
+// column's block maximum, the size of FP32 rounding.  A product of two such values is the sum
+// of nine slice products s_s t_t 2^(-8(s+t)); grouped by level l = s + t, each level's sum over
+// the 64 samples is an integer below 2^24, so the FP32 accumulation of the BF16 matrix cores is
+// exact.  After each block the five level sums are combined and scaled by 2^(e_row + e_col - 16)
+// in FP64 and added to FP64 accumulators.
+//
+// The sketch side has one representation (launch_sketch_split), used both as the row operand
+// and, in the Gram tiles, as the column operand: H is exactly R(A)^T R(A).  The data side is the
+// weighted fiber w_j X(j, i), split in the kernel with the block maximum of its column (the 64
+// samples of a column sit in four lanes: a max over the lane's 16 values and two exchanges).  So
+// B = R(A)^T R(diag(w) X): both products are those of one slightly perturbed problem, whose
+// solution moves by cond(A) times the perturbation, as with FP32 storage alone.
+//   v_mfma_f32_16x16x32_bf16 layouts: A(i, k) at lane i + 16 (k / 8), element k % 8;
+//   B(k, j) at lane j + 16 (k / 8), element k % 8; D(i, j) at lane j + 16 (i / 4), register i % 4.
+
+__device__ __forceinline__ int block_exponent(double m) {
+  int e = 0;
+  if (m > 0.0) (void)frexp(m, &e);  // m = f 2^e, f in [0.5, 1): every |v| <= m is below 2^e
+  return e;
+}
+
+// three 8-bit slices of y = v 2^(8 - e), |y| < 256 (exact FP64 steps)
+struct Slices3 {
+  __bf16 s[3];
+};
+__device__ __forceinline__ Slices3 split3(double v, int e) {
+  const double y = ldexp(v, 8 - e);
+  const double a0 = rint(y);
+  const double r1 = (y - a0) * 256.0;
+  const double a1 = rint(r1);
+  const double a2 = rint((r1 - a1) * 256.0);
+  return Slices3{{(__bf16)(float)a0, (__bf16)(float)a1, (__bf16)(float)a2}};
+}
+
+// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup
+__global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ A, int64_t J, int P,
+                                                      __bf16* __restrict__ S3, int64_t ld, int* __restrict__ E,
+                                                      const int* status) {
+  __shared__ float tile[kSplitBlock][kSplitBlock + 1];
+  __shared__ float cmax[4][kSplitBlock];
+  if (*status != kDevOk) return;
+  const int p0 = blockIdx.x * 64;
+  const int64_t j0 = (int64_t)blockIdx.y * kSplitBlock;
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;  // column, quarter of the samples
+  const int p = p0 + c;
+  for (int r = q; r < kSplitBlock; r += 4) {
+    const int64_t j = j0 + r;
+    tile[r][c] = (j < J && p < P) ? A[j * P + p] : 0.f;
+  }
+  __syncthreads();
+  float mx = 0.f;
+  for (int r = 16 * q; r < 16 * q + 16; ++r) mx = fmaxf(mx, fabsf(tile[r][c]));
+  cmax[q][c] = mx;
+  __syncthreads();
+  if (p >= P) return;
+  const int e = block_exponent((double)fmaxf(fmaxf(cmax[0][c], cmax[1][c]), fmaxf(cmax[2][c], cmax[3][c])));
+  if (q == 0) E[(int64_t)blockIdx.y * P + p] = e;
+  bf8 o[3][2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const Slices3 x = split3((double)tile[16 * q + r][c], e);
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) o[sl][r / 8][r % 8] = x.s[sl];
+  }
+#pragma unroll
+  for (int sl = 0; sl < 3; ++sl) {
+    bf8* dst = (bf8*)(S3 + ((int64_t)sl * P + p) * ld + j0 + 16 * q);
+    dst[0] = o[sl][0];
+    dst[1] = o[sl][1];
+  }
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
+  constexpr int RT = 16 * MB;
+  __shared__ int64_t s_roff[kMaxChunk];
+  __shared__ double s_w[kMaxChunk];
+  if (*a.status != kDevOk) return;
+  const int P = a.P, In = a.In;
+  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
+  const int s = lb / a.tiles, t = lb - s * a.tiles;
+  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
+  const int row0 = rt * RT;
+  const bool gram = ct < a.gram_tiles;
+  const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
+  if (gram && col0 >= row0 + RT) return;
+  const int64_t r0 = (int64_t)s * a.chunk;  // a multiple of kSplitBlock
+  const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
+  const int nrows = (int)(r1 - r0);
+  const int nblk = (nrows + kSplitBlock - 1) / kSplitBlock;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int li = lane & 15, lg = lane >> 4;
+  const float* X = (const float*)a.panel;
+  if (!gram) {
+    // row offsets and weights of the chunk's samples; past the chunk the weight is zero
+    for (int r = threadIdx.x; r < nblk * kSplitBlock; r += 256) {
+      int64_t off = 0;
+      double w = 0.0;
+      if (r < nrows) {
+        if (a.direct) {
+          off = r0 + r;
+        } else {
+          const int32_t* ij = a.idx + (r0 + r) * a.K;
+          for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+        }
+        w = a.w[r0 + r];
+      }
+      s_roff[r] = off * In;
+      s_w[r] = w;
+    }
+    __syncthreads();
+  }
+  const __bf16* S3 = (const __bf16*)a.S3;
+  const int64_t ld = a.ld, sstride = (int64_t)P * ld;
+  const int64_t eb0 = r0 / kSplitBlock;
+  // row operand: sketch row p = row0 + 16 m + li (clamped: rows past P are computed, not stored)
+  const __bf16* arow[MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int pr = row0 + 16 * m + li;
+    arow[m] = S3 + (int64_t)(pr < P ? pr : P - 1) * ld + r0;
+  }
+  const int bc = col0 + 16 * wave + li;
+  const int bcg = bc < P ? bc : P - 1;                    // Gram side: sketch column
+  const __bf16* brow = S3 + (int64_t)bcg * ld + r0;
+  const int bcol = bc < In ? bc : In - 1;                 // data side: fiber entry
+  f4 acc[MB][5];
+  double out[MB][4];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+#pragma unroll
+    for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int base = b * kSplitBlock;
+    const int* Eb = a.E + (eb0 + b) * P;
+    bf8 bs[3][2];
+    int fcol;
+    if (gram) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) bs[sl][ks] = *(const bf8*)(brow + sl * sstride + base + 32 * ks + 8 * lg);
+      fcol = Eb[bcg];
+    } else {
+      double v[2][8];
+      double mx = 0.0;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int r = base + 32 * ks + 8 * lg + e;
+          v[ks][e] = s_w[r] * (double)X[s_roff[r] + bcol];
+          mx = fmax(mx, fabs(v[ks][e]));
+        }
+      // the block's 64 samples of this column are held by lanes li, li + 16, li + 32, li + 48
+      mx = fmax(mx, __shfl_xor(mx, 16));
+      mx = fmax(mx, __shfl_xor(mx, 32));
+      fcol = block_exponent(mx);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const Slices3 x = split3(v[ks][e], fcol);
+#pragma unroll
+          for (int sl = 0; sl < 3; ++sl) bs[sl][ks][e] = x.s[sl];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      bf8 as[3][2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) as[sl][ks] = *(const bf8*)(arow[m] + sl * sstride + base + 32 * ks + 8 * lg);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int si = 0; si < 3; ++si)
+#pragma unroll
+          for (int ti = 0; ti < 3; ++ti)
+            acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[si][ks], bs[ti][ks], acc[m][si + ti], 0, 0, 0);
+    }
+    // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pr = row0 + 16 * m + 4 * lg + q;
+        const int erow = Eb[pr < P ? pr : P - 1];
+        double v = (double)acc[m][4][q];
+        v = fma(v, 0.00390625, (double)acc[m][3][q]);
+        v = fma(v, 0.00390625, (double)acc[m][2][q]);
+        v = fma(v, 0.00390625, (double)acc[m][1][q]);
+        v = fma(v, 0.00390625, (double)acc[m][0][q]);
+        out[m][q] += ldexp(v, erow + fcol - 16);
+      }
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int col = col0 + wave * 16 + li;
+  if (gram) {
+    double* H = a.Hpart + (int64_t)s * P * P;
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + m * 16 + 4 * lg + q;
+        if (row < P && col < P && col <= row) H[(int64_t)row * P + col] = out[m][q];
+      }
+  } else {
+    double* B = a.Bpart + (int64_t)s * P * In;
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + m * 16 + 4 * lg + q;
+        if (row < P && col < In) B[(int64_t)row * In + col] = out[m][q];
+      }
+  }
+}
+
 // Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
 __global__ __launch_bounds__(256) void k_reduce_parts(ReduceJob j0, ReduceJob j1, int64_t nb0, int nparts, int P,
                                                       const int* status) {
@@ -371,12 +603,15 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s,
 
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) {
   NormalEqPlan pl;
-  // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding
-  if (P <= 128) {
+  // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding;
+  // the three-slice kernel keeps two waves per SIMD up to mb = 5: one tile when P <= 80, else
+  // the mb in [3, 5] with least padding
+  const int mb_max = ne_dtype == 3 ? 5 : 8, mb_min = ne_dtype == 3 ? 3 : 4;
+  if (P <= 16 * mb_max) {
     pl.mb = (P + 15) / 16;
   } else {
-    int best = 8, best_pad = 1 << 30;
-    for (int mb = 8; mb >= 4; --mb) {
+    int best = mb_max, best_pad = 1 << 30;
+    for (int mb = mb_max; mb >= mb_min; --mb) {
       const int rt = 16 * mb;
       const int pad = (P + rt - 1) / rt * rt - P;
       if (pad < best_pad) {
@@ -395,6 +630,9 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   if (ne_dtype == 2) {
     per_cu = 2;  // register bound (196 of 512 registers per lane: two waves per SIMD)
     quantum = kKB16;
+  } else if (ne_dtype == 3) {
+    per_cu = 2;  // register bound
+    quantum = kSplitBlock;
   } else {
     const int kg = ne_dtype == 1 ? 2 : 1;
     const int esz = ne_dtype == 1 ? 4 : 8;
@@ -413,8 +651,9 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   const int64_t maxchunk = kMaxChunk - quantum;
   if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
   int64_t chunk = (J + S - 1) / S;
-  // the BF16 form reads its transposed sketch in 16-byte groups: splits start on a quantum
-  if (ne_dtype == 2) chunk = (chunk + quantum - 1) / quantum * quantum;
+  // the BF16 form reads its transposed sketch in 16-byte groups, the three-slice form in
+  // 64-sample exponent blocks: splits start on a quantum
+  if (ne_dtype >= 2) chunk = (chunk + quantum - 1) / quantum * quantum;
   pl.chunk = chunk;
   pl.splits = (int)((J + chunk - 1) / chunk);
   return pl;
@@ -430,6 +669,28 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   const unsigned grid = (unsigned)(pl.splits * a.tiles);
   if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s, e0, e1);
+  if (ne_dtype == 3) {
+    switch (pl.mb) {
+#define TRALS_NE3_CASE(MB)                                                                  \
+  case MB:                                                                                  \
+    if (e0)                                                                                 \
+      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a); \
+    else                                                                                    \
+      k_normal_eq_x3<MB><<<grid, 256, 0, s>>>(a);                                           \
+    break;
+      TRALS_NE3_CASE(1)
+      TRALS_NE3_CASE(2)
+      TRALS_NE3_CASE(3)
+      TRALS_NE3_CASE(4)
+      TRALS_NE3_CASE(5)
+      TRALS_NE3_CASE(6)
+      TRALS_NE3_CASE(7)
+      TRALS_NE3_CASE(8)
+#undef TRALS_NE3_CASE
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (ne_dtype == 2) {
     switch (pl.mb) {
 #define TRALS_NE16_CASE(MB)                                                                  \
@@ -453,6 +714,14 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_sketch_split(const float* A, int64_t J, int P, void* S3, int64_t ld, int* E, const int* status,
+                               hipStream_t s) {
+  if (J < 1 || P < 1 || ld % kSplitBlock || ld < J) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((P + 63) / 64), (unsigned)((J + kSplitBlock - 1) / kSplitBlock));
+  k_sketch_split<<<grid, 256, 0, s>>>(A, J, P, (__bf16*)S3, ld, E, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
