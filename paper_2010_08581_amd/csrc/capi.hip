@@ -19,9 +19,11 @@ using namespace trals;
 namespace {
 
 constexpr size_t kAlign = 256;
-// FP32 path contraction: false = FP32 operands widened on the FP64 matrix cores, true = three
-// 8-bit slices on the BF16 matrix cores (exact slice products, FP64 block sums)
-constexpr bool kFp32ThreeSlice = false;
+// FP32 path contraction: FP32 operands widened on the FP64 matrix cores, or (when some update
+// has more than kThreeSliceMinP unknowns) three 8-bit slices on the BF16 matrix cores (exact
+// slice products, FP64 block sums), which keeps two waves per SIMD only up to 80-row tiles
+// and so wins where the FP64 kernel would need several row tiles anyway
+constexpr int kThreeSliceMinP = 128;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -140,9 +142,10 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   p->sk_sz = p->sk_dt == 0 ? 8 : 4;
   p->panel_dt = p->prec == TRALS_F64 ? 0 : p->prec == TRALS_F32 ? 1 : 2;
   p->panel_sz = p->panel_dt == 0 ? 8 : p->panel_dt == 1 ? 4 : 2;
-  // FP32: FP32 sketch and fibers widened exactly on the FP64 matrix cores (ne_dt 1); the
-  // three-slice form on the BF16 matrix cores (ne_dt 3) is selected by kFp32ThreeSlice
-  p->ne_dt = (p->prec == TRALS_F32 && kFp32ThreeSlice) ? 3 : p->panel_dt;
+  // FP32: FP32 sketch and fibers widened exactly on the FP64 matrix cores (ne_dt 1), or the
+  // three-slice form on the BF16 matrix cores (ne_dt 3) for large P (Pmax is set below)
+  p->ne_dt = p->panel_dt;
+  if (p->prec == TRALS_F32 && p->Pmax > kThreeSliceMinP) p->ne_dt = 3;
   if (d->init_cores && d->init_dtype != TRALS_F64 && d->init_dtype != TRALS_F32) return TRALS_EINVAL;
   if (src) {
     if (src->true_dtype != TRALS_F64 && src->true_dtype != TRALS_F32) return TRALS_EINVAL;

@@ -372,12 +372,15 @@ __device__ __forceinline__ Slices3 split3(double v, int e) {
   return Slices3{{(__bf16)(float)a0, (__bf16)(float)a1, (__bf16)(float)a2}};
 }
 
-// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup
+// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup.  Thread
+// (column c, quarter q) takes the column's maximum and splits 16 samples; the slices pass
+// through LDS so that eight lanes store one column's 64 samples (128 contiguous bytes).
 __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ A, int64_t J, int P,
                                                       __bf16* __restrict__ S3, int64_t ld, int* __restrict__ E,
                                                       const int* status) {
   __shared__ float tile[kSplitBlock][kSplitBlock + 1];
   __shared__ float cmax[4][kSplitBlock];
+  __shared__ __align__(16) __bf16 out[3][kSplitBlock][kSplitBlock + 8];
   if (*status != kDevOk) return;
   const int p0 = blockIdx.x * 64;
   const int64_t j0 = (int64_t)blockIdx.y * kSplitBlock;
@@ -392,29 +395,44 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
   for (int r = 16 * q; r < 16 * q + 16; ++r) mx = fmaxf(mx, fabsf(tile[r][c]));
   cmax[q][c] = mx;
   __syncthreads();
-  if (p >= P) return;
   const int e = block_exponent((double)fmaxf(fmaxf(cmax[0][c], cmax[1][c]), fmaxf(cmax[2][c], cmax[3][c])));
-  if (q == 0) E[(int64_t)blockIdx.y * P + p] = e;
-  bf8 o[3][2];
+  if (q == 0 && p < P) E[(int64_t)blockIdx.y * P + p] = e;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const Slices3 x = split3((double)tile[16 * q + r][c], e);
 #pragma unroll
-    for (int sl = 0; sl < 3; ++sl) o[sl][r / 8][r % 8] = x.s[sl];
+    for (int sl = 0; sl < 3; ++sl) out[sl][c][16 * q + r] = x.s[sl];
   }
-#pragma unroll
-  for (int sl = 0; sl < 3; ++sl) {
-    bf8* dst = (bf8*)(S3 + ((int64_t)sl * P + p) * ld + j0 + 16 * q);
-    dst[0] = o[sl][0];
-    dst[1] = o[sl][1];
+  __syncthreads();
+  // 3 slices x 64 columns x 8 pieces of 16 bytes: 6 per thread, eight lanes per column row
+  for (int u = threadIdx.x; u < 3 * 64 * 8; u += 256) {
+    const int sl = u / 512, rem = u - sl * 512, cc = rem >> 3, pc = rem & 7;
+    if (p0 + cc < P)
+      *(bf8*)(S3 + ((int64_t)sl * P + p0 + cc) * ld + j0 + 8 * pc) = *(const bf8*)(&out[sl][cc][8 * pc]);
   }
 }
 
+// Workgroup of 8 waves on a (16 MB) x 64 tile.  Wave group g (waves 4g .. 4g + 3) takes the
+// 32-sample half g of every 64-sample block (one matrix-core k-step); wave 4g + c owns tile
+// columns 16c .. 16c + 15 and all MB row blocks.  The sketch rows of the tile (three slices,
+// both halves) are staged in LDS by the whole workgroup, double-buffered with one barrier per
+// block; each wave loads the column operand of its own columns and half directly into the
+// matrix-core registers, one block ahead: Gram tiles read the sketch slices, data tiles gather
+// the fibers and split them (exponent per column and half: the 32 samples of a column sit in
+// lanes li, li + 16, li + 32, li + 48).  The two groups' FP64 sums are added at the end.
+constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
+                           // of 16 rows fall on distinct banks)
+
 template <int MB>
-__global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
+__global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
+  constexpr int kBufElems = 3 * RT * kX3Ld;            // one buffer of staged sketch slices
+  constexpr int kChunks = 3 * RT * (kSplitBlock / 8);  // 16-byte pieces of a buffer
+  constexpr int kCPT = (kChunks + 511) / 512;          // per thread
+  extern __shared__ __align__(16) unsigned char x3_smem[];
   __shared__ int64_t s_roff[kMaxChunk];
-  __shared__ double s_w[kMaxChunk];
+  __shared__ float s_w[kMaxChunk];
+  __shared__ int s_ea[2][RT];
   if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
@@ -428,14 +446,17 @@ __global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
   const int nrows = (int)(r1 - r0);
   const int nblk = (nrows + kSplitBlock - 1) / kSplitBlock;
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+  const int g = wave >> 2, wc = wave & 3;
   const int li = lane & 15, lg = lane >> 4;
+  __bf16* Ab = (__bf16*)x3_smem;  // [2][3][RT][kX3Ld]
   const float* X = (const float*)a.panel;
   if (!gram) {
-    // row offsets and weights of the chunk's samples; past the chunk the weight is zero
-    for (int r = threadIdx.x; r < nblk * kSplitBlock; r += 256) {
+    // row offsets and (FP32) weights of the chunk's samples; past the chunk the weight is zero
+    for (int r = tid; r < nblk * kSplitBlock; r += 512) {
       int64_t off = 0;
-      double w = 0.0;
+      float w = 0.f;
       if (r < nrows) {
         if (a.direct) {
           off = r0 + r;
@@ -443,27 +464,90 @@ __global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
           const int32_t* ij = a.idx + (r0 + r) * a.K;
           for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
         }
-        w = a.w[r0 + r];
+        w = (float)a.w[r0 + r];
       }
       s_roff[r] = off * In;
       s_w[r] = w;
     }
-    __syncthreads();
   }
   const __bf16* S3 = (const __bf16*)a.S3;
   const int64_t ld = a.ld, sstride = (int64_t)P * ld;
   const int64_t eb0 = r0 / kSplitBlock;
-  // row operand: sketch row p = row0 + 16 m + li (clamped: rows past P are computed, not stored)
-  const __bf16* arow[MB];
+  // staging of the sketch rows: piece q = (slice, row, 8-sample group)
+  bf8 stg[kCPT];
+  int stg_ea = 0;
+  auto load_a = [&](int b) {
+    const int64_t base = r0 + (int64_t)b * kSplitBlock;
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int pr = row0 + 16 * m + li;
-    arow[m] = S3 + (int64_t)(pr < P ? pr : P - 1) * ld + r0;
-  }
-  const int bc = col0 + 16 * wave + li;
-  const int bcg = bc < P ? bc : P - 1;                    // Gram side: sketch column
+    for (int u = 0; u < kCPT; ++u) {
+      const int q = tid + 512 * u;
+      const int qc = q < kChunks ? q : kChunks - 1;
+      const int sl = qc / (RT * 8), rem = qc - sl * (RT * 8), r = rem >> 3, c8 = rem & 7;
+      const int pr = row0 + r < P ? row0 + r : P - 1;
+      stg[u] = *(const bf8*)(S3 + sl * sstride + (int64_t)pr * ld + base + 8 * c8);
+    }
+    if (tid < RT) stg_ea = a.E[(eb0 + b) * P + (row0 + tid < P ? row0 + tid : P - 1)];
+  };
+  auto store_a = [&](int buf) {
+    __bf16* dst = Ab + buf * kBufElems;
+#pragma unroll
+    for (int u = 0; u < kCPT; ++u) {
+      const int q = tid + 512 * u;
+      if (q < kChunks) {
+        const int sl = q / (RT * 8), rem = q - sl * (RT * 8), r = rem >> 3, c8 = rem & 7;
+        *(bf8*)(dst + (sl * RT + r) * kX3Ld + 8 * c8) = stg[u];
+      }
+    }
+    if (tid < RT) s_ea[buf][tid] = stg_ea;
+  };
+  // column operand of this wave: Gram tiles, sketch column bcg; data tiles, fiber entry bcol
+  const int bc = col0 + 16 * wc + li;
+  const int bcg = bc < P ? bc : P - 1;
+  const int bcol = bc < In ? bc : In - 1;
   const __bf16* brow = S3 + (int64_t)bcg * ld + r0;
-  const int bcol = bc < In ? bc : In - 1;                 // data side: fiber entry
+  bf8 nb3[3];     // next block's column operand (Gram tiles)
+  float nx[8];    // next block's fiber values (data tiles)
+  int ncol_e = 0;
+  auto load_b = [&](int b) {
+    const int k0 = b * kSplitBlock + 32 * g + 8 * lg;  // this lane's 8 samples
+    if (gram) {
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) nb3[sl] = *(const bf8*)(brow + sl * sstride + k0);
+      ncol_e = a.E[(eb0 + b) * P + bcg];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) nx[e] = s_w[k0 + e] * X[s_roff[k0 + e] + bcol];
+    }
+  };
+  bf8 cb[3];  // this block's column operand
+  int fcol = 0;
+  auto take_b = [&]() {
+    if (gram) {
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) cb[sl] = nb3[sl];
+      fcol = ncol_e;
+    } else {
+      float mx = 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(nx[e]));
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      fcol = block_exponent((double)mx);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        // y = v 2^(8 - f) in FP32 (|y| < 256; exact power-of-two scaling), then three 8-bit
+        // slices by exact FP32 steps
+        const float y = ldexpf(nx[e], 8 - fcol);
+        const float a0 = rintf(y);
+        const float q1 = (y - a0) * 256.f;
+        const float a1 = rintf(q1);
+        const float a2 = rintf((q1 - a1) * 256.f);
+        cb[0][e] = (__bf16)a0;
+        cb[1][e] = (__bf16)a1;
+        cb[2][e] = (__bf16)a2;
+      }
+    }
+  };
   f4 acc[MB][5];
   double out[MB][4];
 #pragma unroll
@@ -473,76 +557,68 @@ __global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
   }
+  if (!gram) __syncthreads();  // row offsets and weights
+  load_a(0);
+  load_b(0);
+  store_a(0);
+  take_b();
+  __syncthreads();
   for (int b = 0; b < nblk; ++b) {
-    const int base = b * kSplitBlock;
-    const int* Eb = a.E + (eb0 + b) * P;
-    bf8 bs[3][2];
-    int fcol;
-    if (gram) {
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int sl = 0; sl < 3; ++sl) bs[sl][ks] = *(const bf8*)(brow + sl * sstride + base + 32 * ks + 8 * lg);
-      fcol = Eb[bcg];
-    } else {
-      double v[2][8];
-      double mx = 0.0;
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int r = base + 32 * ks + 8 * lg + e;
-          v[ks][e] = s_w[r] * (double)X[s_roff[r] + bcol];
-          mx = fmax(mx, fabs(v[ks][e]));
-        }
-      // the block's 64 samples of this column are held by lanes li, li + 16, li + 32, li + 48
-      mx = fmax(mx, __shfl_xor(mx, 16));
-      mx = fmax(mx, __shfl_xor(mx, 32));
-      fcol = block_exponent(mx);
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const Slices3 x = split3(v[ks][e], fcol);
-#pragma unroll
-          for (int sl = 0; sl < 3; ++sl) bs[sl][ks][e] = x.s[sl];
-        }
+    const int buf = b & 1;
+    if (b + 1 < nblk) {
+      load_a(b + 1);
+      load_b(b + 1);
     }
+    const __bf16* As = Ab + buf * kBufElems;
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
-      bf8 as[3][2];
+      bf8 av[3];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
+      for (int sl = 0; sl < 3; ++sl) av[sl] = *(const bf8*)(As + (sl * RT + 16 * m + li) * kX3Ld + 32 * g + 8 * lg);
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl) as[sl][ks] = *(const bf8*)(arow[m] + sl * sstride + base + 32 * ks + 8 * lg);
+      for (int si = 0; si < 3; ++si)
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int si = 0; si < 3; ++si)
-#pragma unroll
-          for (int ti = 0; ti < 3; ++ti)
-            acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[si][ks], bs[ti][ks], acc[m][si + ti], 0, 0, 0);
+        for (int ti = 0; ti < 3; ++ti)
+          acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[ti], acc[m][si + ti], 0, 0, 0);
+      // one row block's operands live at a time (the loads of the next block stay in flight)
+      __builtin_amdgcn_sched_barrier(0);
     }
     // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int pr = row0 + 16 * m + 4 * lg + q;
-        const int erow = Eb[pr < P ? pr : P - 1];
         double v = (double)acc[m][4][q];
         v = fma(v, 0.00390625, (double)acc[m][3][q]);
         v = fma(v, 0.00390625, (double)acc[m][2][q]);
         v = fma(v, 0.00390625, (double)acc[m][1][q]);
         v = fma(v, 0.00390625, (double)acc[m][0][q]);
-        out[m][q] += ldexp(v, erow + fcol - 16);
+        out[m][q] += ldexp(v, s_ea[buf][16 * m + 4 * lg + q] + fcol - 16);
       }
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+    if (b + 1 < nblk) {
+      store_a(buf ^ 1);
+      take_b();
+    }
+    __syncthreads();
   }
-  const int col = col0 + wave * 16 + li;
+  // fixed-order sum of the two groups: group 1 through LDS, added to group 0's
+  double* red = (double*)x3_smem;
+  if (g == 1)
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[((wc * MB + m) * 4 + q) * 64 + lane] = out[m][q];
+  __syncthreads();
+  if (g == 1) return;
+  const int col = col0 + wc * 16 + li;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[m][q] += red[((wc * MB + m) * 4 + q) * 64 + lane];
   if (gram) {
     double* H = a.Hpart + (int64_t)s * P * P;
 #pragma unroll
@@ -562,6 +638,12 @@ __global__ __launch_bounds__(256) void k_normal_eq_x3(NormalEqArgs a) {
         if (row < P && col < In) B[(int64_t)row * In + col] = out[m][q];
       }
   }
+}
+
+size_t x3_dyn_lds(int mb) {
+  const size_t stage = (size_t)2 * 3 * 16 * mb * kX3Ld * 2;  // two buffers of sketch slices
+  const size_t red = (size_t)4 * mb * 4 * 64 * 8;            // group sums
+  return stage > red ? stage : red;
 }
 
 // Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
@@ -674,9 +756,9 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
 #define TRALS_NE3_CASE(MB)                                                                  \
   case MB:                                                                                  \
     if (e0)                                                                                 \
-      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a); \
+      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(512), x3_dyn_lds(MB), s, e0, e1, 0, a); \
     else                                                                                    \
-      k_normal_eq_x3<MB><<<grid, 256, 0, s>>>(a);                                           \
+      k_normal_eq_x3<MB><<<grid, 512, x3_dyn_lds(MB), s>>>(a);                              \
     break;
       TRALS_NE3_CASE(1)
       TRALS_NE3_CASE(2)

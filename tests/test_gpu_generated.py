@@ -76,3 +76,23 @@ def test_generated_5way_serving_shape_converges():
     f5 = t.fit_error()
     say(f"clean fit {f0:.4e} -> {f5:.4e}")
     assert np.isfinite(f5) and f5 < 0.2 * f0
+
+
+@pytest.mark.parametrize("dims,ranks,prec,J", [
+    ((26, 30, 28), (12, 11, 12), "f64", 1200),   # P = 144, 132, 132: the generated fibers' three
+    ((26, 30, 28), (12, 11, 12), "f32", 1200),   # 48-wide k-rounds; FP32 takes the three-slice path
+    ((9, 8, 10, 7, 8), (12, 5, 12, 4, 12), "f32", 1500),  # order 5, P up to 144
+])
+def test_generated_serving_ranks_lockstep(dims, ranks, prec, J):
+    # serving ranks reach 12 (P = R_{n-1} R_n up to 144): the generated fibers and the rest of
+    # the update against the oracle on the dense tensor of the same definition
+    say(f"case: generated {dims} ranks {ranks} {prec} J={J} lockstep")
+    true = random_cores(dims, ranks, rng_for(24, 1))
+    init = random_cores(dims, ranks, rng_for(24, 3))
+    X, _ = dense_generated(true, 0.01, 3, 17)
+    t = gen_handle(true, ranks, J, 0.01, (3, 17), prec, init)
+    worst = lockstep(t, X, 2 * len(dims), J, core_tol=1e-9 if prec == "f64" else 1e-4)
+    say(f"worst slice {worst:.3e}")
+    fg = t.fit_error()
+    fo = clean_fit(to_np(t.get_cores()), true)
+    assert abs(fg - fo) <= 1e-9 * fo

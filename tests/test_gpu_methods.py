@@ -113,6 +113,23 @@ def test_exact_fp32_lockstep():
     say(f"worst {worst:.3e}")
 
 
+def test_exact_fp32_three_slice_lockstep():
+    # exact TR-ALS with P = 144, 132, 132 in FP32: the enumerated design rows through the
+    # three-slice contraction
+    say("case: exact TR-ALS fp32 26x24x22 R=(12,11,12), lockstep 3 updates")
+    dims, ranks = (26, 24, 22), (12, 11, 12)
+    X = _noisy_ring(dims, ranks, 74).astype(np.float32)
+    init = random_cores(dims, ranks, rng_for(74, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 0, precision="f32", init_cores=init, method="exact")
+    X64 = X.astype(np.float64)
+    for u in range(3):
+        before = to_np(t.get_cores())
+        t.step(1)
+        want = oals.exact_update(X64, before, u)
+        r = assert_core_close(to_np(t.get_cores())[u], want, 1e-4, f"update {u}")
+        say(f"update {u}: worst slice {r:.3e}")
+
+
 def test_exact_full_size_c1():
     # 60^3 (3600-row designs): exact and sampled runs from the same cores reach errors within
     # the paper's (1 + eps) protocol factor

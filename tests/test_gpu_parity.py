@@ -232,3 +232,17 @@ def test_single_workgroup_limit_fp64():
     t = TR(torch.tensor(X, device="cuda"), ranks, 700, precision="f64", init_cores=init)
     worst = lockstep(t, X, 3, 700, core_tol=1e-8)
     say(f"worst core rel diff {worst:.3e}")
+
+
+def test_fp32_three_slice_lockstep():
+    # P = 132, 144, 132 > 128: the FP32 path multiplies three 8-bit slices of the sketch and of
+    # the weighted fibers on the BF16 matrix cores (48-row tiles, exponent blocks of 64 samples,
+    # a ragged last block)
+    say("case: fp32 150x140x130 R=(12,12,11) J=1500 lockstep 4 updates (three-slice contraction)")
+    dims, ranks = (150, 140, 130), (12, 12, 11)
+    X = ring_tensor(random_cores(dims, ranks, rng_for(69, 1)))
+    X = (X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(69, 2).standard_normal(dims)).astype(np.float32)
+    init = random_cores(dims, ranks, rng_for(69, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 1500, precision="f32", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 4, 1500)
+    say(f"worst slice {worst:.3e}")
