@@ -359,17 +359,19 @@ __device__ __forceinline__ int block_exponent(double m) {
   return e;
 }
 
-// three 8-bit slices of y = v 2^(8 - e), |y| < 256 (exact FP64 steps)
+// three 8-bit slices of y = v 2^(8 - e), |y| < 256, of an FP32 value v: the power-of-two
+// scaling, the differences y - rint(y) (|.| <= 1/2, within y's precision) and the products by
+// 256 are exact in FP32, so the slices reproduce y down to 2^-17 (y carries 24 bits)
 struct Slices3 {
   __bf16 s[3];
 };
-__device__ __forceinline__ Slices3 split3(double v, int e) {
-  const double y = ldexp(v, 8 - e);
-  const double a0 = rint(y);
-  const double r1 = (y - a0) * 256.0;
-  const double a1 = rint(r1);
-  const double a2 = rint((r1 - a1) * 256.0);
-  return Slices3{{(__bf16)(float)a0, (__bf16)(float)a1, (__bf16)(float)a2}};
+__device__ __forceinline__ Slices3 split3(float v, int e) {
+  const float y = ldexpf(v, 8 - e);
+  const float a0 = rintf(y);
+  const float r1 = (y - a0) * 256.f;
+  const float a1 = rintf(r1);
+  const float a2 = rintf((r1 - a1) * 256.f);
+  return Slices3{{(__bf16)a0, (__bf16)a1, (__bf16)a2}};
 }
 
 // grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup.  Thread
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
   if (q == 0 && p < P) E[(int64_t)blockIdx.y * P + p] = e;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const Slices3 x = split3((double)tile[16 * q + r][c], e);
+    const Slices3 x = split3(tile[16 * q + r][c], e);
 #pragma unroll
     for (int sl = 0; sl < 3; ++sl) out[sl][c][16 * q + r] = x.s[sl];
   }
@@ -535,16 +537,9 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
       fcol = block_exponent((double)mx);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        // y = v 2^(8 - f) in FP32 (|y| < 256; exact power-of-two scaling), then three 8-bit
-        // slices by exact FP32 steps
-        const float y = ldexpf(nx[e], 8 - fcol);
-        const float a0 = rintf(y);
-        const float q1 = (y - a0) * 256.f;
-        const float a1 = rintf(q1);
-        const float a2 = rintf((q1 - a1) * 256.f);
-        cb[0][e] = (__bf16)a0;
-        cb[1][e] = (__bf16)a1;
-        cb[2][e] = (__bf16)a2;
+        const Slices3 x = split3(nx[e], fcol);
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) cb[sl][e] = x.s[sl];
       }
     }
   };
