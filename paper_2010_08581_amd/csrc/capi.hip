@@ -298,7 +298,7 @@ struct trals_ctx {
 
 namespace {
 
-hipError_t prof_mark(trals_ctx* h, int k, int which) {
+hipError_t prof_mark(trals_ctx* h, int k, int which, hipStream_t s = nullptr) {
   if (!h->prof.on) return hipSuccess;
   Prof& pr = h->prof;
   const size_t slot = 2 * pr.used[k] + which;
@@ -308,7 +308,7 @@ hipError_t prof_mark(trals_ctx* h, int k, int which) {
     if (r != hipSuccess) return r;
     pr.ev[k].push_back(e);
   }
-  const hipError_t r = hipEventRecord(pr.ev[k][slot], h->stream);
+  const hipError_t r = hipEventRecord(pr.ev[k][slot], s ? s : h->stream);
   if (which == 1) pr.used[k] += 1;
   return r;
 }
@@ -336,28 +336,41 @@ hipError_t prof_pair(trals_ctx* h, int k, hipEvent_t* e0, hipEvent_t* e1) {
 
 Ring make_ring(const Problem& p) { return ring_of(p, p.ranks); }
 
-// Sampling table of core m (eq. (3), Definition 4) from the core itself, scanned in place
-// when the draws take inclusive sums.  The numerical rank decides the reading:
+LevWideArgs wide_table_args(trals_ctx* h, int m, const double* G) {
+  LevWideArgs la;
+  memset(&la, 0, sizeof(la));
+  la.G = G;
+  la.I = (int)h->p.dims[m];
+  la.P = P_of(h->p, m);
+  la.K = h->at<double>(h->L.M2);
+  la.F = h->at<double>(h->L.F2);
+  la.qr_work = h->at<double>(h->L.qr);
+  la.Q = h->at<uint64_t>(h->L.cdf[m]);
+  la.status = h->status();
+  la.fail = h->table_fail();
+  la.rel_tol = kTableRelTol;
+  return la;
+}
+
+// Sampling table of mode m (eq. (3), Definition 4) from the rows of G (I_m x P, row i the
+// lateral slice i: the core unfolding G_(2), or a matrix with the same column space), launched
+// on stream s and scanned in place when the draws take inclusive sums.  The numerical rank
+// decides the reading:
 //  * tall (I > P): the column Gram K = G^T G factored with the table tolerance; if it factors,
-//    G_(2) has full column rank and l_i = ||W g_i||^2 (W = L^{-1}); otherwise the leverage
-//    rows' launch takes the table from the pivoted QR of G_(2) (rank-revealing);
-//  * wide (I <= P): the row Gram G G^T factored likewise; if it factors, G_(2) has full row
-//    rank and p_i = 1/I exactly; otherwise the pivoted-QR table.
-int compute_table(trals_ctx* h, int m) {
+//    G has full column rank and l_i = ||W g_i||^2 (W = L^{-1}); otherwise the leverage rows'
+//    launch takes the table from the pivoted QR of G (rank-revealing);
+//  * wide (I <= P): the row Gram G G^T factored likewise; if it factors, G has full row rank
+//    and p_i = 1/I exactly; otherwise the pivoted-QR table.
+int table_launches(trals_ctx* h, int m, const double* G, hipStream_t s) {
   const Problem& p = h->p;
   const int P = P_of(p, m);
   const int I = (int)p.dims[m];
   uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
-  const double* core = h->at<const double>(h->L.core[m]);
-  if (p.method == TRALS_EXACT) {  // no sampling
-    h->table_valid[m] = true;
-    return TRALS_OK;
-  }
-  PROF_BEGIN(TRALS_K_TABLE);
+  HIPTRY(prof_mark(h, TRALS_K_TABLE, 0, s));
   double* M2 = h->at<double>(h->L.M2);
   double* F2 = h->at<double>(h->L.F2);
   if (p.method == TRALS_LEVERAGE && I > P) {
-    HIPTRY(launch_syrk(core, I, P, M2, h->status(), h->stream, /*trans=*/false, h->table_fail()));
+    HIPTRY(launch_syrk(G, I, P, M2, h->status(), s, /*trans=*/false, h->table_fail()));
     CholArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.P = P;
@@ -366,39 +379,36 @@ int compute_table(trals_ctx* h, int m) {
     ca.status = h->status();
     ca.fail = h->table_fail();
     ca.rel_tol = kTableRelTol;
-    HIPTRY(launch_chol(ca, h->stream));
+    HIPTRY(launch_chol(ca, s));
     TriArgs ta;
     memset(&ta, 0, sizeof(ta));
     ta.P = P;
     ta.In_lev = I;
     ta.Wlev = F2;
-    ta.Blev = core;
+    ta.Blev = G;
     ta.Q = Q;
     ta.status = h->status();
     ta.lev_fail = h->table_fail();
     ta.qr_work = h->at<double>(h->L.qr);
-    HIPTRY(launch_trisolve(ta, h->stream));
+    HIPTRY(launch_trisolve(ta, s));
   } else if (p.method == TRALS_LEVERAGE) {
-    LevWideArgs la;
-    memset(&la, 0, sizeof(la));
-    la.G = core;
-    la.I = I;
-    la.P = P;
-    la.K = M2;
-    la.F = F2;
-    la.qr_work = h->at<double>(h->L.qr);
-    la.Q = Q;
-    la.status = h->status();
-    la.fail = h->table_fail();
-    la.rel_tol = kTableRelTol;
-    HIPTRY(launch_lev_wide(la, h->stream));
+    HIPTRY(launch_lev_wide(wide_table_args(h, m, G), s));
   } else {
-    HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
+    HIPTRY(launch_lev_uniform(I, Q, h->status(), s));
   }
-  if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
-  PROF_END(TRALS_K_TABLE);
+  if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Q, I, h->status(), s));
+  HIPTRY(prof_mark(h, TRALS_K_TABLE, 1, s));
   h->table_valid[m] = true;
   return TRALS_OK;
+}
+
+// table of core m from the core itself (initial cores, or after the sample count changed)
+int compute_table(trals_ctx* h, int m) {
+  if (h->p.method == TRALS_EXACT) {  // no sampling
+    h->table_valid[m] = true;
+    return TRALS_OK;
+  }
+  return table_launches(h, m, h->at<const double>(h->L.core[m]), h->stream);
 }
 
 int run_update(trals_ctx* h) {
@@ -527,23 +537,25 @@ int run_update(trals_ctx* h) {
   double* M = h->at<double>(h->L.M);
   double* F = h->at<double>(h->L.F);
   double* Bred = h->at<double>(h->L.Bred);  // I_n x P: row i = b_i
-  // H first; the right-hand sides are needed only by the solve, so for a single-workgroup
-  // factorisation they are reduced by extra workgroups of the factorisation's launch
   const ReduceJob jobH{na.Hpart, (int64_t)P * P, 1, M}, jobB{na.Bpart, (int64_t)P * In, 2, Bred};
-  const bool b_beside = chol_single_workgroup(P);
-  PROF_BEGIN(TRALS_K_REDUCE);
-  HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, h->status(),
-                             h->stream));
-  PROF_END(TRALS_K_REDUCE);
+  // eq. (3): the new core's leverage table.  Its unfolding is G_(2) = B^T H^{-1} (rows z_i =
+  // H^{-1} b_i) with H nonsingular, so G_(2) and B^T have the same column space, hence the same
+  // rank and the same leverage scores (Definition 4).  When both factorisations fit one
+  // workgroup each, the table is taken from B^T beside the factorisation of H (same launches)
+  // instead of after the solve.  B = H G_(2)^T carries the conditioning of H: if the Gram of
+  // B^T does not factor within the table tolerance, the table is instead taken from the pivoted
+  // QR of the new core once it is solved (a launch that does nothing otherwise).  Larger
+  // problems take the table from the new core after the solve.
+  const bool pair = p.method == TRALS_LEVERAGE && chol_single_workgroup(P);
+  const bool wide = In <= P;
+  // without a table beside it, a single-workgroup factorisation reduces B with extra workgroups
+  const bool b_beside = !pair && chol_single_workgroup(P);
   CholArgs ca;
   memset(&ca, 0, sizeof(ca));
   ca.P = P;
   ca.H = M;
   ca.W = F;
   ca.status = h->status();
-  PROF_BEGIN(TRALS_K_FACTOR);
-  HIPTRY(launch_chol(ca, h->stream, b_beside ? &jobB : nullptr, pl.splits));
-  PROF_END(TRALS_K_FACTOR);
   TriArgs ta;
   memset(&ta, 0, sizeof(ta));
   ta.P = P;
@@ -552,18 +564,67 @@ int run_update(trals_ctx* h) {
   ta.Bsol = Bred;
   ta.core = h->at<double>(h->L.core[n]);
   ta.status = h->status();
+  uint64_t* Qn = h->at<uint64_t>(h->L.cdf[n]);
+  PROF_BEGIN(TRALS_K_REDUCE);
+  HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, h->status(),
+                             h->stream));
+  PROF_END(TRALS_K_REDUCE);
+  if (pair) {
+    CholArgs ck;
+    memset(&ck, 0, sizeof(ck));
+    LevWideArgs lw = wide_table_args(h, n, Bred);
+    lw.qr_work = nullptr;  // a breakdown is left to the QR of the new core below
+    if (!wide) {
+      // K = B B^T, factored beside H with the table tolerance; the leverage rows of B^T then
+      // run in the solve's launch
+      PROF_BEGIN(TRALS_K_TABLE);
+      HIPTRY(launch_syrk(Bred, In, P, h->at<double>(h->L.M2), h->status(), h->stream, /*trans=*/false,
+                         h->table_fail()));
+      PROF_END(TRALS_K_TABLE);
+      ck.P = P;
+      ck.H = h->at<double>(h->L.M2);
+      ck.W = h->at<double>(h->L.F2);
+      ck.status = h->status();
+      ck.fail = h->table_fail();
+      ck.rel_tol = kTableRelTol;
+      ta.In_lev = In;
+      ta.Wlev = ck.W;
+      ta.Blev = Bred;
+      ta.Q = Qn;
+      ta.lev_fail = h->table_fail();
+    }
+    PROF_BEGIN(TRALS_K_FACTOR);
+    HIPTRY(launch_chol_pair(ca, wide ? nullptr : &ck, wide ? &lw : nullptr, h->stream));
+    PROF_END(TRALS_K_FACTOR);
+  } else {
+    PROF_BEGIN(TRALS_K_FACTOR);
+    HIPTRY(launch_chol(ca, h->stream, b_beside ? &jobB : nullptr, pl.splits));
+    PROF_END(TRALS_K_FACTOR);
+  }
   PROF_BEGIN(TRALS_K_SOLVE);
   HIPTRY(launch_trisolve(ta, h->stream));
+  PROF_END(TRALS_K_SOLVE);
+  if (pair) {
+    PROF_BEGIN(TRALS_K_TABLE);
+    HIPTRY(launch_lev_fallback(h->at<const double>(h->L.core[n]), In, P, h->at<double>(h->L.qr), Qn,
+                               h->table_fail(), h->status(), h->stream, /*keep_if_clear=*/true));
+    if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Qn, In, h->status(), h->stream));
+    PROF_END(TRALS_K_TABLE);
+  }
   if (p.normalize) {
     const int nx = (n + 1) % N;
+    PROF_BEGIN(TRALS_K_SOLVE);
     HIPTRY(launch_gauge(h->at<double>(h->L.core[n]), In, p.ranks[(n + N - 1) % N], p.ranks[n],
                         h->at<double>(h->L.core[nx]), p.dims[nx], p.ranks[nx], h->at<double>(h->L.M2),
                         h->at<double>(h->L.gauge), h->status(), h->stream));
+    PROF_END(TRALS_K_SOLVE);
   }
-  PROF_END(TRALS_K_SOLVE);
-  // eq. (3): the new core's sampling table
-  const int rc = compute_table(h, n);
-  if (rc) return rc;
+  if (pair) {
+    h->table_valid[n] = true;
+  } else {
+    const int rc = compute_table(h, n);  // from the new core; uniform tables; none when exact
+    if (rc) return rc;
+  }
   h->upd += 1;
   h->have_last = !exact;
   return TRALS_OK;

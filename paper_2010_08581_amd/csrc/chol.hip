@@ -581,9 +581,11 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   const bool lev = (int)blockIdx.x >= a.solve_groups;
   const int grp = lev ? (int)blockIdx.x - a.solve_groups : (int)blockIdx.x;
   if (lev && a.lev_fail && *a.lev_fail) {
-    // the core Gram did not factor: the first table workgroup takes the whole table from the
-    // pivoted QR of the core (its dynamic LDS, 16 nblk rows of 17 doubles, holds the scratch)
-    if (grp == 0) lev_qr_table(a.Blev, a.In_lev, P, a.qr_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
+    // the Gram did not factor: the first table workgroup takes the whole table from the
+    // pivoted QR of Blev (its dynamic LDS, 16 nblk rows of 17 doubles, holds the scratch), or,
+    // without qr_work, a later launch takes it from elsewhere
+    if (grp == 0 && a.qr_work)
+      lev_qr_table(a.Blev, a.In_lev, P, a.qr_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
     return;
   }
   const double* W = lev ? a.Wlev : a.Wsol;
@@ -761,7 +763,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
 // a.K), its factorisation in LDS with the table tolerance, then the uniform table if it
 // factored, else the pivoted-QR table.
 template <int kW>
-__global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca) {
+__device__ __forceinline__ void lev_wide_body(const LevWideArgs& a, const CholArgs& ca) {
   extern __shared__ double lw_smem[];
   __shared__ int s_wide_fail;
   if (*a.status != kDevOk) return;
@@ -827,19 +829,39 @@ __global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca
     const double pr = 1.0 / (double)I;  // full row rank: p_i = l_i / rank = 1 / I
     const uint64_t q = (uint64_t)floor(pr * 4503599627370496.0);
     for (int i = threadIdx.x; i < I; i += 64 * kW) a.Q[i] = q;
-  } else {
+  } else if (a.qr_work) {
     lev_qr_table(a.G, I, P, a.qr_work, a.Q, a.status, (unsigned char*)lw_smem, threadIdx.x, 64 * kW);
   }
+  // without qr_work the breakdown is only reported (a later launch takes the table)
+  if (!a.qr_work && threadIdx.x == 0) *a.fail = ok ? 0 : 1;
 }
 
-// Table from the breakdown word of a factorisation run before: uniform if it factored (a wide
-// core's row Gram), else the pivoted QR of G.
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca) {
+  lev_wide_body<kW>(a, ca);
+}
+
+// Two independent single-workgroup jobs in one launch: workgroup 0 factors a0; workgroup 1
+// factors a1, or (wide = 1) takes the table of the wide matrix of lw as k_lev_wide does.
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void k_chol_pair(CholArgs a0, CholArgs a1, LevWideArgs lw, int wide) {
+  if (blockIdx.x == 1 && wide) {
+    lev_wide_body<kW>(lw, a1);
+    return;
+  }
+  chol_body<false, kW>(blockIdx.x == 0 ? a0 : a1);
+}
+
+// Table from the breakdown word of a factorisation run before: the pivoted QR of G if it broke
+// down; else uniform (a wide core's row Gram factored), or nothing (keep_if_clear: the table
+// was written already).
 __global__ __launch_bounds__(1024) void k_lev_fallback(const double* __restrict__ G, int I, int P,
                                                        double* __restrict__ qr_work, uint64_t* __restrict__ Q,
-                                                       const int* fail, int* status) {
+                                                       const int* fail, int* status, int keep_if_clear) {
   extern __shared__ unsigned char lf_smem[];
   if (*status != kDevOk) return;
   if (*fail == 0) {
+    if (keep_if_clear) return;
     const double pr = 1.0 / (double)I;
     const uint64_t q = (uint64_t)floor(pr * 4503599627370496.0);
     for (int i = threadIdx.x; i < I; i += 1024) Q[i] = q;
@@ -938,13 +960,15 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
 }
 
 hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
-                               int* status, hipStream_t s) {
-  k_lev_fallback<<<1, 1024, lev_qr_smem_bytes(P), s>>>(G, I, P, qr_work, Q, fail, status);
+                               int* status, hipStream_t s, bool keep_if_clear) {
+  k_lev_fallback<<<1, 1024, lev_qr_smem_bytes(P), s>>>(G, I, P, qr_work, Q, fail, status, keep_if_clear ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
-  if (a.I > a.P || a.I < 1 || (a.P + 15) / 16 > kMaxBlk) return hipErrorInvalidValue;
+namespace {
+
+// the row-Gram factorisation of a wide table: only the breakdown matters, not W's bands
+CholArgs wide_chol_args(const LevWideArgs& a) {
   CholArgs ca;
   memset(&ca, 0, sizeof(ca));
   ca.P = a.I;
@@ -954,13 +978,54 @@ hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
   ca.fail = a.fail;
   ca.rel_tol = a.rel_tol;
   ca.factor_only = 1;
+  return ca;
+}
+
+// dynamic LDS of a single-workgroup wide table with kW waves
+size_t wide_lds(const LevWideArgs& a, int kW) {
+  const size_t need = chol_work_doubles(a.I) * sizeof(double);
+  const size_t qr = lev_qr_smem_bytes(a.P);
+  const size_t red = (size_t)kW * kBlk * sizeof(double);  // Gram partial blocks
+  size_t lds = need > qr ? need : qr;
+  return lds > red ? lds : red;
+}
+
+}  // namespace
+
+hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s) {
+  if ((a1 == nullptr) == (lw == nullptr) || !chol_single_workgroup(a0.P)) return hipErrorInvalidValue;
+  if (a1 && !chol_single_workgroup(a1->P)) return hipErrorInvalidValue;
+  if (lw && (lw->I > lw->P || lw->I < 1 || !chol_single_workgroup(lw->I) || (lw->P + 15) / 16 > kMaxBlk))
+    return hipErrorInvalidValue;
+  const int n0 = (a0.P + 15) / 16, n1 = a1 ? (a1->P + 15) / 16 : (lw->I + 15) / 16;
+  const int kW = (n0 <= 4 && n1 <= 4) ? 8 : 16;
+  size_t lds = chol_work_doubles(a0.P) * sizeof(double);
+  CholArgs c1;
+  LevWideArgs l1;
+  memset(&l1, 0, sizeof(l1));
+  if (a1) {
+    c1 = *a1;
+    const size_t b = chol_work_doubles(a1->P) * sizeof(double);
+    lds = b > lds ? b : lds;
+  } else {
+    l1 = *lw;
+    c1 = wide_chol_args(*lw);
+    const size_t b = wide_lds(*lw, kW);
+    lds = b > lds ? b : lds;
+  }
+  if (kW == 8)
+    k_chol_pair<8><<<2, 512, lds, s>>>(a0, c1, l1, lw ? 1 : 0);
+  else
+    k_chol_pair<16><<<2, 1024, lds, s>>>(a0, c1, l1, lw ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
+  if (a.I > a.P || a.I < 1 || (a.P + 15) / 16 > kMaxBlk) return hipErrorInvalidValue;
+  const CholArgs ca = wide_chol_args(a);
   if (chol_single_workgroup(a.I)) {
     const bool small = (a.I + 15) / 16 <= 4;
-    const size_t need = chol_work_doubles(a.I) * sizeof(double);
-    const size_t qr = lev_qr_smem_bytes(a.P);
-    const size_t red = (size_t)(small ? 8 : 16) * kBlk * sizeof(double);  // Gram partial blocks
-    size_t lds = need > qr ? need : qr;
-    lds = lds > red ? lds : red;
+    const size_t lds = wide_lds(a, small ? 8 : 16);
     if (small)
       k_lev_wide<8><<<1, 512, lds, s>>>(a, ca);
     else

@@ -157,7 +157,8 @@ bool chol_single_workgroup(int P);  // the factorisation runs as one workgroup (
 // table weights Q_i = floor(||W g_i||^2 / P * 2^52) of the rows of Blev (In_lev x P, a core
 // unfolding).  Either part is skipped when its W is NULL.  When *lev_fail is set (the core
 // Gram's factorisation broke down) the table comes from the pivoted QR of Blev instead
-// (levqr.h), with qr_work (In_lev * P doubles) as its work memory.
+// (levqr.h), with qr_work (In_lev * P doubles) as its work memory; with qr_work NULL the
+// table is left to a later launch.
 struct TriArgs {
   int P, In_sol, In_lev;
   const double* Wsol;
@@ -179,6 +180,7 @@ hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
 // launch does all of it (Gram into K, factorisation in LDS, table); above, the Gram and the
 // blocked factorisation are separate launches (CholArgs with fail) and launch_lev_fallback
 // writes the table.  K: I x I doubles, F: chol_work_doubles(I), qr_work: I * P doubles.
+// Without qr_work a breakdown only sets *fail (cleared otherwise) and Q is not written.
 struct LevWideArgs {
   const double* G;
   int I, P;
@@ -191,10 +193,15 @@ struct LevWideArgs {
   double rel_tol;
 };
 hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s);
-// table from *fail: uniform (1/I) if it is clear, else the pivoted QR of G (one workgroup)
+// table from *fail: the pivoted QR of G (one workgroup) if it is set; if it is clear, uniform
+// (1/I), or nothing when keep_if_clear
 hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
-                               int* status, hipStream_t s);
+                               int* status, hipStream_t s, bool keep_if_clear = false);
 constexpr double kTableRelTol = 1e-8;  // pivot tolerance of the table factorisations
+// Two independent single-workgroup jobs in one launch (both sizes must satisfy
+// chol_single_workgroup): the factorisation a0, beside either the factorisation *a1 or the
+// whole table of the wide matrix *lw (exactly one of a1, lw non-null).
+hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s);
 
 // ---- generated data source and transfer-matrix inner products ----
 // Sampled fibers of X = TR(G*) + sigma Z: out[j][i] = sum_p G*_n[i][p] T[j][p] + sigma z(lin),

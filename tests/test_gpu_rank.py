@@ -13,6 +13,12 @@ of rank 5 < P, a tall core with cond(G_(2)) = 1e6 (full rank, but its Gram squar
 1e12) and a square core with cond 1e7 (full row rank: the uniform table); then the same paths
 at sizes past the single-workgroup factorisation (a 200 x 256 wide core with and without a
 zero slice, a 300 x 168 tall core of rank 100).
+
+After an update the table of the new core is taken from the right-hand sides B (its unfolding
+is B^T H^{-1}, the same column space); when the Gram of B^T does not factor within the table
+tolerance, from the pivoted QR of the new core.  The last two cases force that: one bond index
+of the neighbouring core scaled by 1e-5 scales the matching design columns, so that H and B
+(pivots about 1e-11 of the largest) and the new core are all badly scaled, tall and wide.
 """
 import numpy as np
 import pytest
@@ -74,6 +80,13 @@ def ill_conditioned(m, log10_cond, seed):
     return f
 
 
+def small_bond(m, s):
+    def f(c):
+        c[m][:, :, 0] *= s
+        return c
+    return f
+
+
 CASES = [
     ("wide zero slice", (8, 9, 10), (3, 3, 3), zero_slice(1, 4), 0, 64),
     ("wide dependent slices", (8, 9, 10), (3, 3, 3), dependent_slice(1, 2, 7, 2.0), 0, 64),
@@ -83,6 +96,8 @@ CASES = [
     ("wide 200x256 zero slice", (200, 20, 20), (16, 16, 16), zero_slice(0, 17), 1, 600),
     ("wide 200x256 full rank", (200, 20, 20), (16, 16, 16), lambda c: c, 1, 600),
     ("tall 300x168 rank 100", (300, 12, 12), (12, 13, 14), low_rank(0, 100, 4), 1, 800),
+    ("tall B Gram breakdown", (30, 31, 32), (3, 3, 3), small_bond(0, 1e-5), 1, 200),
+    ("wide B Gram breakdown", (8, 9, 10), (3, 3, 3), small_bond(2, 1e-5), 0, 64),
 ]
 
 
