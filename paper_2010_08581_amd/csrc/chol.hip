@@ -31,7 +31,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kLd = 17;         // padded row stride of a 16 x 16 block (doubles)
 constexpr int kBlk = 16 * kLd;  // doubles per stored block
 constexpr int kLdsBlocks = 9;   // nblk up to which a factor is staged in LDS (45 blocks, 98 KB)
-constexpr int kCholWaves = 16;
+constexpr int kCholWaves = 8;  // waves per workgroup of the large-P steps
 constexpr int kMaxBlk = 64;     // P <= 1024
 
 __device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -99,6 +99,28 @@ template <typename Ptr>
 __device__ __forceinline__ void store_acc(Ptr C, d4 v, int lane) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) C[(4 * r + (lane >> 4)) * kLd + (lane & 15)] = v[r];
+}
+
+// a lane's four operand values of a 16 x 16 block (row-major, stride kLd) for mma_frag: entry
+// (lane % 16, 4 ks + lane / 16) for ks = 0 .. 3
+template <typename Ptr>
+__device__ __forceinline__ void load_frag(Ptr X, int lane, double f[4]) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) f[ks] = X[(lane & 15) * kLd + 4 * ks + (lane >> 4)];
+}
+
+// the inverse of load_frag: write a lane's four operand values of a 16 x 16 block
+template <typename Ptr>
+__device__ __forceinline__ void store_frag(Ptr X, const d4& f, int lane) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) X[(lane & 15) * kLd + 4 * ks + (lane >> 4)] = f[ks];
+}
+
+// acc += sign * A B^T from fragments loaded by load_frag (the same product as mma_abt)
+__device__ __forceinline__ d4 mma_frag(const double a[4], const double b[4], d4 acc, double sign) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) acc = mfma(sign * a[ks], b[ks], acc);
+  return acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -184,10 +206,26 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   double* Ls = lds;
   if (kRegion) {
-    for (int e = threadIdx.x; e < nslots * kBlk; e += kThr) {
-      int bi, bj;
-      slot_ij(e / kBlk, bi, bj);
-      Ls[e] = a.Lg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk];
+    // eight loads in flight per thread before any store
+    constexpr int kB = 8;
+    const int tot = nslots * kBlk;
+    for (int base = 0; base < tot; base += kB * kThr) {
+      double v[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + q * kThr;
+        v[q] = 0.0;
+        if (e < tot) {
+          int bi, bj;
+          slot_ij(e / kBlk, bi, bj);
+          v[q] = a.Lg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + q * kThr;
+        if (e < tot) Ls[e] = v[q];
+      }
     }
   } else {
     // stage the lower blocks (full diagonal blocks; identity on the padded diagonal), eight
@@ -224,19 +262,32 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
       s_tol = a.scal[0];
       s_fail = 0;
     }
-    // the previous step's trailing update of this region, A_ij -= sum_c L(i, pb0 + c)
-    // L(j, pb0 + c)^T: the same products in the same order as for the blocks below the region
-    if (a.pnb > 0)
+    // the previous step's panel for the rows of this region, L(i, pb0 + c) = sum_{c' <= c}
+    // A(i, pb0 + c') W(pb0 + c, pb0 + c')^T (into LDS after the staging blocks, and into Lp),
+    // then its trailing update A_ij -= sum_c L(i, pb0 + c) L(j, pb0 + c)^T
+    if (a.pnb > 0) {
+      double* Lsc = Ls + (nslots + nblk) * kBlk;  // nblk x pnb blocks
+      for (int t = wave; t < nblk * a.pnb; t += kW) {
+        const int bi = t / a.pnb, c = t - bi * a.pnb;
+        d4 f = {0.0, 0.0, 0.0, 0.0};
+        for (int c2 = 0; c2 <= c; ++c2)
+          f = mma_abt(a.W + (int64_t)slot(a.pb0 + c, a.pb0 + c2) * kBlk,
+                      a.Lg + (int64_t)slot(g0 + bi, a.pb0 + c2) * kBlk, f, lane, 1.0);
+        // f holds W L^T's block, i.e. L(g0 + bi, pb0 + c) in operand order
+        store_frag(Lsc + t * kBlk, f, lane);
+        store_frag(a.Lp + (int64_t)slot(g0 + bi, a.pb0 + c) * kBlk, f, lane);
+      }
+      __syncthreads();
       for (int sl = wave; sl < nslots; sl += kW) {
         int bi, bj;
         slot_ij(sl, bi, bj);
         double* Ab = Ls + sl * kBlk;
         d4 acc = load_acc(Ab, lane);
         for (int c = 0; c < a.pnb; ++c)
-          acc = mma_abt(a.Lg + (int64_t)slot(g0 + bi, a.pb0 + c) * kBlk, a.Lg + (int64_t)slot(g0 + bj, a.pb0 + c) * kBlk,
-                        acc, lane, -1.0);
+          acc = mma_abt(Lsc + (bi * a.pnb + c) * kBlk, Lsc + (bj * a.pnb + c) * kBlk, acc, lane, -1.0);
         store_acc(Ab, acc, lane);
       }
+    }
   } else if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < P; i += 64) mx = fmax(mx, Ls[slot(i >> 4, i >> 4) * kBlk + (i & 15) * kLd + (i & 15)]);
@@ -474,85 +525,102 @@ __global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, 
   }
 }
 
-// one wave per block row i >= b0 + nb: L(i, b0 + q) = sum_{c <= q} A(i, b0 + c) W(b0 + q, b0 + c)^T
-__global__ __launch_bounds__(256) void k_big_panel(double* __restrict__ Lg, const double* __restrict__ W, int nblk,
-                                                   int b0, int nb, const int* status, const int* fail) {
-  if (*status != kDevOk || (fail && *fail)) return;
-  const int lane = threadIdx.x & 63;
-  const int i = b0 + nb + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (i >= nblk) return;
-  d4 acc[4];
+// Trailing block (i, j) after the step on the four blocks b0 .. b0 + 3 (i >= j beyond them), by
+// one wave.  The panel rows it needs are formed here, L(x, b0 + c) = sum_{c' <= c}
+// A(x, b0 + c') W(b0 + c, b0 + c')^T for x = i, j (every operand loaded before the first
+// product); then A_ij -= sum_c L(i, b0 + c) L(j, b0 + c)^T.  The wave of the diagonal block
+// (i, i) stores row i of the panel into Lp.  The products W A^T leave L in operand order, so no
+// exchange between lanes is needed.
+__device__ __forceinline__ void trail_block(double* __restrict__ Lg, double* __restrict__ Lp,
+                                            const double* __restrict__ W, int i, int j, int b0, int lane) {
+  double fw[10][4], fi[4][4], fj[4][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-    if (q < nb)
-      for (int c = 0; c <= q; ++c)
-        acc[q] = mma_abt(Lg + (int64_t)slot(i, b0 + c) * kBlk, W + (int64_t)slot(b0 + q, b0 + c) * kBlk, acc[q],
-                         lane, 1.0);
+  for (int c = 0, t = 0; c < 4; ++c)
+#pragma unroll
+    for (int c2 = 0; c2 <= c; ++c2, ++t) load_frag(W + (int64_t)slot(b0 + c, b0 + c2) * kBlk, lane, fw[t]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    load_frag(Lg + (int64_t)slot(i, b0 + c) * kBlk, lane, fi[c]);
+    load_frag(Lg + (int64_t)slot(j, b0 + c) * kBlk, lane, fj[c]);
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (q < nb) store_acc(Lg + (int64_t)slot(i, b0 + q) * kBlk, acc[q], lane);
-}
-
-// trailing block (i, j) after the step on blocks b0 .. b0 + nb - 1 (b0 + nb <= j <= i), by one
-// wave: A_ij -= sum_q L(i, b0 + q) L(j, b0 + q)^T
-__device__ __forceinline__ void trail_block(double* __restrict__ Lg, int i, int j, int b0, int nb, int lane) {
   double* Aij = Lg + (int64_t)slot(i, j) * kBlk;
   d4 acc = load_acc(Aij, lane);
-  for (int c = 0; c < nb; ++c)
-    acc = mma_abt(Lg + (int64_t)slot(i, b0 + c) * kBlk, Lg + (int64_t)slot(j, b0 + c) * kBlk, acc, lane, -1.0);
+#pragma unroll
+  for (int c = 0, t = 0; c < 4; ++c) {
+    d4 li = {0.0, 0.0, 0.0, 0.0}, lj = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c2 = 0; c2 <= c; ++c2, ++t) {
+      li = mma_frag(fw[t], fi[c2], li, 1.0);
+      if (i != j) lj = mma_frag(fw[t], fj[c2], lj, 1.0);
+    }
+    if (i == j) {
+      lj = li;
+      store_frag(Lp + (int64_t)slot(i, b0 + c) * kBlk, li, lane);
+    }
+    const double a4[4] = {li[0], li[1], li[2], li[3]}, b4[4] = {lj[0], lj[1], lj[2], lj[3]};
+    acc = mma_frag(a4, b4, acc, -1.0);
+  }
   store_acc(Aij, acc, lane);
 }
 
-// band I (blocks 4I .. 4I + nbI - 1), one workgroup per band J < I: 16 waves, wave (r, c) the
-// output block (4I + r, 4J + c)
-__device__ __forceinline__ void wrow_body(const double* __restrict__ Lg, double* __restrict__ W, int nblk, int I,
+// band I (blocks 4I .. 4I + nbI - 1), one workgroup per band J < I: 8 waves, wave (r, c) the
+// output blocks (4I + r, 4J + c) and (4I + r + 2, 4J + c); L read from Lp
+__device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double* __restrict__ W, int nblk, int I,
                                           int J) {
   __shared__ double stage[16][16 * kLd];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
-  const int r = wave >> 2, c = wave & 3;
+  const int r0 = wave >> 2, c = wave & 3;
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
-  const int bi = 4 * I + r, bj = 4 * J + c;
-  d4 sacc = {0.0, 0.0, 0.0, 0.0};
-  if (r < nbI) {
-    for (int M = J; M < I; ++M)
-      for (int m = 0; m < 4; ++m) {
-        const int bm = 4 * M + m;
-        if (bm < bj) continue;  // W(bm, bj) is zero above the diagonal
-        sacc = mma_ab(Lg + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
-      }
-  }
-  store_acc(stage[wave], sacc, lane);
-  __syncthreads();
-  if (r >= nbI) return;
-  d4 w = {0.0, 0.0, 0.0, 0.0};
-  for (int r2 = 0; r2 <= r; ++r2)
-    w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage[4 * r2 + c], w, lane);
+  const int bj = 4 * J + c;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) w[q] = -w[q];
-  store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 2 * h, bi = 4 * I + r;
+    d4 sacc = {0.0, 0.0, 0.0, 0.0};
+    if (r < nbI) {
+      for (int M = J; M < I; ++M)
+        for (int m = 0; m < 4; ++m) {
+          const int bm = 4 * M + m;
+          if (bm < bj) continue;  // W(bm, bj) is zero above the diagonal
+          sacc = mma_ab(Lp + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
+        }
+    }
+    store_acc(stage[4 * r + c], sacc, lane);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + 2 * h, bi = 4 * I + r;
+    if (r < nbI) {
+      d4 w = {0.0, 0.0, 0.0, 0.0};
+      for (int r2 = 0; r2 <= r; ++r2)
+        w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage[4 * r2 + c], w, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = -w[q];
+      store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
+    }
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_big_wrow(const double* __restrict__ Lg, double* __restrict__ W, int nblk,
-                                                   int I, const int* status, const int* fail) {
+__global__ __launch_bounds__(64 * kCholWaves) void k_big_wrow(const double* __restrict__ Lp, double* __restrict__ W,
+                                                              int nblk, int I, const int* status, const int* fail) {
   if (*status != kDevOk || (fail && *fail)) return;
-  wrow_body(Lg, W, nblk, I, blockIdx.x);
+  wrow_body(Lp, W, nblk, I, blockIdx.x);
 }
 
-// Step a.b0 / 4 > 0 of the factorisation in one launch.  Workgroup 0 applies the previous
-// step's trailing update to the diagonal region, then factors and inverts it; workgroups
-// 1 .. I take band I of W (I = 0: none); the rest apply the previous step's trailing update
-// to the blocks below the region, one block per wave.  Only workgroup 0 reads the status word:
-// it may set it meanwhile, and the others' indexing does not depend on the data.
-__global__ __launch_bounds__(1024) void k_chol_step(CholArgs a, int I) {
+// Step a.b0 / 4 > 0 of the factorisation in one launch.  Workgroup 0 forms the previous step's
+// panel for the rows of the diagonal region, applies that step's trailing update to the region,
+// then factors and inverts it; workgroups 1 .. I take band I of W (I = 0: none); the rest apply
+// the previous step's trailing update to the blocks below the region, one block per wave,
+// forming the panel rows they need themselves.  Only workgroup 0 reads the status word: it may
+// set it meanwhile, and the others' indexing does not depend on the data.
+__global__ __launch_bounds__(64 * kCholWaves) void k_chol_step(CholArgs a, int I) {
   const int nblk = (a.P + 15) / 16;
   if (blockIdx.x == 0) {
     chol_body<true, kCholWaves>(a);
     return;
   }
   if ((int)blockIdx.x <= I) {
-    wrow_body(a.Lg, a.W, nblk, I, (int)blockIdx.x - 1);
+    wrow_body(a.Lp, a.W, nblk, I, (int)blockIdx.x - 1);
     return;
   }
   const int q = ((int)blockIdx.x - 1 - I) * kCholWaves + (int)(threadIdx.x >> 6);
@@ -561,7 +629,7 @@ __global__ __launch_bounds__(1024) void k_chol_step(CholArgs a, int I) {
   int ii, jj;
   slot_ij(q, ii, jj);
   if (ii < a.nb) return;  // inside the region: workgroup 0 applies it
-  trail_block(a.Lg, a.b0 + ii, a.b0 + jj, a.pb0, a.pnb, threadIdx.x & 63);
+  trail_block(a.Lg, a.Lp, a.W, a.b0 + ii, a.b0 + jj, a.pb0, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -600,6 +668,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   // their loads) and the Z operands before Y is exchanged, so that their memory latency overlaps
   // that work.  Larger P streams them one block ahead of the matrix cores.
   constexpr bool kHeld = T <= 2;
+  constexpr int kRing = 4;  // W blocks in flight per wave when streamed
   constexpr int kHB = kHeld ? 4 * T : 1;
   double wo[T][kHB][4];
   auto load_y_operands = [&]() {
@@ -655,19 +724,24 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) acc = mfma(wo[t][J][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
     } else if (K < nblk) {
+      // blocks (K, 0 .. K) streamed through a ring of kRing blocks: kRing - 1 loads stay in
+      // flight behind the block in use (clamped to block K past the end)
       const double* Wr = W + (int64_t)slot(K, 0) * kBlk + r16 * kLd + k4;
-      double wc[4];
+      double wb[kRing][4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) wc[ks] = Wr[4 * ks];
-      for (int J = 0; J <= K; ++J) {
-        const int Jn = J < K ? J + 1 : K;
-        double wn[4];
+      for (int d = 0; d < kRing; ++d)
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) wn[ks] = Wr[Jn * kBlk + 4 * ks];
+        for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wr[(d <= K ? d : K) * kBlk + 4 * ks];
+      for (int J0 = 0; J0 <= K; J0 += kRing) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          acc = mfma(wc[ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
-          wc[ks] = wn[ks];
+        for (int d = 0; d < kRing; ++d) {
+          const int J = J0 + d;
+          if (J <= K)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = mfma(wb[d][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+          const int Jn = J + kRing <= K ? J + kRing : K;
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wr[Jn * kBlk + 4 * ks];
         }
       }
     }
@@ -732,22 +806,35 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
             for (int ks = 0; ks < 4; ++ks)
               acc = mfma(wo[t][m][ks], Bs[(16 * (K + m) + 4 * ks + k4) * kLdB + r16], acc);
       } else {
-      int sl = slot(K, K);
-      double wc[4];
+        // blocks (K .. nblk-1, K) through the same ring; block (J, K) is at slot(J, K), and
+        // slot(J + 1, K) = slot(J, K) + J + 1
+        double wb[kRing][4];
+        int sl = slot(K, K), Jl = K;  // next block to load and its slot
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) wc[ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
-      for (int J = K; J < nblk; ++J) {
-        const int sn = J + 1 < nblk ? sl + J + 1 : sl;
-        double wn[4];
+        for (int d = 0; d < kRing; ++d) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) wn[ks] = Wc[(int64_t)sn * kBlk + 4 * ks * kLd];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          acc = mfma(wc[ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
-          wc[ks] = wn[ks];
+          for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
+          if (Jl + 1 < nblk) {
+            sl += Jl + 1;
+            ++Jl;
+          }
         }
-        sl = sn;
-      }
+        for (int J0 = K; J0 < nblk; J0 += kRing) {
+#pragma unroll
+          for (int d = 0; d < kRing; ++d) {
+            const int J = J0 + d;
+            if (J < nblk)
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks)
+                acc = mfma(wb[d][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
+            if (Jl + 1 < nblk) {
+              sl += Jl + 1;
+              ++Jl;
+            }
+          }
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -889,7 +976,7 @@ size_t chol_factor_doubles(int P) {
 size_t chol_work_doubles(int P) {
   const int nblk = (P + 15) / 16;
   if (nblk <= kLdsBlocks) return chol_factor_doubles(P) + (size_t)nblk * kBlk;  // W + staging blocks
-  return 2 * chol_factor_doubles(P) + 8;                                        // W, work matrix, tolerance
+  return 3 * chol_factor_doubles(P) + 8;  // W, work matrix, panel blocks L, tolerance
 }
 
 hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s,
@@ -930,7 +1017,8 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
   }
   CholArgs a = args;
   a.Lg = a.W + chol_factor_doubles(a.P);
-  a.scal = a.W + 2 * chol_factor_doubles(a.P);
+  a.Lp = a.W + 2 * chol_factor_doubles(a.P);
+  a.scal = a.W + 3 * chol_factor_doubles(a.P);
   const int nslots = nblk * (nblk + 1) / 2;
   k_big_init<<<(unsigned)((nslots * kBlk + 255) / 256 < 1024 ? (nslots * kBlk + 255) / 256 : 1024), 256, 0, s>>>(
       a.H, a.P, a.Lg, a.scal, a.status, a.fail ? a.fail : a.status, a.rel_tol);
@@ -940,22 +1028,20 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     a.nb = nblk - a.b0 < 4 ? nblk - a.b0 : 4;
     a.pb0 = K > 0 ? a.b0 - 4 : 0;  // every region but the last has four blocks
     a.pnb = K > 0 ? 4 : 0;
-    const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb) * kBlk * sizeof(double);
+    // region blocks, staging blocks, and the previous step's panel rows of the region
+    const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb + (size_t)a.nb * a.pnb) * kBlk * sizeof(double);
     if (K == 0) {
-      k_chol<true, kCholWaves><<<1, 1024, lds, s>>>(a);
+      k_chol<true, kCholWaves><<<1, 64 * kCholWaves, lds, s>>>(a);
     } else {
       // band K - 1 of W: K - 1 workgroups (none when only the factor's regions are needed)
       const int band = (K >= 2 && !a.factor_only) ? K - 1 : 0;
       const int rem = nblk - a.b0;
       const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
-      k_chol_step<<<(unsigned)(1 + band + tgroups), 1024, lds, s>>>(a, band);
+      k_chol_step<<<(unsigned)(1 + band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
     }
-    const int rows = nblk - a.b0 - a.nb;
-    if (rows > 0)
-      k_big_panel<<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(a.Lg, a.W, nblk, a.b0, a.nb, a.status, a.fail);
   }
   if (nb64 >= 2 && !a.factor_only)
-    k_big_wrow<<<(unsigned)(nb64 - 1), 1024, 0, s>>>(a.Lg, a.W, nblk, nb64 - 1, a.status, a.fail);
+    k_big_wrow<<<(unsigned)(nb64 - 1), 64 * kCholWaves, 0, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status, a.fail);
   return hipGetLastError();
 }
 

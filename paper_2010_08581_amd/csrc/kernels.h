@@ -139,8 +139,10 @@ struct CholArgs {
   double rel_tol;    // 0: P eps
   int factor_only;   // 1: only the factor's diagonal regions of W are needed (large P: the
                      // off-diagonal bands of W are skipped)
-  // set by launch_chol for large P: work matrix, tolerance, and the diagonal region of a step
+  // set by launch_chol for large P: work matrix, panel blocks of L, tolerance, and the diagonal
+  // region of a step
   double* Lg;
+  double* Lp;
   double* scal;
   int b0, nb;
   int pb0, pnb;  // the previous step's region (pnb = 0: none), whose trailing update of this
