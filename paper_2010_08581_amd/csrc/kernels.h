@@ -66,7 +66,7 @@ struct NormalEqArgs {
   int64_t J;
   int64_t chunk;              // sample rows per split
   int P, In;
-  int gram_tiles;             // 64-wide column tiles of the Gram part
+  int gram_tiles;             // column tiles of the Gram part (64 wide; 128, three-slice form)
   int col_tiles, tiles, splits;  // filled in by launch_normal_eq
   double* Hpart;              // splits x P x P (lower triangle written)
   double* Bpart;              // splits x P x I_n

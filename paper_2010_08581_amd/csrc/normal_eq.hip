@@ -32,6 +32,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kColTile = 64;
+constexpr int kX3ColTile = 128;  // column tile of the three-slice kernel (eight waves of 16)
 constexpr int kKB = 32;          // sample rows per LDS stage (8 MFMA k-steps)
 constexpr int kMaxChunk = 1024;  // sample rows per split, padding included (row offsets and weights in LDS)
 constexpr int kLdsBytes = 160 * 1024;
@@ -414,47 +415,40 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
   }
 }
 
-// Workgroup of 8 waves on a (16 MB) x 64 tile.  Wave group g (waves 4g .. 4g + 3) takes the
-// 32-sample half g of every 64-sample block (one matrix-core k-step); wave 4g + c owns tile
-// columns 16c .. 16c + 15 and all MB row blocks.  The sketch rows of the tile (three slices,
-// both halves) are staged in LDS by the whole workgroup, double-buffered with one barrier per
-// block; each wave loads the column operand of its own columns and half directly into the
-// matrix-core registers, one block ahead: Gram tiles read the sketch slices, data tiles gather
-// the fibers and split them (exponent per column and half: the 32 samples of a column sit in
-// lanes li, li + 16, li + 32, li + 48).  The two groups' FP64 sums are added at the end.
+// Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
+// MB row blocks and both 32-sample halves (matrix-core k-steps) of every 64-sample block, so
+// that its five level sums cover 64 samples between FP64 flushes (each stays below 2^22 in
+// magnitude, exact in FP32).  The sketch rows of the tile (three slices, both halves) are staged
+// in LDS by the whole workgroup, double-buffered with one barrier per block; each wave loads the
+// column operand of its own columns directly into the matrix-core registers, one block ahead:
+// Gram tiles read the sketch slices, data tiles gather the fibers and split them (exponent per
+// column and 64-sample block, as the sketch's: a column's 64 samples sit in lanes li, li + 16,
+// li + 32, li + 48, sixteen each).
 constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
                            // of 16 rows fall on distinct banks)
 
-template <int MB>
-__global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
+// One tile of k_normal_eq_x3; GRAM selects the column operand (the two paths' registers are
+// allocated separately).  Data tiles gather their fibers two blocks ahead (the block loop is
+// unrolled by two so that the two gather buffers keep static indices); Gram tiles read their
+// column slices one block ahead.
+template <int MB, bool GRAM>
+__device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, int col0, int64_t* s_roff,
+                                        float* s_w, int (*s_ea)[16 * MB], unsigned char* smem) {
   constexpr int RT = 16 * MB;
   constexpr int kBufElems = 3 * RT * kX3Ld;            // one buffer of staged sketch slices
   constexpr int kChunks = 3 * RT * (kSplitBlock / 8);  // 16-byte pieces of a buffer
   constexpr int kCPT = (kChunks + 511) / 512;          // per thread
-  extern __shared__ __align__(16) unsigned char x3_smem[];
-  __shared__ int64_t s_roff[kMaxChunk];
-  __shared__ float s_w[kMaxChunk];
-  __shared__ int s_ea[2][RT];
-  if (*a.status != kDevOk) return;
   const int P = a.P, In = a.In;
-  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
-  const int s = lb / a.tiles, t = lb - s * a.tiles;
-  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
-  const int row0 = rt * RT;
-  const bool gram = ct < a.gram_tiles;
-  const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
-  if (gram && col0 >= row0 + RT) return;
   const int64_t r0 = (int64_t)s * a.chunk;  // a multiple of kSplitBlock
   const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
   const int nrows = (int)(r1 - r0);
   const int nblk = (nrows + kSplitBlock - 1) / kSplitBlock;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
-  const int g = wave >> 2, wc = wave & 3;
   const int li = lane & 15, lg = lane >> 4;
-  __bf16* Ab = (__bf16*)x3_smem;  // [2][3][RT][kX3Ld]
+  __bf16* Ab = (__bf16*)smem;  // [2][3][RT][kX3Ld]
   const float* X = (const float*)a.panel;
-  if (!gram) {
+  if (!GRAM) {
     // row offsets and (FP32) weights of the chunk's samples; past the chunk the weight is zero
     for (int r = tid; r < nblk * kSplitBlock; r += 512) {
       int64_t off = 0;
@@ -503,44 +497,53 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
     if (tid < RT) s_ea[buf][tid] = stg_ea;
   };
   // column operand of this wave: Gram tiles, sketch column bcg; data tiles, fiber entry bcol
-  const int bc = col0 + 16 * wc + li;
+  const int bc = col0 + 16 * wave + li;
   const int bcg = bc < P ? bc : P - 1;
   const int bcol = bc < In ? bc : In - 1;
   const __bf16* brow = S3 + (int64_t)bcg * ld + r0;
-  bf8 nb3[3];     // next block's column operand (Gram tiles)
-  float nx[8];    // next block's fiber values (data tiles)
+  bf8 nb3[2][3];      // Gram tiles: next block's column slices, both halves
   int ncol_e = 0;
-  auto load_b = [&](int b) {
-    const int k0 = b * kSplitBlock + 32 * g + 8 * lg;  // this lane's 8 samples
-    if (gram) {
+  float nx[2][2][8];  // data tiles: two blocks' fiber values, both halves
+  auto load_b = [&](int b, float (&dst)[2][8]) {
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) nb3[sl] = *(const bf8*)(brow + sl * sstride + k0);
-      ncol_e = a.E[(eb0 + b) * P + bcg];
-    } else {
+    for (int h = 0; h < 2; ++h) {
+      const int k0 = b * kSplitBlock + 32 * h + 8 * lg;  // this lane's 8 samples of half h
+      if (GRAM) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) nx[e] = s_w[k0 + e] * X[s_roff[k0 + e] + bcol];
+        for (int sl = 0; sl < 3; ++sl) nb3[h][sl] = *(const bf8*)(brow + sl * sstride + k0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[h][e] = s_w[k0 + e] * X[s_roff[k0 + e] + bcol];
+      }
     }
+    if (GRAM) ncol_e = a.E[(eb0 + b) * P + bcg];
   };
-  bf8 cb[3];  // this block's column operand
+  bf8 cb[2][3];  // this block's column operand
   int fcol = 0;
-  auto take_b = [&]() {
-    if (gram) {
+  auto take_b = [&](const float (&src)[2][8]) {
+    if (GRAM) {
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) cb[sl] = nb3[sl];
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) cb[h][sl] = nb3[h][sl];
       fcol = ncol_e;
     } else {
       float mx = 0.f;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(nx[e]));
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(src[h][e]));
       mx = fmaxf(mx, __shfl_xor(mx, 16));
       mx = fmaxf(mx, __shfl_xor(mx, 32));
       fcol = block_exponent((double)mx);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const Slices3 x = split3(nx[e], fcol);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl) cb[sl][e] = x.s[sl];
-      }
+        for (int e = 0; e < 8; ++e) {
+          const Slices3 x = split3(src[h][e], fcol);
+#pragma unroll
+          for (int sl = 0; sl < 3; ++sl) cb[h][sl][e] = x.s[sl];
+        }
     }
   };
   f4 acc[MB][5];
@@ -552,30 +555,38 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
   }
-  if (!gram) __syncthreads();  // row offsets and weights
+  if (!GRAM) __syncthreads();  // row offsets and weights
   load_a(0);
-  load_b(0);
+  load_b(0, nx[0]);
   store_a(0);
-  take_b();
+  take_b(nx[0]);
+  if (nblk > 1) load_b(1, nx[1]);  // data tiles: block 1 in flight from the start
   __syncthreads();
-  for (int b = 0; b < nblk; ++b) {
+  // block b: its operands are staged (buffer b & 1, cb); the gather of block b + 1 is in
+  // src1 (data) and block b + 2 goes into src2
+  auto step = [&](int b, float (&src1)[2][8], float (&src2)[2][8]) {
     const int buf = b & 1;
     if (b + 1 < nblk) {
       load_a(b + 1);
-      load_b(b + 1);
+      if (GRAM) load_b(b + 1, src2);
     }
+    if (!GRAM && b + 2 < nblk) load_b(b + 2, src2);
     const __bf16* As = Ab + buf * kBufElems;
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
-      bf8 av[3];
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) av[sl] = *(const bf8*)(As + (sl * RT + 16 * m + li) * kX3Ld + 32 * g + 8 * lg);
+      for (int h = 0; h < 2; ++h) {
+        bf8 av[3];
 #pragma unroll
-      for (int si = 0; si < 3; ++si)
+        for (int sl = 0; sl < 3; ++sl)
+          av[sl] = *(const bf8*)(As + (sl * RT + 16 * m + li) * kX3Ld + 32 * h + 8 * lg);
 #pragma unroll
-        for (int ti = 0; ti < 3; ++ti)
-          acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[ti], acc[m][si + ti], 0, 0, 0);
-      // one row block's operands live at a time (the loads of the next block stay in flight)
+        for (int si = 0; si < 3; ++si)
+#pragma unroll
+          for (int ti = 0; ti < 3; ++ti)
+            acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
+      }
+      // one row block's operands live at a time (the loads of the next blocks stay in flight)
       __builtin_amdgcn_sched_barrier(0);
     }
     // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
@@ -596,25 +607,16 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
       for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
     if (b + 1 < nblk) {
       store_a(buf ^ 1);
-      take_b();
+      take_b(src1);
     }
     __syncthreads();
+  };
+  for (int b = 0; b < nblk; b += 2) {
+    step(b, nx[1], nx[0]);
+    if (b + 1 < nblk) step(b + 1, nx[0], nx[1]);
   }
-  // fixed-order sum of the two groups: group 1 through LDS, added to group 0's
-  double* red = (double*)x3_smem;
-  if (g == 1)
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[((wc * MB + m) * 4 + q) * 64 + lane] = out[m][q];
-  __syncthreads();
-  if (g == 1) return;
-  const int col = col0 + wc * 16 + li;
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[m][q] += red[((wc * MB + m) * 4 + q) * 64 + lane];
-  if (gram) {
+  const int col = col0 + wave * 16 + li;
+  if (GRAM) {
     double* H = a.Hpart + (int64_t)s * P * P;
 #pragma unroll
     for (int m = 0; m < MB; ++m)
@@ -635,10 +637,29 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   }
 }
 
+template <int MB>
+__global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
+  constexpr int RT = 16 * MB;
+  extern __shared__ __align__(16) unsigned char x3_smem[];
+  __shared__ int64_t s_roff[kMaxChunk];
+  __shared__ float s_w[kMaxChunk];
+  __shared__ int s_ea[2][RT];
+  if (*a.status != kDevOk) return;
+  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
+  const int s = lb / a.tiles, t = lb - s * a.tiles;
+  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
+  const int row0 = rt * RT;
+  if (ct < a.gram_tiles) {
+    const int col0 = ct * kX3ColTile;
+    if (col0 >= row0 + RT) return;  // strictly above the diagonal
+    x3_tile<MB, true>(a, s, row0, col0, s_roff, s_w, s_ea, x3_smem);
+  } else {
+    x3_tile<MB, false>(a, s, row0, (ct - a.gram_tiles) * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+  }
+}
+
 size_t x3_dyn_lds(int mb) {
-  const size_t stage = (size_t)2 * 3 * 16 * mb * kX3Ld * 2;  // two buffers of sketch slices
-  const size_t red = (size_t)4 * mb * 4 * 64 * 8;            // group sums
-  return stage > red ? stage : red;
+  return (size_t)2 * 3 * 16 * mb * kX3Ld * 2;  // two buffers of sketch slices
 }
 
 // Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
@@ -680,27 +701,33 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s,
 
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) {
   NormalEqPlan pl;
-  // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding;
-  // the three-slice kernel keeps two waves per SIMD up to mb = 5: one tile when P <= 80, else
-  // the mb in [3, 5] with least padding
-  const int mb_max = ne_dtype == 3 ? 5 : 8, mb_min = ne_dtype == 3 ? 3 : 4;
+  // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding.
+  // The three-slice kernel holds its accumulators without spilling up to mb = 4: one tile when
+  // P <= 64, else the mb in [3, 4] with the fewest row tiles (each gathers the fibers again),
+  // then the least padding.
+  const int mb_max = ne_dtype == 3 ? 4 : 8, mb_min = ne_dtype == 3 ? 3 : 4;
   if (P <= 16 * mb_max) {
     pl.mb = (P + 15) / 16;
   } else {
-    int best = mb_max, best_pad = 1 << 30;
+    int best = mb_max, best_pad = 1 << 30, best_tiles = 1 << 30;
     for (int mb = mb_max; mb >= mb_min; --mb) {
       const int rt = 16 * mb;
-      const int pad = (P + rt - 1) / rt * rt - P;
-      if (pad < best_pad) {
+      const int tiles = (P + rt - 1) / rt;
+      const int pad = tiles * rt - P;
+      const bool better = ne_dtype == 3 ? (tiles < best_tiles || (tiles == best_tiles && pad < best_pad))
+                                        : pad < best_pad;
+      if (better) {
         best_pad = pad;
+        best_tiles = tiles;
         best = mb;
       }
     }
     pl.mb = best;
   }
   pl.row_tiles = (P + 16 * pl.mb - 1) / (16 * pl.mb);
-  pl.gram_tiles = (P + kColTile - 1) / kColTile;
-  pl.data_tiles = (In + kColTile - 1) / kColTile;
+  const int ctile = ne_dtype == 3 ? kX3ColTile : kColTile;
+  pl.gram_tiles = (P + ctile - 1) / ctile;
+  pl.data_tiles = (In + ctile - 1) / ctile;
   const int64_t tiles = (int64_t)pl.row_tiles * (pl.gram_tiles + pl.data_tiles);
   // workgroups resident per CU (LDS-bound) and the rows one split must be a multiple of
   int per_cu, quantum;
@@ -759,10 +786,6 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
       TRALS_NE3_CASE(2)
       TRALS_NE3_CASE(3)
       TRALS_NE3_CASE(4)
-      TRALS_NE3_CASE(5)
-      TRALS_NE3_CASE(6)
-      TRALS_NE3_CASE(7)
-      TRALS_NE3_CASE(8)
 #undef TRALS_NE3_CASE
       default: return hipErrorInvalidValue;
     }
