@@ -21,10 +21,11 @@
 // core in slice-major storage.)  Products run in FP64 from the FP64 cores; the row is
 // rounded once to the sketch type.
 //
-// One workgroup handles jb samples: one thread per sample and table draws (tables staged in
-// LDS when they fit), then thread (s, b) carries row b of M_s through the chain, the slices
-// of all jb samples staged in LDS (loads batched, one round trip per kB per thread), and the
-// finished rows leave through LDS as one contiguous store.
+// A workgroup stages the tables once (in LDS when they fit) and then takes batches of jb
+// samples, gridDim.x batches apart: one thread per sample and table draws, then thread (s, b)
+// carries row b of M_s through the chain, the slices of all jb samples staged in LDS (loads
+// batched, one round trip per kB per thread), and the finished rows leave through LDS as one
+// contiguous store.
 #include <type_traits>
 
 #include "kernels.h"
@@ -34,6 +35,7 @@ namespace trals {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr size_t kDrawLdsBytes = 160 * 1024;  // LDS per compute unit
 
 // inclusive prefix sums of t[0, n) in place (kThreads threads: contiguous chunks per thread,
 // a shuffle scan of the chunk sums per wave, then the wave totals)
@@ -76,7 +78,6 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   int32_t* s_idx = (int32_t*)(s_w + jb);              // jb * K (padded to even)
   double* s_p = s_w + jb + (jb * K + 1) / 2;          // jb * K: probability of each draw
   uint64_t* tab = (uint64_t*)(s_p + jb * K);
-  const int64_t j0 = (int64_t)blockIdx.x * jb;
   const int tid = threadIdx.x;
 
   // ---- draws ----
@@ -121,6 +122,10 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     __syncthreads();
     if (a.weights) lds_scan_u64(tab, o, s_wsum);
   }
+  // batches of jb samples, gridDim.x apart (the tables above are staged once per workgroup)
+  const int64_t nbatch = (a.J + jb - 1) / jb;
+  for (int64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+  const int64_t j0 = batch * jb;
   if (tid < jb && !a.draw) {
     // given samples (same rows, no rescaling), or every index tuple in panel-row order
     const int64_t j = j0 + tid;
@@ -295,6 +300,8 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
     TA* A = (TA*)a.A + j0 * P;
     for (int64_t e = tid; e < rows * P; e += kThreads) A[e] = out[e];
   }
+  __syncthreads();  // the next batch reuses the LDS
+  }
 }
 
 template <typename TA>
@@ -318,7 +325,12 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   if (a.draw && a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
   const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2 + (size_t)jb * K) * sizeof(double);
   const size_t lds = head + (a.draw && a.tables_in_lds ? tbytes : 0);
-  const unsigned blocks = (unsigned)((a.J + jb - 1) / jb);
+  // a resident round of workgroups (LDS-bound, at most four per compute unit), each looping
+  // over its batches
+  const int64_t nbatch = (a.J + jb - 1) / jb;
+  int64_t per_cu = (int64_t)(kDrawLdsBytes / lds);
+  per_cu = per_cu < 1 ? 1 : per_cu > 4 ? 4 : per_cu;
+  const unsigned blocks = (unsigned)(nbatch < per_cu * kPlanCUs ? nbatch : per_cu * kPlanCUs);
   switch (RM) {
     case 4: k_draw<TA, 4><<<blocks, kThreads, lds, s>>>(a); break;
     case 6: k_draw<TA, 6><<<blocks, kThreads, lds, s>>>(a); break;
