@@ -50,8 +50,9 @@ typedef enum {
   TRALS_OK = 0,
   TRALS_EINVAL = -1,     /* bad argument: shape, rank, J, dtype, NaN/Inf in X, small workspace */
   TRALS_ENOMEM = -2,     /* host allocation failed */
-  TRALS_ESINGULAR = -3,  /* sampled normal equations or a core's Gram not positive definite;
-                            the core being updated is left unchanged */
+  TRALS_ESINGULAR = -3,  /* sampled normal equations not positive definite, or an all-zero
+                            core (no sampling distribution); the core being updated is left
+                            unchanged */
   TRALS_EHIP = -4,       /* a HIP runtime call failed */
   TRALS_ESTATE = -5,     /* handle is in a failed state (reset it with trals_set_cores) */
   TRALS_ERANGE = -6,     /* trals_fit_error_noalloc: the problem's scratch exceeds the library's

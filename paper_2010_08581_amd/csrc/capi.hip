@@ -768,7 +768,7 @@ const char* trals_strerror(int code) {
     case TRALS_OK: return "ok";
     case TRALS_EINVAL: return "invalid argument";
     case TRALS_ENOMEM: return "out of host memory";
-    case TRALS_ESINGULAR: return "sampled normal equations or core Gram not positive definite";
+    case TRALS_ESINGULAR: return "sampled normal equations not positive definite, or a zero core";
     case TRALS_EHIP: return "HIP runtime error";
     case TRALS_ESTATE: return "handle in a failed or incomplete state";
     case TRALS_PENDING: return "work still running";

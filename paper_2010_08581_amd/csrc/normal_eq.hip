@@ -35,6 +35,8 @@ constexpr int kColTile = 64;
 constexpr int kX3ColTile = 128;  // column tile of the three-slice kernel (eight waves of 16)
 constexpr int kKB = 32;          // sample rows per LDS stage (8 MFMA k-steps)
 constexpr int kMaxChunk = 1024;  // sample rows per split, padding included (row offsets and weights in LDS)
+// the three-slice kernel keeps one workgroup per CU either way: longer splits, fewer FP64 partials
+constexpr int kMaxChunkX3 = 4096;
 constexpr int kLdsBytes = 160 * 1024;
 
 // LDS bytes of the FP64 / FP32 kernel: KG groups x double-buffered A and B stages.
@@ -641,8 +643,8 @@ template <int MB>
 __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
   extern __shared__ __align__(16) unsigned char x3_smem[];
-  __shared__ int64_t s_roff[kMaxChunk];
-  __shared__ float s_w[kMaxChunk];
+  __shared__ int64_t s_roff[kMaxChunkX3];
+  __shared__ float s_w[kMaxChunkX3];
   __shared__ int s_ea[2][RT];
   if (*a.status != kDevOk) return;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
@@ -752,7 +754,7 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   if (S < 1) S = 1;
   if (S > J / quantum) S = J / quantum;
   if (S < 1) S = 1;
-  const int64_t maxchunk = kMaxChunk - quantum;
+  const int64_t maxchunk = (ne_dtype == 3 ? kMaxChunkX3 : kMaxChunk) - quantum;
   if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
   int64_t chunk = (J + S - 1) / S;
   // the BF16 form reads its transposed sketch in 16-byte groups, the three-slice form in
