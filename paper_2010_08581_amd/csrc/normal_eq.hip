@@ -649,7 +649,10 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   if (*a.status != kDevOk) return;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
   const int s = lb / a.tiles, t = lb - s * a.tiles;
-  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
+  // row tiles vary fastest: the row tiles of one column tile (which gather the same fibers) run
+  // side by side on one XCD and share them through its L2
+  const int row_tiles = a.tiles / a.col_tiles;
+  const int rt = t % row_tiles, ct = t / row_tiles;
   const int row0 = rt * RT;
   if (ct < a.gram_tiles) {
     const int col0 = ct * kX3ColTile;
