@@ -481,6 +481,18 @@ def main():
         out["forms"]["bf16"] = rb
         log(f"bf16 form: {rb['ms_per_sweep']:.3f} ms/sweep ({rb['speedup_vs_f32']:.2f}x), fit {rb['fit_error']:.4e}")
         torch.cuda.empty_cache()
+        # the BF16 form with its subchain products on BF16 matrix cores as well
+        hc, rc = run_workload(args, cfg, X, init, "bf16c", args.steps, args.warmup, 10, 10)
+        rc["speedup_vs_f32"] = res["ms_per_sweep"] / rc["ms_per_sweep"]
+        rc["fit_rel_diff_vs_f32"] = abs(rc["fit_error"] - res["fit_error"]) / res["fit_error"]
+        if args.oracle_updates > 0:
+            out["error_vs_oracle"]["bf16c"] = oracle_lockstep(hc, X64, cfg, args.oracle_updates)
+        hc.close()
+        del hc
+        out["forms"]["bf16_chains"] = rc
+        log(f"bf16 form, chains on matrix cores: {rc['ms_per_sweep']:.3f} ms/sweep ({rc['speedup_vs_f32']:.2f}x), "
+            f"fit {rc['fit_error']:.4e}")
+        torch.cuda.empty_cache()
     del X64
     extra = {}
     for key in [k for k in args.forms.split(",") if k and k != args.config]:

@@ -63,10 +63,15 @@ typedef enum {
 typedef enum {
   TRALS_F64 = 0,   /* IEEE double */
   TRALS_F32 = 1,   /* IEEE single */
-  TRALS_BF16 = 2   /* bfloat16 (precision TRALS_BF16 selects the BF16 form: BF16 data panels
-                      and sketch on matrix cores with FP32 accumulation, FP64 Gram/Cholesky) */
-  /* TRALS_F32: FP32 data panels and sketch, multiplied on the FP64 matrix cores (FP32 operands
-     widen exactly) with FP64 sums; TRALS_F64: FP64 throughout. */
+  TRALS_BF16 = 2,  /* bfloat16 (precision TRALS_BF16 selects the BF16 form: BF16 data panels
+                      and sketch on matrix cores with FP32 accumulation, FP64 Gram/Cholesky;
+                      the subchain rows formed in FP64 and rounded once to BF16) */
+  TRALS_BF16_CHAINS = 3  /* precision only: the BF16 form with the subchain products (Algorithm 4)
+                            also on BF16 matrix cores, FP32 accumulation, each operand a pair of
+                            BF16 values (about 16 bits) */
+  /* TRALS_F32: FP32 data panels and sketch with FP64 sums: multiplied on the FP64 matrix cores
+     (FP32 operands widen exactly) when every R[n-1]R[n] <= 128, else on the BF16 matrix cores as
+     three 8-bit slices per operand (exact products); TRALS_F64: FP64 throughout. */
 } trals_dtype;
 
 typedef enum {
@@ -86,7 +91,7 @@ typedef struct {
                               system); ignored by TRALS_EXACT */
   uint64_t seed;           /* Philox4x64-10 key word 0 */
   uint64_t stream_id;      /* Philox4x64-10 key word 1 (independent problems use distinct ids) */
-  int32_t precision;       /* TRALS_F64, TRALS_F32 or TRALS_BF16 */
+  int32_t precision;       /* TRALS_F64, TRALS_F32, TRALS_BF16 or TRALS_BF16_CHAINS */
   const void* init_cores;  /* optional device pointer to all N cores (layout above), element type
                               init_dtype; NULL draws every entry iid N(0,1) (Section 3) from the seed */
   int32_t init_dtype;      /* TRALS_F64 or TRALS_F32 */

@@ -12,9 +12,9 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import TRALS_F32, TRALS_F64, TRALS_BF16, TralsError  # noqa: F401
+from ._lib import TRALS_F32, TRALS_F64, TRALS_BF16, TRALS_BF16_CHAINS, TralsError  # noqa: F401
 
-_PREC = {"f64": TRALS_F64, "f32": TRALS_F32, "bf16": TRALS_BF16}
+_PREC = {"f64": TRALS_F64, "f32": TRALS_F32, "bf16": TRALS_BF16, "bf16c": TRALS_BF16_CHAINS}
 _METHOD = {"leverage": _lib.TRALS_LEVERAGE, "uniform": _lib.TRALS_UNIFORM, "exact": _lib.TRALS_EXACT}
 
 
@@ -52,7 +52,8 @@ class TRALS:
 
     X: CUDA tensor (float32 or float64), C order.  ranks: R[0..N-1] (core n is
     R[n-1] x I[n] x R[n]).  samples: J per core update.  precision: "f64",
-    "f32" or "bf16".  init_cores: optional list of N tensors (any device) of
+    "f32", "bf16" or "bf16c" (the BF16 form with its subchain products on BF16
+    matrix cores as well).  init_cores: optional list of N tensors (any device) of
     shapes (R[n-1], I[n], R[n]); None draws N(0,1) entries on the GPU.
     method: "leverage" (Algorithm 2), "uniform" (Algorithm 2 with uniform
     sampling) or "exact" (Algorithm 1; samples is ignored).  normalize:

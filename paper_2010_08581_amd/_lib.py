@@ -16,7 +16,7 @@ TRALS_ERANGE = -6
 TRALS_NOALLOC_SCRATCH_BYTES = 16 << 20
 TRALS_PENDING = 1
 TRALS_ASYNC_FIT = 1
-TRALS_F64, TRALS_F32, TRALS_BF16 = 0, 1, 2
+TRALS_F64, TRALS_F32, TRALS_BF16, TRALS_BF16_CHAINS = 0, 1, 2, 3
 TRALS_LEVERAGE, TRALS_UNIFORM, TRALS_EXACT = 0, 1, 2
 
 # every symbol include/trals.h declares

@@ -50,6 +50,7 @@ struct Problem {
   uint64_t seed, stream_id;
   int prec;
   int sk_dt, panel_dt, ne_dt;  // cores are FP64 in every precision
+  bool bf16_chains;            // BF16 form: subchain products on BF16 matrix cores
   size_t sk_sz, panel_sz;
   int64_t E;     // prod dims
   int Pmax;
@@ -85,7 +86,9 @@ int64_t J_of(const Problem& p, int n) { return p.method == TRALS_EXACT ? p.E / p
 int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr) {
   if (!d || !d->dims || !d->ranks) return TRALS_EINVAL;
   if (d->order < 2 || d->order > kMaxOrder) return TRALS_EINVAL;
-  if (d->precision != TRALS_F64 && d->precision != TRALS_F32 && d->precision != TRALS_BF16) return TRALS_EINVAL;
+  if (d->precision != TRALS_F64 && d->precision != TRALS_F32 && d->precision != TRALS_BF16 &&
+      d->precision != TRALS_BF16_CHAINS)
+    return TRALS_EINVAL;
   memset(p, 0, sizeof(*p));
   p->N = d->order;
   p->E = 1;
@@ -133,7 +136,8 @@ int validate(const trals_desc* d, Problem* p, const trals_source* src = nullptr)
   }
   p->seed = d->seed;
   p->stream_id = d->stream_id;
-  p->prec = d->precision;
+  p->bf16_chains = d->precision == TRALS_BF16_CHAINS;
+  p->prec = p->bf16_chains ? TRALS_BF16 : d->precision;
   // storage of the sketch (FP64 or FP32) and of the data panels (FP64, FP32 or BF16), and the
   // arithmetic of the normal-equation products; the cores (tiny) are FP64 throughout
   // sketch: FP64 rows, FP32 rows, or (BF16 form) two transposed BF16 copies of the same size as
@@ -454,6 +458,7 @@ int run_update(trals_ctx* h) {
     da.A2 = h->at<char>(h->L.A) + (size_t)P * da.ldt * 2;
   }
   da.status = h->status();
+  da.mfma_chain = p.bf16_chains ? 1 : 0;
   da.weights = p.tables_as_weights ? 1 : 0;
   da.draw = exact ? 0 : 1;
   da.enumerate = exact ? 1 : 0;

@@ -18,8 +18,10 @@
 // G^(m_0)(:, i_{m_0}, :) ... G^(m_{N-2})(:, i_{m_{N-2}}, :) (an R_n x R_{n-1} matrix M_j),
 // stored with column a*R_n + b holding w_j M_j(b, a).  (This column order is a permutation
 // of the paper's a + R_{n-1} b; it makes the solution columns the lateral slices of the new
-// core in slice-major storage.)  Products run in FP64 from the FP64 cores; the row is
-// rounded once to the sketch type.
+// core in slice-major storage.)  FP64 and FP32 sketches: products in FP64 from the FP64 cores,
+// the row rounded once to the sketch type.  BF16 sketch (the BF16 form): products on BF16
+// matrix cores with FP32 accumulation, every operand (slice or partial product) a pair of BF16
+// values, hi + lo, so that each product carries about 16 bits.
 //
 // A workgroup stages the tables once (in LDS when they fit) and then takes batches of jb
 // samples, gridDim.x batches apart: one thread per sample and table draws, then thread (s, b)
@@ -35,6 +37,14 @@ namespace trals {
 namespace {
 
 constexpr int kThreads = 256;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// BF16 form: chain products on BF16 matrix cores.  One wave per sample keeps D = M^T of its
+// chain as kT x kT tiles of 16 x 16 FP32 accumulators (kT = 1 for ranks up to 16, 2 up to 32);
+// at most kChainSPW(RM) samples per wave, so a workgroup holds 4 kChainSPW(RM) samples.
+__host__ __device__ constexpr int kChainT(int rm) { return rm <= 16 ? 1 : 2; }
+__host__ __device__ constexpr int kChainSPW(int rm) { return rm <= 16 ? 8 : 4; }
 constexpr size_t kDrawLdsBytes = 160 * 1024;  // LDS per compute unit
 
 // inclusive prefix sums of t[0, n) in place (kThreads threads: contiguous chunks per thread,
@@ -62,7 +72,7 @@ __device__ void lds_scan_u64(uint64_t* t, int n, uint64_t* wsum) {
   __syncthreads();
 }
 
-template <typename TA, int RM>
+template <typename TA, int RM, bool CHAIN>
 __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   __shared__ uint64_t s_wsum[kThreads / 64];
   extern __shared__ double lds[];
@@ -189,6 +199,21 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   double row[RM];
 #pragma unroll
   for (int c = 0; c < RM; ++c) row[c] = 0.0;
+  // BF16 form: the transposed chain D_0 = S_0^T, D_k = S_k^T D_{k-1} on BF16 matrix cores with
+  // FP32 accumulation (D_{K-1} = M^T).  A D tile's accumulator layout, row 4 (lane / 16) + r and
+  // column lane % 16, is the B operand of the next product when the 32 reduction slots of the
+  // 16 x 16 x 32 instruction are numbered so that lane group g's eight slots are rows 4g .. 4g + 3
+  // and 16 + 4g .. 16 + 4g + 3; the A operand (the slice, transposed) takes the same numbering.
+  constexpr bool kMfmaChain = CHAIN && std::is_same<TA, __bf16>::value;
+  constexpr int kT = kChainT(RM), kSPW = kMfmaChain ? kChainSPW(RM) : 1;
+  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+  f4 D[kSPW][kT][kT];
+#pragma unroll
+  for (int q = 0; q < kSPW; ++q)
+#pragma unroll
+    for (int tr = 0; tr < kT; ++tr)
+#pragma unroll
+      for (int tc = 0; tc < kT; ++tc) D[q][tr][tc] = f4{0.f, 0.f, 0.f, 0.f};
   int rin = Rn;
   for (int k = 0; k < K; ++k) {
     int m = n + 1 + k;
@@ -234,7 +259,63 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
         if (dst[q] >= 0) S[dst[q]] = v[q];
     }
     __syncthreads();
-    if (live) {
+    if constexpr (kMfmaChain) {
+#pragma unroll
+      for (int q = 0; q < kSPW; ++q) {
+        const int sq = wave + 4 * q;
+        if (sq >= jb) continue;  // wave-uniform
+        const double* Sj = S + sq * kSlice;  // rin x rout, row-major
+        if (k == 0) {
+          // D_0 = S_0^T (rout x Rn): entry (i, j) = S_0(j, i)
+#pragma unroll
+          for (int tr = 0; tr < kT; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < kT; ++tc)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = 16 * tr + 4 * l4 + r, j = 16 * tc + l16;
+                D[q][tr][tc][r] = (i < rout && j < rin) ? (float)Sj[j * rout + i] : 0.f;
+              }
+        } else {
+          // B operand: D_{k-1} (rin x Rn), slots as above; A operand: S_k^T (rout x rin).  Each
+          // operand is a BF16 pair, hi = bf16(v) and lo = bf16(v - hi), and the product is
+          // hi hi + hi lo + lo hi in FP32 (the dropped lo lo term and the pair's residue are
+          // below 2^-16 of the operands)
+          bf8 bh[kT], bl[kT];
+#pragma unroll
+          for (int tc = 0; tc < kT; ++tc)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const float v = (t < 4 || kT == 2) ? D[q][t < 4 ? 0 : kT - 1][tc][t & 3] : 0.f;
+              bh[tc][t] = (__bf16)v;
+              bl[tc][t] = (__bf16)(v - (float)bh[tc][t]);
+            }
+          f4 Dn[kT][kT];
+#pragma unroll
+          for (int tr = 0; tr < kT; ++tr) {
+            bf8 ah, al;
+            const int i = 16 * tr + l16;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int kk = t < 4 ? 4 * l4 + t : 16 + 4 * l4 + (t - 4);
+              const double v = (i < rout && kk < rin) ? Sj[kk * rout + i] : 0.0;
+              ah[t] = (__bf16)v;
+              al[t] = (__bf16)(v - (double)ah[t]);
+            }
+#pragma unroll
+            for (int tc = 0; tc < kT; ++tc) {
+              f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[tc], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[tc], acc, 0, 0, 0);
+              Dn[tr][tc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[tc], acc, 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int tr = 0; tr < kT; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < kT; ++tc) D[q][tr][tc] = Dn[tr][tc];
+        }
+      }
+    } else if (live) {
       // rin, rout are uniform (the copy's guard is a scalar branch)
       const double* Sj = S + sj * kSlice;
       if (k == 0) {
@@ -266,7 +347,40 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   const int P = Rn * Rp;
   __syncthreads();
   const int64_t rows = a.J - j0 < jb ? a.J - j0 : jb;
-  if constexpr (std::is_same<TA, __bf16>::value) {
+  if constexpr (kMfmaChain) {
+    // BF16 pair, transposed: column col = c R_n + b holds its jb samples contiguously; entry
+    // (c, b) of M^T sits in tile (c / 16, b / 16), row 4 (lane / 16) + r, column lane % 16
+    __bf16* o1 = (__bf16*)S;  // P x jb each (2 P jb bf16 <= jb * kSlice doubles)
+    __bf16* o2 = o1 + P * jb;
+#pragma unroll
+    for (int q = 0; q < kSPW; ++q) {
+      const int sq = wave + 4 * q;
+      if (sq >= jb) continue;
+      const double w = s_w[sq];
+#pragma unroll
+      for (int tr = 0; tr < kT; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < kT; ++tc)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = 16 * tr + 4 * l4 + r, bb = 16 * tc + l16;
+            if (c < Rp && bb < Rn) {
+              const int col = c * Rn + bb;
+              const double v = (double)D[q][tr][tc][r];
+              o1[col * jb + sq] = (__bf16)(w * v);
+              o2[col * jb + sq] = (__bf16)(w * (w * v));
+            }
+          }
+    }
+    __syncthreads();
+    __bf16* T1 = (__bf16*)a.A + j0;
+    __bf16* T2 = (__bf16*)a.A2 + j0;
+    for (int64_t e = tid; e < rows * P; e += kThreads) {
+      const int col = (int)(e / rows), q = (int)(e - (int64_t)col * rows);
+      T1[col * a.ldt + q] = o1[col * jb + q];
+      T2[col * a.ldt + q] = o2[col * jb + q];
+    }
+  } else if constexpr (std::is_same<TA, __bf16>::value) {
     // BF16 pair, transposed: column col = c R_n + b holds its jb samples contiguously
     __bf16* o1 = (__bf16*)S;  // P x jb each (2 P jb bf16 <= jb * kSlice doubles)
     __bf16* o2 = o1 + P * jb;
@@ -304,6 +418,18 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   }
 }
 
+// the BF16 sketch has both chain forms; the others form their rows in FP64 only
+template <typename TA, int R>
+void launch_rm(const DrawArgs& a, unsigned blocks, size_t lds, hipStream_t s) {
+  if constexpr (std::is_same<TA, __bf16>::value) {
+    if (a.mfma_chain) {
+      k_draw<TA, R, true><<<blocks, kThreads, lds, s>>>(a);
+      return;
+    }
+  }
+  k_draw<TA, R, false><<<blocks, kThreads, lds, s>>>(a);
+}
+
 template <typename TA>
 hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   int rmax = 0;
@@ -316,6 +442,8 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   int jb = kThreads / Rn;
   const int cap = (int)((64 * 1024) / ((RM * RM + 1) * sizeof(double)));
   jb = jb < cap ? jb : cap;
+  // BF16 form: the chain tiles of at most kChainSPW samples per wave live in registers
+  if (std::is_same<TA, __bf16>::value && a.mfma_chain && jb > 4 * kChainSPW(RM)) jb = 4 * kChainSPW(RM);
   if (jb < 1) return hipErrorInvalidValue;
   a.jb = jb;
   const int K = a.ring.N - 1;
@@ -331,17 +459,22 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   int64_t per_cu = (int64_t)(kDrawLdsBytes / lds);
   per_cu = per_cu < 1 ? 1 : per_cu > 4 ? 4 : per_cu;
   const unsigned blocks = (unsigned)(nbatch < per_cu * kPlanCUs ? nbatch : per_cu * kPlanCUs);
+#define TRALS_DRAW_CASE(R)                        \
+  case R:                                         \
+    launch_rm<TA, R>(a, blocks, lds, s);          \
+    break;
   switch (RM) {
-    case 4: k_draw<TA, 4><<<blocks, kThreads, lds, s>>>(a); break;
-    case 6: k_draw<TA, 6><<<blocks, kThreads, lds, s>>>(a); break;
-    case 8: k_draw<TA, 8><<<blocks, kThreads, lds, s>>>(a); break;
-    case 10: k_draw<TA, 10><<<blocks, kThreads, lds, s>>>(a); break;
-    case 12: k_draw<TA, 12><<<blocks, kThreads, lds, s>>>(a); break;
-    case 16: k_draw<TA, 16><<<blocks, kThreads, lds, s>>>(a); break;
-    case 20: k_draw<TA, 20><<<blocks, kThreads, lds, s>>>(a); break;
-    case 24: k_draw<TA, 24><<<blocks, kThreads, lds, s>>>(a); break;
-    default: k_draw<TA, 32><<<blocks, kThreads, lds, s>>>(a); break;
+    TRALS_DRAW_CASE(4)
+    TRALS_DRAW_CASE(6)
+    TRALS_DRAW_CASE(8)
+    TRALS_DRAW_CASE(10)
+    TRALS_DRAW_CASE(12)
+    TRALS_DRAW_CASE(16)
+    TRALS_DRAW_CASE(20)
+    TRALS_DRAW_CASE(24)
+    default: TRALS_DRAW_CASE(32)
   }
+#undef TRALS_DRAW_CASE
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct DrawArgs {
   int64_t ldt;                  // BF16 pair only: row length (a multiple of 64 samples)
   const int* status;
   int weights;                  // 1: cdf holds the weights Q (scanned in LDS); 0: inclusive sums C
+  int mfma_chain;               // BF16 sketch: 1 = subchain products on BF16 matrix cores
   int draw;                     // 1: draw the samples; 0: take idx as given, rows without weights
   // with draw == 0: 1 = row j is the j-th index tuple in the order of the mode-n panel's rows
   // (digit k = (j / en_stride[k]) mod I of the k-th mode after n; idx is not read) and

@@ -6,7 +6,9 @@ sampled LS solution from BF16 operands differs from the FP64 one by a few times 
 well-conditioned systems used here (measured 2-3e-3): per-update cores must agree within 1e-2
 in lockstep.  The sampling never sees BF16 (tables come from the FP32 cores in FP64), so the
 indices stay bit-exact.  The fit error at convergence must be within 1e-2 relative of the
-oracle's.
+oracle's.  Each case runs for the default BF16 form (subchain rows formed in FP64, rounded once
+to BF16) and for "bf16c", whose subchain products also run on BF16 matrix cores (each operand a
+pair of BF16 values, FP32 accumulation).
 """
 import numpy as np
 import pytest
@@ -31,26 +33,30 @@ def TR(*a, **k):
     return TRALS(*a, **k)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16c"])
 @pytest.mark.parametrize("cfg,dims,ranks,J", [
     ("c2", (120, 136, 150), (10, 10, 10), 2000),
     ("c3", (21, 22, 20, 23, 19), (5,) * 5, 4096),
 ])
-def test_bf16_lockstep(cfg, dims, ranks, J):
-    say(f"case: bf16 lockstep {cfg} {dims} J={J}")
-    X, _, init = make_config(cfg, dims=dims, dtype=np.float32)
-    t = TR(torch.tensor(X, device="cuda"), ranks, J, precision="bf16", init_cores=init)
+def test_bf16_lockstep(cfg, dims, ranks, J, prec):
+    # "bf16c": the subchain products on BF16 matrix cores too (pairs of BF16 operands, FP32
+    # accumulation: about 16 bits per product, below the BF16 rounding of the sketch)
+    say(f"case: {prec} lockstep {cfg} {dims} ranks {ranks} J={J}")
+    X, _, init = make_config(cfg, dims=dims, dtype=np.float32, ranks=ranks)
+    t = TR(torch.tensor(X, device="cuda"), ranks, J, precision=prec, init_cores=init)
     worst = lockstep(t, X.astype(np.float64), 2 * len(dims), J, core_tol=1e-2)
     say(f"bf16 worst core rel diff {worst:.3e}")
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16c"])
 @pytest.mark.parametrize("cfg,dims,ranks,J,sweeps", [
     ("c3", (21, 22, 20, 23, 19), (5,) * 5, 4096, 6),
     ("c3", (30, 26, 28, 24), (5,) * 4, 3000, 8),
 ])
-def test_bf16_converged_fit_within_1e2_of_oracle(cfg, dims, ranks, J, sweeps):
-    say(f"case: bf16 converged fit {cfg} {dims} ranks {ranks} J={J} sweeps={sweeps}")
+def test_bf16_converged_fit_within_1e2_of_oracle(cfg, dims, ranks, J, sweeps, prec):
+    say(f"case: {prec} converged fit {cfg} {dims} ranks {ranks} J={J} sweeps={sweeps}")
     X, _, init = make_config(cfg, dims=dims, dtype=np.float32, ranks=ranks)
-    t = TR(torch.tensor(X, device="cuda"), ranks, J, precision="bf16", init_cores=init)
+    t = TR(torch.tensor(X, device="cuda"), ranks, J, precision=prec, init_cores=init)
     t.sweep(sweeps)
     fb = t.fit_error()
     ref = oals.tr_als_sampled(X.astype(np.float64), init, J, sweeps, seed=0)
@@ -59,7 +65,8 @@ def test_bf16_converged_fit_within_1e2_of_oracle(cfg, dims, ranks, J, sweeps):
     assert abs(fb - fo) <= 1e-2 * fo
 
 
-def test_bf16_lockstep_rank20():
+@pytest.mark.parametrize("prec", ["bf16", "bf16c"])
+def test_bf16_lockstep_rank20(prec):
     # P = 400 (the BF16 contraction's 80-row tiles, the blocked factorisation, the 24-rank draw
     # instance writing the transposed BF16 pair) on a 4-way tensor with a C = 3 mode like the
     # video workload, built from rank-20 cores plus 1% noise; every core unfolding is wide
@@ -67,12 +74,12 @@ def test_bf16_lockstep_rank20():
     # over-parameterised free run (rank 20 on a small tensor of four blobs) drives the sampled
     # systems to cond(A)^2 2^-9 > 1, beyond what BF16 operands resolve.
     from synth import random_cores, ring_tensor, rng_for
-    say("case: bf16 lockstep 30x32x3x36 R=20 J=1500, 4 updates")
+    say(f"case: {prec} lockstep 30x32x3x36 R=20 J=1500, 4 updates")
     dims, ranks = (30, 32, 3, 36), (20,) * 4
     X = ring_tensor(random_cores(dims, ranks, rng_for(68, 1)))
     X = (X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(68, 2).standard_normal(dims)).astype(np.float32)
     init = random_cores(dims, ranks, rng_for(68, 3))
-    t = TR(torch.tensor(X, device="cuda"), ranks, 1500, precision="bf16", init_cores=init)
+    t = TR(torch.tensor(X, device="cuda"), ranks, 1500, precision=prec, init_cores=init)
     worst = lockstep(t, X.astype(np.float64), 4, 1500, core_tol=1e-2)
     say(f"bf16 worst core rel diff {worst:.3e}")
 
