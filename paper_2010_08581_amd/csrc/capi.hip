@@ -247,7 +247,8 @@ void plan(const Problem& p, Layout* L) {
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
-  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [20] int table breakdown
+  L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [20] int table
+                       // breakdown, [24] int completion counter of the solve
   L->total = off;
 }
 
@@ -287,6 +288,7 @@ struct trals_ctx {
   T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
   int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
   int* table_fail() { return reinterpret_cast<int*>(ws + L.scal + 20); }
+  int* solve_counter() { return reinterpret_cast<int*>(ws + L.scal + 24); }
   double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
   unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
 };
@@ -549,7 +551,7 @@ int run_update(trals_ctx* h) {
   // workgroup each, the table is taken from B^T beside the factorisation of H (same launches)
   // instead of after the solve.  B = H G_(2)^T carries the conditioning of H: if the Gram of
   // B^T does not factor within the table tolerance, the table is instead taken from the pivoted
-  // QR of the new core once it is solved (a launch that does nothing otherwise).  Larger
+  // QR of the new core once it is solved (by the solve's last workgroup).  Larger
   // problems take the table from the new core after the solve.
   const bool pair = p.method == TRALS_LEVERAGE && chol_single_workgroup(P);
   const bool wide = In <= P;
@@ -598,8 +600,14 @@ int run_update(trals_ctx* h) {
       ta.Q = Qn;
       ta.lev_fail = h->table_fail();
     }
+    // the table from the pivoted QR of the new core, if that Gram breaks down: by the solve's
+    // last workgroup
+    ta.Q = Qn;
+    ta.last_counter = h->solve_counter();
+    ta.core_fail = h->table_fail();
+    ta.fallback_work = h->at<double>(h->L.qr);
     PROF_BEGIN(TRALS_K_FACTOR);
-    HIPTRY(launch_chol_pair(ca, wide ? nullptr : &ck, wide ? &lw : nullptr, h->stream));
+    HIPTRY(launch_chol_pair(ca, wide ? nullptr : &ck, wide ? &lw : nullptr, h->stream, h->solve_counter()));
     PROF_END(TRALS_K_FACTOR);
   } else {
     PROF_BEGIN(TRALS_K_FACTOR);
@@ -609,11 +617,9 @@ int run_update(trals_ctx* h) {
   PROF_BEGIN(TRALS_K_SOLVE);
   HIPTRY(launch_trisolve(ta, h->stream));
   PROF_END(TRALS_K_SOLVE);
-  if (pair) {
+  if (pair && !p.tables_as_weights) {
     PROF_BEGIN(TRALS_K_TABLE);
-    HIPTRY(launch_lev_fallback(h->at<const double>(h->L.core[n]), In, P, h->at<double>(h->L.qr), Qn,
-                               h->table_fail(), h->status(), h->stream, /*keep_if_clear=*/true));
-    if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Qn, In, h->status(), h->stream));
+    HIPTRY(launch_scan_u64(Qn, In, h->status(), h->stream));
     PROF_END(TRALS_K_TABLE);
   }
   if (p.normalize) {

@@ -843,6 +843,21 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
       }
     }
   }
+  if (a.last_counter && *a.core_fail) {
+    // The table's Gram broke down (known before this launch, the same for every workgroup): the
+    // solve workgroup that finishes last (fence, then a counter: every other workgroup's rows are
+    // written and visible) takes the new core's table from its pivoted QR and resets the counter.
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(a.last_counter, 1) == a.solve_groups - 1;
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      lev_qr_table(a.core, a.In_sol, P, a.fallback_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
+      if (threadIdx.x == 0) *a.last_counter = 0;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -931,7 +946,9 @@ __global__ __launch_bounds__(64 * kW) void k_lev_wide(LevWideArgs a, CholArgs ca
 // Two independent single-workgroup jobs in one launch: workgroup 0 factors a0; workgroup 1
 // factors a1, or (wide = 1) takes the table of the wide matrix of lw as k_lev_wide does.
 template <int kW>
-__global__ __launch_bounds__(64 * kW) void k_chol_pair(CholArgs a0, CholArgs a1, LevWideArgs lw, int wide) {
+__global__ __launch_bounds__(64 * kW) void k_chol_pair(CholArgs a0, CholArgs a1, LevWideArgs lw, int wide,
+                                                        int* clear) {
+  if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
   if (blockIdx.x == 1 && wide) {
     lev_wide_body<kW>(lw, a1);
     return;
@@ -939,16 +956,14 @@ __global__ __launch_bounds__(64 * kW) void k_chol_pair(CholArgs a0, CholArgs a1,
   chol_body<false, kW>(blockIdx.x == 0 ? a0 : a1);
 }
 
-// Table from the breakdown word of a factorisation run before: the pivoted QR of G if it broke
-// down; else uniform (a wide core's row Gram factored), or nothing (keep_if_clear: the table
-// was written already).
+// Table from the breakdown word of a factorisation run before: uniform if it factored (a wide
+// core's row Gram), else the pivoted QR of G.
 __global__ __launch_bounds__(1024) void k_lev_fallback(const double* __restrict__ G, int I, int P,
                                                        double* __restrict__ qr_work, uint64_t* __restrict__ Q,
-                                                       const int* fail, int* status, int keep_if_clear) {
+                                                       const int* fail, int* status) {
   extern __shared__ unsigned char lf_smem[];
   if (*status != kDevOk) return;
   if (*fail == 0) {
-    if (keep_if_clear) return;
     const double pr = 1.0 / (double)I;
     const uint64_t q = (uint64_t)floor(pr * 4503599627370496.0);
     for (int i = threadIdx.x; i < I; i += 1024) Q[i] = q;
@@ -1046,8 +1061,8 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
 }
 
 hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
-                               int* status, hipStream_t s, bool keep_if_clear) {
-  k_lev_fallback<<<1, 1024, lev_qr_smem_bytes(P), s>>>(G, I, P, qr_work, Q, fail, status, keep_if_clear ? 1 : 0);
+                               int* status, hipStream_t s) {
+  k_lev_fallback<<<1, 1024, lev_qr_smem_bytes(P), s>>>(G, I, P, qr_work, Q, fail, status);
   return hipGetLastError();
 }
 
@@ -1078,7 +1093,8 @@ size_t wide_lds(const LevWideArgs& a, int kW) {
 
 }  // namespace
 
-hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s) {
+hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s,
+                            int* clear) {
   if ((a1 == nullptr) == (lw == nullptr) || !chol_single_workgroup(a0.P)) return hipErrorInvalidValue;
   if (a1 && !chol_single_workgroup(a1->P)) return hipErrorInvalidValue;
   if (lw && (lw->I > lw->P || lw->I < 1 || !chol_single_workgroup(lw->I) || (lw->P + 15) / 16 > kMaxBlk))
@@ -1100,9 +1116,9 @@ hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWid
     lds = b > lds ? b : lds;
   }
   if (kW == 8)
-    k_chol_pair<8><<<2, 512, lds, s>>>(a0, c1, l1, lw ? 1 : 0);
+    k_chol_pair<8><<<2, 512, lds, s>>>(a0, c1, l1, lw ? 1 : 0, clear);
   else
-    k_chol_pair<16><<<2, 1024, lds, s>>>(a0, c1, l1, lw ? 1 : 0);
+    k_chol_pair<16><<<2, 1024, lds, s>>>(a0, c1, l1, lw ? 1 : 0, clear);
   return hipGetLastError();
 }
 

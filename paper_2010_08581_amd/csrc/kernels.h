@@ -174,6 +174,12 @@ struct TriArgs {
   int* status;
   const int* lev_fail;
   double* qr_work;
+  // optional: the solve workgroup that finishes last (counted on *last_counter, which must be 0
+  // at launch and is left 0) takes the table Q of the new core (core, In_sol x P) from its
+  // pivoted QR when *core_fail is set, with fallback_work (In_sol * P doubles)
+  int* last_counter;
+  const int* core_fail;
+  double* fallback_work;
 };
 hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
 
@@ -196,15 +202,16 @@ struct LevWideArgs {
   double rel_tol;
 };
 hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s);
-// table from *fail: the pivoted QR of G (one workgroup) if it is set; if it is clear, uniform
-// (1/I), or nothing when keep_if_clear
+// table from *fail: uniform (1/I) if it is clear, else the pivoted QR of G (one workgroup)
 hipError_t launch_lev_fallback(const double* G, int I, int P, double* qr_work, uint64_t* Q, const int* fail,
-                               int* status, hipStream_t s, bool keep_if_clear = false);
+                               int* status, hipStream_t s);
 constexpr double kTableRelTol = 1e-8;  // pivot tolerance of the table factorisations
 // Two independent single-workgroup jobs in one launch (both sizes must satisfy
 // chol_single_workgroup): the factorisation a0, beside either the factorisation *a1 or the
 // whole table of the wide matrix *lw (exactly one of a1, lw non-null).
-hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s);
+// clear (optional): an int the launch sets to 0 first (the solve's completion counter below)
+hipError_t launch_chol_pair(const CholArgs& a0, const CholArgs* a1, const LevWideArgs* lw, hipStream_t s,
+                            int* clear = nullptr);
 
 // ---- generated data source and transfer-matrix inner products ----
 // Sampled fibers of X = TR(G*) + sigma Z: out[j][i] = sum_p G*_n[i][p] T[j][p] + sigma z(lin),
