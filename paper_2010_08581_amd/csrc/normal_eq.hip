@@ -237,7 +237,10 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   const int P = a.P, In = a.In;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
   const int s = lb / a.tiles, t = lb - s * a.tiles;
-  const int ct = t % a.col_tiles, rt = t / a.col_tiles;
+  // row tiles vary fastest: the row tiles of one column tile (which gather the same fibers) run
+  // side by side on one XCD and share them through its L2
+  const int row_tiles = a.tiles / a.col_tiles;
+  const int rt = t % row_tiles, ct = t / row_tiles;
   const int row0 = rt * RT;
   const bool gram = ct < a.gram_tiles;
   const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
@@ -279,8 +282,8 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
   f4 acc[MB];
 #pragma unroll
   for (int m = 0; m < MB; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
-  // one k-step = 32 samples; the operands of the next step are loaded while the matrix cores
-  // work on the current one (two register buffers, npad / 32 is even)
+  // one k-step = 32 samples; the operands of later steps are loaded while the matrix cores work
+  // on the current one
   auto load = [&](int base, bf8(&av)[MB], bf8& bv) {
     const int k0 = base + 8 * lg;  // this lane's 8 samples
 #pragma unroll
@@ -305,13 +308,20 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
 #pragma unroll
     for (int m = 0; m < MB; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m], 0, 0, 0);
   };
-  bf8 a0[MB], a1[MB], b0, b1;
-  load(0, a0, b0);
-  for (int base = 0; base < npad; base += 64) {
-    load(base + 32, a1, b1);
-    step(base, a0, b0);
-    if (base + 64 < npad) load(base + 64, a0, b0);
-    step(base + 32, a1, b1);
+  // kRing k-steps in flight: step k uses buffer k % kRing, which is then reloaded with step
+  // k + kRing (the loop runs kRing steps per iteration so that the buffers keep static indices)
+  constexpr int kRing = 4;
+  bf8 av[kRing][MB], bv[kRing];
+#pragma unroll
+  for (int d = 0; d < kRing; ++d)
+    if (32 * d < npad) load(32 * d, av[d], bv[d]);
+  for (int base = 0; base < npad; base += 32 * kRing) {
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) {
+      const int kb = base + 32 * d;
+      if (kb < npad) step(kb, av[d], bv[d]);
+      if (kb + 32 * kRing < npad) load(kb + 32 * kRing, av[d], bv[d]);
+    }
   }
   const int col = col0 + wave * 16 + li;
   if (gram) {
