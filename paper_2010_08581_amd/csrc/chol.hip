@@ -636,12 +636,13 @@ __global__ __launch_bounds__(64 * kCholWaves) void k_chol_step(CholArgs a, int I
 // Right-hand sides in row form (row i = b_i, P doubles).  Workgroups [0, solve_groups) solve
 // 16 rows each: z_i = W^T (W b_i), written as row i of the core (slice-major, FP64).
 // Workgroups [solve_groups, +lev_groups) take 16 rows each of a core unfolding G_(2) and
-// write the table weights Q_i = floor(||W g_i||^2 / P * 2^52).  Each wave takes the 16-row
-// blocks K = wave, wave + 4, ...
-template <int T>
-__global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
+// write the table weights Q_i = floor(||W g_i||^2 / P * 2^52).  Each of the NW waves takes
+// the 16-row blocks K = wave, wave + NW, ...
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_trisolve(TriArgs a) {
+  constexpr int kThr = 64 * NW;
   extern __shared__ double lds[];
-  __shared__ double s_red[4][16];
+  __shared__ double s_red[NW][16];
   if (*a.status != kDevOk) return;
   constexpr int kLdB = 17;
   const int P = a.P;
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     // pivoted QR of Blev (its dynamic LDS, 16 nblk rows of 17 doubles, holds the scratch), or,
     // without qr_work, a later launch takes it from elsewhere
     if (grp == 0 && a.qr_work)
-      lev_qr_table(a.Blev, a.In_lev, P, a.qr_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
+      lev_qr_table(a.Blev, a.In_lev, P, a.qr_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, kThr);
     return;
   }
   const double* W = lev ? a.Wlev : a.Wsol;
@@ -667,14 +668,14 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   // in registers: the Y operands are loaded while the right-hand sides are staged (right after
   // their loads) and the Z operands before Y is exchanged, so that their memory latency overlaps
   // that work.  Larger P streams them one block ahead of the matrix cores.
-  constexpr bool kHeld = T <= 2;
+  constexpr bool kHeld = T <= 2 && NW == 4;
   constexpr int kRing = 4;  // W blocks in flight per wave when streamed
   constexpr int kHB = kHeld ? 4 * T : 1;
   double wo[T][kHB][4];
   auto load_y_operands = [&]() {
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const int K = wave + 4 * t;
+      const int K = wave + NW * t;
       const double* Wr = W + (int64_t)slot(K < nblk ? K : 0, 0) * kBlk + r16 * kLd + k4;
 #pragma unroll
       for (int J = 0; J < kHB; ++J)
@@ -689,11 +690,11 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     // staging a copy per workgroup in LDS was measured slower (an extra round trip of up to 61 KB)
     const int cnt = 16 * nblk * 16;
     constexpr int kB = 8;
-    for (int base = 0; base < cnt; base += kB * 256) {
+    for (int base = 0; base < cnt; base += kB * kThr) {
       double v[kB];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + 256 * q;
+        const int e = base + (int)threadIdx.x + kThr * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         const bool ok = e < cnt && i0 + j < In && p < P;
         v[q] = ok ? Bsrc[(int64_t)(i0 + j) * P + p] : 0.0;
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
         if (base == 0) load_y_operands();
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + 256 * q;
+        const int e = base + (int)threadIdx.x + kThr * q;
         const int j = e / (nblk * 16), p = e - j * (nblk * 16);
         if (e < cnt) Bs[p * kLdB + j] = v[q];
       }
@@ -715,7 +716,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   d4 Y[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int K = wave + 4 * t;
+    const int K = wave + NW * t;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     if (kHeld) {
 #pragma unroll
@@ -760,7 +761,9 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     __syncthreads();
     if (threadIdx.x < 16 && i0 + (int)threadIdx.x < In) {
       const int j = threadIdx.x;
-      const double lv = ((s_red[0][j] + s_red[1][j]) + s_red[2][j]) + s_red[3][j];
+      double lv = s_red[0][j];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) lv += s_red[w][j];  // in wave order
       a.Q[i0 + j] = (uint64_t)floor(lv / (double)P * 4503599627370496.0);  // 2^52
     }
     return;
@@ -771,7 +774,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   if constexpr (kHeld) {
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const int K = wave + 4 * t;
+      const int K = wave + NW * t;
       int sl = slot(K < nblk ? K : 0, K < nblk ? K : 0);
 #pragma unroll
       for (int m = 0; m < kHB; ++m) {
@@ -785,7 +788,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int K = wave + 4 * t;
+    const int K = wave + NW * t;
     if (K < nblk)
 #pragma unroll
       for (int r = 0; r < 4; ++r) Bs[(16 * K + 4 * r + k4) * kLdB + r16] = Y[t][r];
@@ -795,7 +798,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
   double* out = a.core + (int64_t)(i0 + r16) * P;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int K = wave + 4 * t;
+    const int K = wave + NW * t;
     if (K < nblk) {
       d4 acc = {0.0, 0.0, 0.0, 0.0};
       if (kHeld) {
@@ -854,7 +857,7 @@ __global__ __launch_bounds__(256) void k_trisolve(TriArgs a) {
     __syncthreads();
     if (s_last) {
       __threadfence();
-      lev_qr_table(a.core, a.In_sol, P, a.fallback_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, 256);
+      lev_qr_table(a.core, a.In_sol, P, a.fallback_work, a.Q, a.status, (unsigned char*)lds, threadIdx.x, kThr);
       if (threadIdx.x == 0) *a.last_counter = 0;
     }
   }
@@ -973,11 +976,13 @@ __global__ __launch_bounds__(1024) void k_lev_fallback(const double* __restrict_
 }
 
 hipError_t trisolve_dispatch(const TriArgs& a, int nblk, unsigned grid, size_t lds, hipStream_t s) {
-  if (nblk <= 4) k_trisolve<1><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 8) k_trisolve<2><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 16) k_trisolve<4><<<grid, 256, lds, s>>>(a);
-  else if (nblk <= 32) k_trisolve<8><<<grid, 256, lds, s>>>(a);
-  else k_trisolve<16><<<grid, 256, lds, s>>>(a);
+  // four waves with every W operand in registers up to 8 blocks; beyond, sixteen waves (one or
+  // a few block rows each: the chains of dependent block products are spread over the CU)
+  if (nblk <= 4) k_trisolve<1, 4><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 8) k_trisolve<2, 4><<<grid, 256, lds, s>>>(a);
+  else if (nblk <= 16) k_trisolve<1, 16><<<grid, 1024, lds, s>>>(a);
+  else if (nblk <= 32) k_trisolve<2, 16><<<grid, 1024, lds, s>>>(a);
+  else k_trisolve<4, 16><<<grid, 1024, lds, s>>>(a);
   return hipGetLastError();
 }
 
