@@ -32,6 +32,13 @@ constexpr int kLd = 17;         // padded row stride of a 16 x 16 block (doubles
 constexpr int kBlk = 16 * kLd;  // doubles per stored block
 constexpr int kLdsBlocks = 9;   // nblk up to which a factor is staged in LDS (45 blocks, 98 KB)
 constexpr int kCholWaves = 8;  // waves per workgroup of the large-P steps
+// dynamic LDS of a large-P step: a four-block region (10 blocks), its staging blocks (4), the
+// previous step's panel rows (16), that panel's operands (10 + 16); the band workgroups of the
+// same launch use the first 16 blocks.  With the static arrays of the factorisation (about
+// 12 KB) it stays within the 160 KB of a workgroup.
+constexpr size_t kRegionLdsBytes = (size_t)(10 + 4 + 16 + 10 + 16) * kBlk * sizeof(double);
+constexpr size_t kWrowLdsBytes = (size_t)16 * kBlk * sizeof(double);
+static_assert(kRegionLdsBytes + 16384 <= 160 * 1024, "large-P step LDS");
 constexpr int kMaxBlk = 64;     // P <= 1024
 
 __device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -123,6 +130,24 @@ __device__ __forceinline__ d4 mma_frag(const double a[4], const double b[4], d4 
   return acc;
 }
 
+// acc += sign sum_{c < n} A_c B_c^T over blocks A_c = A0 + c kBlk, B_c = B0 + c kBlk (1 <= n <= 4),
+// added in the order c = 0, 1, ... like repeated mma_abt; every fragment is loaded before the
+// first product (loads past n repeat block n - 1 and are not used)
+template <typename PA, typename PB>
+__device__ __forceinline__ d4 mma_abt_run4(PA A0, PB B0, int n, d4 acc, int lane, double sign) {
+  double fa[4][4], fb[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cc = c < n ? c : n - 1;
+    load_frag(A0 + cc * kBlk, lane, fa[c]);
+    load_frag(B0 + cc * kBlk, lane, fb[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (c < n) acc = mma_frag(fa[c], fb[c], acc, sign);
+  return acc;
+}
+
 // ---------------------------------------------------------------------------------------
 // K = A^T A (P x P, row-major; the lower blocks including full diagonal blocks are written)
 // for A = rows x P, row-major, or column-major when kTrans (element (r, c) at c * rows + r).
@@ -205,26 +230,49 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
   const int nslots = nblk * (nblk + 1) / 2;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   double* Ls = lds;
+  // region path: the previous step's inverse diagonal blocks W(pb0 + c, pb0 + c2), c2 <= c, and
+  // the region's rows of its block columns A(g0 + bi, pb0 + c2), the operands of the panel below
+  // (after the staging blocks and the panel blocks)
+  const int nWp = kRegion ? a.pnb * (a.pnb + 1) / 2 : 0;
+  double* const Wp = Ls + (nslots + nblk + nblk * (kRegion ? a.pnb : 0)) * kBlk;
+  double* const Ap = Wp + nWp * kBlk;
   if (kRegion) {
-    // eight loads in flight per thread before any store
-    constexpr int kB = 8;
-    const int tot = nslots * kBlk;
-    for (int base = 0; base < tot; base += kB * kThr) {
-      double v[kB];
+    // the region's blocks and the panel operands, one wave per block (a lane takes four entries
+    // of row lane / 4, lanes 0-15 the padding column too); every load of a wave is issued before
+    // its first store
+    constexpr int kPer = (10 + 10 + 16 + kW - 1) / kW;  // blocks per wave: four-block regions
+    const int nall = nslots + nWp + nblk * a.pnb;
+    const int r = lane >> 2, c0 = 4 * (lane & 3);
+    double v[kPer][5];
 #pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + q * kThr;
-        v[q] = 0.0;
-        if (e < tot) {
-          int bi, bj;
-          slot_ij(e / kBlk, bi, bj);
-          v[q] = a.Lg[(int64_t)slot(g0 + bi, g0 + bj) * kBlk + e % kBlk];
-        }
+    for (int u = 0; u < kPer; ++u) {
+      const int q = wave + kW * u;
+      const double* src = a.Lg;
+      int bi, bj;
+      if (q < nslots) {
+        slot_ij(q, bi, bj);
+        src = a.Lg + (int64_t)slot(g0 + bi, g0 + bj) * kBlk;
+      } else if (q < nslots + nWp) {
+        slot_ij(q - nslots, bi, bj);
+        src = a.W + (int64_t)slot(a.pb0 + bi, a.pb0 + bj) * kBlk;
+      } else if (q < nall) {
+        const int t = q - nslots - nWp;
+        bi = t / a.pnb;
+        src = a.Lg + (int64_t)slot(g0 + bi, a.pb0 + t - bi * a.pnb) * kBlk;
       }
+      const bool in = q < nall;
 #pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const int e = base + (int)threadIdx.x + q * kThr;
-        if (e < tot) Ls[e] = v[q];
+      for (int i = 0; i < 4; ++i) v[u][i] = in ? src[r * kLd + c0 + i] : 0.0;
+      v[u][4] = in && lane < 16 ? src[lane * kLd + 16] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = wave + kW * u;
+      if (q < nall) {
+        double* dst = q < nslots ? Ls + q * kBlk : q < nslots + nWp ? Wp + (q - nslots) * kBlk : Ap + (q - nslots - nWp) * kBlk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[r * kLd + c0 + i] = v[u][i];
+        if (lane < 16) dst[lane * kLd + 16] = v[u][4];
       }
     }
   } else {
@@ -267,14 +315,16 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
     // then its trailing update A_ij -= sum_c L(i, pb0 + c) L(j, pb0 + c)^T
     if (a.pnb > 0) {
       double* Lsc = Ls + (nslots + nblk) * kBlk;  // nblk x pnb blocks
+      // (the previous region has four blocks, pnb = 4 divides kW: odd rounds take the columns in
+      // reverse, so that a wave's tasks c and 3 - c add up to five block products)
       for (int t = wave; t < nblk * a.pnb; t += kW) {
-        const int bi = t / a.pnb, c = t - bi * a.pnb;
+        const int bi = t / a.pnb, cr = t - bi * a.pnb;
+        const int c = ((t / kW) & 1) ? a.pnb - 1 - cr : cr;
         d4 f = {0.0, 0.0, 0.0, 0.0};
-        for (int c2 = 0; c2 <= c; ++c2)
-          f = mma_abt(a.W + (int64_t)slot(a.pb0 + c, a.pb0 + c2) * kBlk,
-                      a.Lg + (int64_t)slot(g0 + bi, a.pb0 + c2) * kBlk, f, lane, 1.0);
+        // blocks (c, c2), c2 = 0 .. c, are consecutive slots
+        f = mma_abt_run4(Wp + slot(c, 0) * kBlk, Ap + bi * a.pnb * kBlk, c + 1, f, lane, 1.0);
         // f holds W L^T's block, i.e. L(g0 + bi, pb0 + c) in operand order
-        store_frag(Lsc + t * kBlk, f, lane);
+        store_frag(Lsc + (bi * a.pnb + c) * kBlk, f, lane);
         store_frag(a.Lp + (int64_t)slot(g0 + bi, a.pb0 + c) * kBlk, f, lane);
       }
       __syncthreads();
@@ -283,8 +333,7 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
         slot_ij(sl, bi, bj);
         double* Ab = Ls + sl * kBlk;
         d4 acc = load_acc(Ab, lane);
-        for (int c = 0; c < a.pnb; ++c)
-          acc = mma_abt(Lsc + (bi * a.pnb + c) * kBlk, Lsc + (bj * a.pnb + c) * kBlk, acc, lane, -1.0);
+        acc = mma_abt_run4(Lsc + bi * a.pnb * kBlk, Lsc + bj * a.pnb * kBlk, a.pnb, acc, lane, -1.0);
         store_acc(Ab, acc, lane);
       }
     }
@@ -352,9 +401,12 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
         v[k] *= il;
         if (lme == k) myil = il;
         // keep the update right-looking: each column is final when its pivot step starts, so
-        // the compiler cannot defer the updates into a dependent chain at the pivot
+        // the compiler cannot defer the updates into a dependent chain at the pivot; the
+        // breakdown flag and the lane's scale are settled in the step too (deferred past the
+        // loop they keep sixteen pivots and scales live)
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) asm volatile("" : "+v"(v[j]));
+        asm volatile("" : "+v"(myil), "+v"(bad));
       }
       if (grp == 0) {
         if (tri == 0) {
@@ -567,7 +619,8 @@ __device__ __forceinline__ void trail_block(double* __restrict__ Lg, double* __r
 // output blocks (4I + r, 4J + c) and (4I + r + 2, 4J + c); L read from Lp
 __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double* __restrict__ W, int nblk, int I,
                                           int J) {
-  __shared__ double stage[16][16 * kLd];
+  extern __shared__ double lds[];
+  double* const stage = lds;  // 16 blocks (kWrowLdsBytes)
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   const int r0 = wave >> 2, c = wave & 3;
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
@@ -584,7 +637,7 @@ __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double*
           sacc = mma_ab(Lp + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
         }
     }
-    store_acc(stage[4 * r + c], sacc, lane);
+    store_acc(stage + (4 * r + c) * kBlk, sacc, lane);
   }
   __syncthreads();
 #pragma unroll
@@ -593,7 +646,7 @@ __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double*
     if (r < nbI) {
       d4 w = {0.0, 0.0, 0.0, 0.0};
       for (int r2 = 0; r2 <= r; ++r2)
-        w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage[4 * r2 + c], w, lane);
+        w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage + (4 * r2 + c) * kBlk, w, lane);
 #pragma unroll
       for (int q = 0; q < 4; ++q) w[q] = -w[q];
       store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
@@ -1048,20 +1101,23 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     a.nb = nblk - a.b0 < 4 ? nblk - a.b0 : 4;
     a.pb0 = K > 0 ? a.b0 - 4 : 0;  // every region but the last has four blocks
     a.pnb = K > 0 ? 4 : 0;
-    // region blocks, staging blocks, and the previous step's panel rows of the region
-    const size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb + (size_t)a.nb * a.pnb) * kBlk * sizeof(double);
+    // region blocks, staging blocks, the previous step's panel rows of the region, and that
+    // panel's operands (the step's inverse diagonal blocks, the region's rows of its columns)
+    size_t lds = ((size_t)a.nb * (a.nb + 1) / 2 + a.nb + 2 * (size_t)a.nb * a.pnb + (size_t)a.pnb * (a.pnb + 1) / 2) *
+                 kBlk * sizeof(double);  // at most kRegionLdsBytes
     if (K == 0) {
       k_chol<true, kCholWaves><<<1, 64 * kCholWaves, lds, s>>>(a);
     } else {
       // band K - 1 of W: K - 1 workgroups (none when only the factor's regions are needed)
       const int band = (K >= 2 && !a.factor_only) ? K - 1 : 0;
+      if (band > 0 && lds < kWrowLdsBytes) lds = kWrowLdsBytes;
       const int rem = nblk - a.b0;
       const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
       k_chol_step<<<(unsigned)(1 + band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
     }
   }
   if (nb64 >= 2 && !a.factor_only)
-    k_big_wrow<<<(unsigned)(nb64 - 1), 64 * kCholWaves, 0, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status, a.fail);
+    k_big_wrow<<<(unsigned)(nb64 - 1), 64 * kCholWaves, kWrowLdsBytes, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status, a.fail);
   return hipGetLastError();
 }
 
