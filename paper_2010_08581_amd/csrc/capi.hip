@@ -35,7 +35,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, partial, scal, total;
+  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, qalt, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -243,12 +243,15 @@ void plan(const Problem& p, Layout* L) {
       }
     L->qr = take(qr * 8);
   }
+  // a table formed beside the next update (taken if its factorisation breaks down)
+  L->qalt = take(p.method == TRALS_LEVERAGE ? (size_t)p.Imax * 8 : 0);
   const int64_t fit_rows = p.generated ? 0 : p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
   L->partial = take((size_t)L->partial_count * 8);
   L->scal = take(64);  // [0] double result, [8] u64 nonfinite, [16] int status, [20] int table
-                       // breakdown, [24] int completion counter of the solve
+                       // breakdown, [24] int completion counter of the solve, [28] int guard
+                       // word of the repeated draws after a table breakdown
   L->total = off;
 }
 
@@ -283,12 +286,18 @@ struct trals_ctx {
   bool async_fit = false;
   double xnorm2 = 0.0;   // ||X||_F^2, or ||TR(G*)||_F^2 for a generated source
   hipError_t last_hip = hipSuccess;
+  // a wide core's table checked beside the next update (table_ahead): the second stream, its
+  // fork and join events, and the mode whose check is outstanding (-1: none)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int ahead_mode = -1;
 
   template <typename T>
   T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
   int* status() { return reinterpret_cast<int*>(ws + L.scal + 16); }
   int* table_fail() { return reinterpret_cast<int*>(ws + L.scal + 20); }
   int* solve_counter() { return reinterpret_cast<int*>(ws + L.scal + 24); }
+  int* redo_word() { return reinterpret_cast<int*>(ws + L.scal + 28); }
   double* scal_d() { return reinterpret_cast<double*>(ws + L.scal); }
   unsigned long long* nonfinite() { return reinterpret_cast<unsigned long long*>(ws + L.scal + 8); }
 };
@@ -415,6 +424,58 @@ int compute_table(trals_ctx* h, int m) {
     return TRALS_OK;
   }
   return table_launches(h, m, h->at<const double>(h->L.core[m]), h->stream);
+}
+
+// The table of a wide core (I <= P) with more rows than one workgroup factors.  Its numerical
+// rank takes a blocked factorisation of the row Gram (several launches, a few workgroups each),
+// but the table is exactly uniform whenever that factors.  The uniform table is written at once
+// on the handle's stream, where the next update draws from it, and the factorisation (with the
+// pivoted-QR table into qalt) runs on a second stream beside the next update's draws and
+// contraction.  The next update joins it before its own factorisation: after a breakdown the
+// QR table replaces the uniform one and the draws and contraction are repeated (launches
+// guarded by a device word), so every result is that of the serial order.
+bool table_ahead_applies(const trals_ctx* h, int m) {
+  const Problem& p = h->p;
+  const int I = (int)p.dims[m];
+  return p.method == TRALS_LEVERAGE && !p.generated && I <= P_of(p, m) && !chol_single_workgroup(I);
+}
+
+int table_ahead(trals_ctx* h, int m) {
+  const Problem& p = h->p;
+  const int I = (int)p.dims[m];
+  if (!h->aux) {
+    HIPTRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    HIPTRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  }
+  uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
+  uint64_t* Qalt = h->at<uint64_t>(h->L.qalt);
+  HIPTRY(hipEventRecord(h->ev_fork, h->stream));
+  HIPTRY(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+  LevWideArgs la = wide_table_args(h, m, h->at<const double>(h->L.core[m]));
+  la.Q = Qalt;
+  HIPTRY(launch_lev_wide(la, h->aux));
+  if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Qalt, I, h->status(), h->aux));
+  HIPTRY(hipEventRecord(h->ev_join, h->aux));
+  HIPTRY(prof_mark(h, TRALS_K_TABLE, 0));
+  HIPTRY(launch_lev_uniform(I, Q, h->status(), h->stream));
+  if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Q, I, h->status(), h->stream));
+  HIPTRY(prof_mark(h, TRALS_K_TABLE, 1));
+  h->table_valid[m] = true;
+  h->ahead_mode = m;
+  return TRALS_OK;
+}
+
+// join an outstanding table check into the handle's stream; the guard word then says whether
+// the launches it guards repeat their work
+int table_settle(trals_ctx* h) {
+  if (h->ahead_mode < 0) return TRALS_OK;
+  const int m = h->ahead_mode;
+  h->ahead_mode = -1;
+  HIPTRY(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+  HIPTRY(launch_table_settle(h->table_fail(), h->status(), h->at<const uint64_t>(h->L.qalt),
+                             h->at<uint64_t>(h->L.cdf[m]), (int)h->p.dims[m], h->redo_word(), h->stream));
+  return TRALS_OK;
 }
 
 int run_update(trals_ctx* h) {
@@ -576,6 +637,26 @@ int run_update(trals_ctx* h) {
   HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, h->status(),
                              h->stream));
   PROF_END(TRALS_K_REDUCE);
+  if (h->ahead_mode >= 0) {
+    // the previous core's table was checked beside these draws (table_ahead): join it, then
+    // repeat the draws, the contraction and its reduction, launches that skip unless that
+    // check broke down and replaced the uniform table they drew from
+    const int rc = table_settle(h);
+    if (rc) return rc;
+    int* g = h->redo_word();
+    DrawArgs dr = da;
+    dr.status = g;
+    HIPTRY(launch_draw(dr, p.sk_dt, h->stream));
+    if (p.ne_dt == 3) {
+      const int64_t ld3 = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+      HIPTRY(launch_sketch_split(h->at<const float>(h->L.A), Jn, P, h->at<void>(h->L.S3), ld3,
+                                 h->at<int>(h->L.E3), g, h->stream));
+    }
+    NormalEqArgs nr = na;
+    nr.status = g;
+    HIPTRY(launch_normal_eq(nr, pl, p.ne_dt, h->stream, nullptr, nullptr));
+    HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, g, h->stream));
+  }
   if (pair) {
     CholArgs ck;
     memset(&ck, 0, sizeof(ck));
@@ -632,6 +713,9 @@ int run_update(trals_ctx* h) {
   }
   if (pair) {
     h->table_valid[n] = true;
+  } else if (table_ahead_applies(h, n)) {
+    const int rc = table_ahead(h, n);  // checked beside the next update
+    if (rc) return rc;
   } else {
     const int rc = compute_table(h, n);  // from the new core; uniform tables; none when exact
     if (rc) return rc;
@@ -924,6 +1008,11 @@ static int run_updates(trals_ctx* h, int64_t count) {
       return rc;
     }
   }
+  const int rc = table_settle(h);
+  if (rc) {
+    h->failed = true;
+    return rc;
+  }
   return sync_status(h);
 }
 
@@ -938,6 +1027,13 @@ int trals_sweep_async(trals_handle h, int32_t n_sweeps, int32_t flags) {
   const int64_t count = (int64_t)n_sweeps * h->p.N;
   for (int64_t u = 0; u < count; ++u) {
     const int rc = run_update(h);
+    if (rc) {
+      h->failed = true;
+      return rc;
+    }
+  }
+  {
+    const int rc = table_settle(h);
     if (rc) {
       h->failed = true;
       return rc;
@@ -1035,6 +1131,12 @@ int trals_fit_error(trals_handle h, double* rel_err) {
 int trals_destroy(trals_handle h) {
   if (!h) return TRALS_OK;
   if (h->pending) (void)hipStreamSynchronize(h->stream);  // work may still use the workspace
+  if (h->aux) {
+    (void)hipStreamSynchronize(h->aux);  // a table check left behind by a failed update
+    (void)hipStreamDestroy(h->aux);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->done) (void)hipEventDestroy(h->done);
   pinned_put(h->host_res);
   for (auto& v : h->prof.ev)

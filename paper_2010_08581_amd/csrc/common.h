@@ -10,7 +10,8 @@ constexpr int kMaxOrder = 16;   // N
 constexpr int kMaxRank = 32;    // R_n
 
 // Status word kept in device memory; kernels raise it, the host reads it at sync points.
-enum DevStatus : int { kDevOk = 0, kDevSingular = 1 };
+// kDevIdle: the word of a guarded launch with nothing to do (its kernels skip like after an error)
+enum DevStatus : int { kDevOk = 0, kDevSingular = 1, kDevIdle = 2 };
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): multipliers and Weyl key increments.
 constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;

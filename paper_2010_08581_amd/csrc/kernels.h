@@ -255,6 +255,10 @@ hipError_t launch_gauge(double* core, int64_t In, int Rp, int R, double* next, i
                         double* S, double* work, int* status, hipStream_t s);
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s);
 hipError_t launch_scan_u64(uint64_t* Q, int In, const int* status, hipStream_t s);
+// One workgroup: Q <- Qalt (In entries) if *status is clear and *fail is set, and *redo = kDevOk
+// in that case, kDevIdle otherwise
+hipError_t launch_table_settle(const int* fail, const int* status, const uint64_t* Qalt, uint64_t* Q, int In, int* redo,
+                               hipStream_t s);
 
 // ---- fit error ----
 constexpr int kFitRows = 8;       // rows of X (C order, last mode contiguous) per fit block

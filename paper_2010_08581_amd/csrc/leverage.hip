@@ -47,7 +47,24 @@ __global__ __launch_bounds__(1024) void k_scan_u64(uint64_t* Q, int In, const in
   }
 }
 
+// After a table formed beside the next update: if its factorisation broke down (*fail set),
+// the table Qalt replaces Q, and *redo = kDevOk lets the launches guarded by it repeat the next
+// update's draws and contraction; otherwise *redo = kDevIdle and they skip.
+__global__ __launch_bounds__(1024) void k_table_settle(const int* fail, const int* status, const uint64_t* Qalt,
+                                                       uint64_t* Q, int In, int* redo) {
+  const bool take = *status == kDevOk && *fail != 0;
+  if (take)
+    for (int i = threadIdx.x; i < In; i += 1024) Q[i] = Qalt[i];
+  if (threadIdx.x == 0) *redo = take ? kDevOk : kDevIdle;
+}
+
 }  // namespace
+
+hipError_t launch_table_settle(const int* fail, const int* status, const uint64_t* Qalt, uint64_t* Q, int In, int* redo,
+                               hipStream_t s) {
+  k_table_settle<<<1, 1024, 0, s>>>(fail, status, Qalt, Q, In, redo);
+  return hipGetLastError();
+}
 
 hipError_t launch_lev_uniform(int In, uint64_t* Q, const int* status, hipStream_t s) {
   k_lev_uniform<<<(In + 255) / 256, 256, 0, s>>>(In, Q, status);

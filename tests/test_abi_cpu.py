@@ -93,10 +93,12 @@ def test_method_validation_and_exact_sizing(lib):
     rc, _ = ws((2, 2, 50), (3, 3, 3), 0, method=_lib.TRALS_EXACT)
     assert rc == _lib.TRALS_EINVAL
     # uniform sizes like leverage sampling without the pivoted-QR work copy of the largest core
-    # unfolding (max_n I_n R[n-1] R[n] doubles, 256-byte aligned)
+    # unfolding (max_n I_n R[n-1] R[n] doubles) and the second table of the largest mode (a table
+    # checked beside the next update: max_n I_n weights), each 256-byte aligned
     rc, b_uni = ws((40, 30, 20), (2, 3, 2), 100, _lib.TRALS_F64, method=_lib.TRALS_UNIFORM)
     qr = max(40 * 2 * 2, 30 * 2 * 3, 20 * 3 * 2) * 8
-    assert rc == 0 and b_lev - b_uni == (qr + 255) // 256 * 256
+    qalt = 40 * 8
+    assert rc == 0 and b_lev - b_uni == (qr + 255) // 256 * 256 + (qalt + 255) // 256 * 256
 
 
 def test_exact_rejects_generated_source(lib):

@@ -113,3 +113,35 @@ def test_degenerate_core_tables_match_oracle(name, dims, ranks, mutate, start, J
     t.set_cores(cores)  # every table but that of the next update's core, from these cores
     worst = lockstep(t, X, 2, J, start=start, core_tol=1e-9)
     say(f"{name}: worst slice {worst:.3e}")
+
+
+@pytest.mark.parametrize("dup", [False, True], ids=["full rank", "two equal slices"])
+def test_wide_table_checked_beside_next_update(dup):
+    # A 200 x 256 wide core (past the single-workgroup factorisation): its table is written
+    # uniform at once and its rank checked beside the next update's draws, within one call.
+    # With two equal slices of X along mode 0, the new core 0 has two equal rows (rank 199): the
+    # check breaks down, the pivoted-QR table replaces the uniform one, and update 1 must repeat
+    # its draws and contraction from it.  Update 1 is compared with the oracle's update from the
+    # GPU's new core 0 (indices bit for bit).
+    from oracle import als as oals
+    from paper_2010_08581_amd import TRALS
+    from tests.gpu_helpers import assert_core_close, to_np
+    dims, ranks, J = (200, 20, 20), (16, 16, 16), 600
+    say(f"case: table beside the next update, dims {dims} ranks {ranks} J={J}, equal slices {dup}")
+    X = rng_for(91, 0).standard_normal(dims)
+    if dup:
+        X[17] = X[3]
+    t = TRALS(torch.tensor(X, device="cuda"), ranks, J, precision="f64",
+              init_cores=random_cores(dims, ranks, rng_for(91, 4)))
+    before = to_np(t.get_cores())
+    t.step(2)
+    after = to_np(t.get_cores())
+    c0, _, _ = oals.lockstep_update(X, before, 0, J, 0, 0, 0)
+    assert_core_close(after[0], c0, 1e-9, "update 0 (core 0)")
+    c1, idx_o, w_o = oals.lockstep_update(X, [after[0]] + before[1:], 1, J, 0, 0, 1)
+    idx_g, w_g = t.last_samples()
+    assert np.array_equal(idx_g, idx_o), f"update 1: sampled indices differ ({int(np.sum(idx_g != idx_o))} entries)"
+    np.testing.assert_allclose(w_g, w_o, rtol=1e-6)
+    r = assert_core_close(after[1], c1, 1e-9, "update 1 (core 1)")
+    say(f"update 1 core 1: worst slice {r:.3e}")
+    t.close()
