@@ -35,7 +35,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, qalt, partial, scal, total;
+  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, qalt, ysol, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -245,6 +245,8 @@ void plan(const Problem& p, Layout* L) {
   }
   // a table formed beside the next update (taken if its factorisation breaks down)
   L->qalt = take(p.method == TRALS_LEVERAGE ? (size_t)p.Imax * 8 : 0);
+  // the first half of a solve spread over several workgroups per row group (P > 128)
+  L->ysol = take(p.Pmax > 128 ? solve_split_doubles((int)p.Imax, p.Pmax) * 8 : 0);
   const int64_t fit_rows = p.generated ? 0 : p.E / p.dims[p.N - 1];
   const int64_t fit_blocks = (fit_rows + kFitRows - 1) / kFitRows;
   L->partial_count = fit_blocks > kScanBlocks ? fit_blocks : kScanBlocks;
@@ -632,6 +634,7 @@ int run_update(trals_ctx* h) {
   ta.Bsol = Bred;
   ta.core = h->at<double>(h->L.core[n]);
   ta.status = h->status();
+  if (P > 128) ta.split_work = h->at<double>(h->L.ysol);
   uint64_t* Qn = h->at<uint64_t>(h->L.cdf[n]);
   PROF_BEGIN(TRALS_K_REDUCE);
   HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, h->status(),

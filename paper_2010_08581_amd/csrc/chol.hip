@@ -40,6 +40,7 @@ constexpr size_t kRegionLdsBytes = (size_t)(10 + 4 + 16 + 10 + 16) * kBlk * size
 constexpr size_t kWrowLdsBytes = (size_t)16 * kBlk * sizeof(double);
 static_assert(kRegionLdsBytes + 16384 <= 160 * 1024, "large-P step LDS");
 constexpr int kMaxBlk = 64;     // P <= 1024
+constexpr int kMaxSolveParts = 8;  // workgroups per 16-row group and half of a split solve
 
 __device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -917,6 +918,156 @@ __global__ __launch_bounds__(64 * NW) void k_trisolve(TriArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// The solve for P > 128 in two launches.  On one compute unit a 16-row group's 2 nblk (nblk +
+// 1) / 2 block products take longer than the FP64 matrix cores allow for the whole solve, and
+// a few groups leave most units idle; here each group is spread over sp.n workgroups per half:
+//   kZ = false: Y_K = sum_{J <= K} W_KJ B_J for the block rows K of the part, into Ys;
+//   kZ = true:  Z_K = sum_{J >= K} W_JK^T Y_J for the block rows K of the part (Y_J from Ys),
+//               written as rows of the core.
+// Parts are contiguous ranges of K, [sp.lo[p], sp.lo[p + 1]), of about equal product counts;
+// wave w takes K = lo + w, lo + w + 16, ...  Every block product and its order are those of
+// k_trisolve.  Ys: group g's block K at (g nblk + K) 256 doubles, entry (i, j) = Y_K(i, j)
+// (row i of the block row, right-hand side j).
+struct SolveParts {
+  int n;
+  int lo[kMaxSolveParts + 1];
+};
+
+template <bool kZ>
+__global__ __launch_bounds__(1024) void k_solve_half(TriArgs a, SolveParts sp) {
+  constexpr int NW = 16, kThr = 64 * NW, kLdB = 17, kRing = 4;
+  extern __shared__ double lds[];
+  if (*a.status != kDevOk) return;
+  const int P = a.P, nblk = (P + 15) / 16, In = a.In_sol;
+  const int g = (int)blockIdx.x / sp.n, part = (int)blockIdx.x - g * sp.n;
+  const int klo = sp.lo[part], khi = sp.lo[part + 1];
+  const int i0 = 16 * g;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, k4 = lane >> 4;
+  double* Bs = lds;  // 16 nblk rows (p) x 16 columns (right-hand sides), stride kLdB
+  double* Ys = a.split_work + (int64_t)g * nblk * 256;
+  const double* W = a.Wsol;
+  // operands: B_J for J < khi (rows of B transposed), or Y_J for J >= klo (from Ys); all loads
+  // of a round issued before any store
+  {
+    const int j0 = kZ ? klo : 0, j1 = kZ ? nblk : khi;
+    const int cnt = 256 * (j1 - j0);
+    constexpr int kB = 8;
+    for (int base = 0; base < cnt; base += kB * kThr) {
+      double v[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + kThr * q;
+        double x = 0.0;
+        if (e < cnt) {
+          if (kZ) {
+            x = Ys[(int64_t)j0 * 256 + e];  // entry (i, j) of block j0 + e / 256
+          } else {
+            const int j = e / (16 * (j1 - j0)), p = e - j * (16 * (j1 - j0));  // row j of the group, column p
+            if (i0 + j < In && p < P) x = a.Bsol[(int64_t)(i0 + j) * P + p];
+          }
+        }
+        v[q] = x;
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int e = base + (int)threadIdx.x + kThr * q;
+        if (e < cnt) {
+          if (kZ) {
+            const int blk = j0 + e / 256, ij = e & 255;
+            Bs[(16 * blk + (ij >> 4)) * kLdB + (ij & 15)] = v[q];
+          } else {
+            const int j = e / (16 * (j1 - j0)), p = e - j * (16 * (j1 - j0));
+            Bs[p * kLdB + j] = v[q];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int K = klo + wave; K < khi; K += NW) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    double wb[kRing][4];
+    if (!kZ) {
+      // blocks (K, 0 .. K) through a ring of kRing blocks (as in k_trisolve)
+      const double* Wr = W + (int64_t)slot(K, 0) * kBlk + r16 * kLd + k4;
+#pragma unroll
+      for (int d = 0; d < kRing; ++d)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wr[(d <= K ? d : K) * kBlk + 4 * ks];
+      for (int J0 = 0; J0 <= K; J0 += kRing) {
+#pragma unroll
+        for (int d = 0; d < kRing; ++d) {
+          const int J = J0 + d;
+          if (J <= K)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = mfma(wb[d][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+          const int Jn = J + kRing <= K ? J + kRing : K;
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wr[Jn * kBlk + 4 * ks];
+        }
+      }
+      // D(i, j) in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ys[(int64_t)K * 256 + (4 * r + k4) * 16 + r16] = acc[r];
+    } else {
+      // blocks (K .. nblk-1, K); block (J, K) at slot(J, K), slot(J + 1, K) = slot(J, K) + J + 1
+      const double* Wc = W + k4 * kLd + r16;
+      int sl = slot(K, K), Jl = K;
+#pragma unroll
+      for (int d = 0; d < kRing; ++d) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
+        if (Jl + 1 < nblk) {
+          sl += Jl + 1;
+          ++Jl;
+        }
+      }
+      for (int J0 = K; J0 < nblk; J0 += kRing) {
+#pragma unroll
+        for (int d = 0; d < kRing; ++d) {
+          const int J = J0 + d;
+          if (J < nblk)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = mfma(wb[d][ks], Bs[(16 * J + 4 * ks + k4) * kLdB + r16], acc);
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) wb[d][ks] = Wc[(int64_t)sl * kBlk + 4 * ks * kLd];
+          if (Jl + 1 < nblk) {
+            sl += Jl + 1;
+            ++Jl;
+          }
+        }
+      }
+      const bool live = i0 + r16 < In;
+      double* out = a.core + (int64_t)(i0 + r16) * P;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = 16 * K + 4 * r + k4;
+        if (live && p < P) out[p] = acc[r];
+      }
+    }
+  }
+}
+
+// contiguous ranges of block rows with about equal product counts: block row K costs K + 1
+// products in the first half, nblk - K in the second
+SolveParts solve_parts(int nblk, int n, bool second) {
+  SolveParts sp;
+  sp.n = n;
+  const int64_t total = (int64_t)nblk * (nblk + 1) / 2;
+  int K = 0;
+  int64_t acc = 0;
+  sp.lo[0] = 0;
+  for (int p = 1; p < n; ++p) {
+    const int64_t target = total * p / n;
+    while (K < nblk && acc + (second ? nblk - K : K + 1) <= target) acc += second ? nblk - K : K + 1, ++K;
+    sp.lo[p] = K;
+  }
+  sp.lo[n] = nblk;
+  return sp;
+}
+
+// ---------------------------------------------------------------------------------------
 // Table of a wide core (I <= P) in one workgroup: the row Gram K = G G^T (lower blocks, into
 // a.K), its factorisation in LDS with the table tolerance, then the uniform table if it
 // factored, else the pivoted-QR table.
@@ -1204,10 +1355,26 @@ hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
   return launch_lev_fallback(a.G, a.I, a.P, a.qr_work, a.Q, a.fail, a.status, s);
 }
 
+size_t solve_split_doubles(int In, int P) { return (size_t)((In + 15) / 16) * ((P + 15) / 16) * 256; }
+
 hipError_t launch_trisolve(const TriArgs& args, hipStream_t s) {
   TriArgs a = args;
   const int nblk = (a.P + 15) / 16;
   if (nblk > kMaxBlk) return hipErrorInvalidValue;
+  if (a.split_work && a.Wsol && !a.Wlev && !a.last_counter && nblk > 8 && a.In_sol > 0) {
+    // about 1.5 workgroups per compute unit in each half (measured best over 1, 1.5, 2 and 4 at
+    // P = 400, 2000 rows), at most kMaxSolveParts per group
+    const int groups = (a.In_sol + 15) / 16;
+    int n = (3 * kPlanCUs / 2 + groups - 1) / groups;
+    n = n < 1 ? 1 : n > kMaxSolveParts ? kMaxSolveParts : n > nblk ? nblk : n;
+    const unsigned grid = (unsigned)(groups * n);
+    const SolveParts p1 = solve_parts(nblk, n, false), p2 = solve_parts(nblk, n, true);
+    // staged blocks are indexed by their block row: room for all nblk (at most 139 KB)
+    const size_t lds = (size_t)nblk * 16 * 17 * sizeof(double);
+    k_solve_half<false><<<grid, 1024, lds, s>>>(a, p1);
+    k_solve_half<true><<<grid, 1024, lds, s>>>(a, p2);
+    return hipGetLastError();
+  }
   a.solve_groups = a.Wsol ? (a.In_sol + 15) / 16 : 0;
   a.lev_groups = a.Wlev ? (a.In_lev + 15) / 16 : 0;
   const unsigned grid = (unsigned)(a.solve_groups + a.lev_groups);

@@ -180,8 +180,13 @@ struct TriArgs {
   int* last_counter;
   const int* core_fail;
   double* fallback_work;
+  // optional, a solve without leverage rows for P > 128: work memory of
+  // solve_split_doubles(In_sol, P) doubles; the solve then runs as two launches, each spread
+  // over several workgroups per 16-row group (the same block products in the same order)
+  double* split_work;
 };
 hipError_t launch_trisolve(const TriArgs& a, hipStream_t s);
+size_t solve_split_doubles(int In, int P);
 
 // Sampling table of a wide core (I <= P: G_(2) is I x P, slice-major).  The row Gram G G^T is
 // factored with tolerance rel_tol; if it factors, G_(2) has full row rank and p_i = 1/I
