@@ -346,23 +346,25 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// FP32 path on BF16 matrix cores with exact products (ne_dtype 3).
+// FP32 path on BF16 matrix cores with FP32-accurate products (ne_dtype 3).
 //
 // Every operand value v of a 64-sample block is written as v = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2)
 // + r with integers |s0| <= 256, |s1|, |s2| <= 128 (exact in BF16) and |r| <= 2^(e-25), e the
 // block exponent of its column (max |v| < 2^e): a relative truncation of at most 2^-24 of the
 // column's block maximum, the size of FP32 rounding.  A product of two such values is the sum
-// of nine slice products s_s t_t 2^(-8(s+t)); grouped by level l = s + t, each level's sum over
-// the 64 samples is an integer below 2^24, so the FP32 accumulation of the BF16 matrix cores is
-// exact.  After each block the five level sums are combined and scaled by 2^(e_row + e_col - 16)
-// in FP64 and added to FP64 accumulators.
+// of nine slice products s_s t_t 2^(-8(s+t)); the six of levels l = s + t <= 2 are formed
+// (kX3Levels), and the three dropped ones are below 2^-24 of the product of the block maxima.
+// Each level's sum over the 64 samples is an integer below 2^24, so the FP32 accumulation of
+// the BF16 matrix cores is exact.  After each block the level sums are combined and scaled by
+// 2^(e_row + e_col - 16) in FP64 and added to FP64 accumulators.
 //
 // The sketch side has one representation (launch_sketch_split), used both as the row operand
 // and, in the Gram tiles, as the column operand: H is exactly R(A)^T R(A).  The data side is the
 // weighted fiber w_j X(j, i), split in the kernel with the block maximum of its column (the 64
 // samples of a column sit in four lanes: a max over the lane's 16 values and two exchanges).  So
-// B = R(A)^T R(diag(w) X): both products are those of one slightly perturbed problem, whose
-// solution moves by cond(A) times the perturbation, as with FP32 storage alone.
+// B = R(A)^T R(diag(w) X) up to the dropped levels: both products are those of one slightly
+// perturbed problem, whose solution moves by cond(A) times the perturbation, as with FP32
+// storage alone.
 //   v_mfma_f32_16x16x32_bf16 layouts: A(i, k) at lane i + 16 (k / 8), element k % 8;
 //   B(k, j) at lane j + 16 (k / 8), element k % 8; D(i, j) at lane j + 16 (i / 4), register i % 4.
 
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
 
 // Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
 // MB row blocks and both 32-sample halves (matrix-core k-steps) of every 64-sample block, so
-// that its five level sums cover 64 samples between FP64 flushes (each stays below 2^22 in
+// that its level sums cover 64 samples between FP64 flushes (each stays below 2^22 in
 // magnitude, exact in FP32).  The sketch rows of the tile (three slices, both halves) are staged
 // in LDS by the whole workgroup, double-buffered with one barrier per block; each wave loads the
 // column operand of its own columns directly into the matrix-core registers, one block ahead:
@@ -438,6 +440,12 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
 // li + 32, li + 48, sixteen each).
 constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
                            // of 16 rows fall on distinct banks)
+// Slice products kept: level l = si + ti of s_si t_ti weighs 2^(-8 l) against the leading
+// product, and levels 0 .. kX3Levels - 1 are multiplied (six products of nine).  The dropped
+// levels 3 and 4 (s1 t2 + s2 t1 + s2 t2, integers below 2^15 + 2^14) leave a product error
+// below 2^-24 of |a| |t| at the block maxima per sample: the accuracy of an FP32 product, the
+// FP32 inputs' own rounding.
+constexpr int kX3Levels = 3;
 
 // One tile of k_normal_eq_x3; GRAM selects the column operand (the two paths' registers are
 // allocated separately).  Data tiles gather their fibers two blocks ahead (the block loop is
@@ -558,12 +566,12 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
         }
     }
   };
-  f4 acc[MB][5];
+  f4 acc[MB][kX3Levels];
   double out[MB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
 #pragma unroll
-    for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
   }
@@ -596,7 +604,8 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
         for (int si = 0; si < 3; ++si)
 #pragma unroll
           for (int ti = 0; ti < 3; ++ti)
-            acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
+            if (si + ti < kX3Levels)
+              acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
       }
       // one row block's operands live at a time (the loads of the next blocks stay in flight)
       __builtin_amdgcn_sched_barrier(0);
@@ -606,17 +615,15 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        double v = (double)acc[m][4][q];
-        v = fma(v, 0.00390625, (double)acc[m][3][q]);
-        v = fma(v, 0.00390625, (double)acc[m][2][q]);
-        v = fma(v, 0.00390625, (double)acc[m][1][q]);
-        v = fma(v, 0.00390625, (double)acc[m][0][q]);
+        double v = (double)acc[m][kX3Levels - 1][q];
+#pragma unroll
+        for (int l = kX3Levels - 2; l >= 0; --l) v = fma(v, 0.00390625, (double)acc[m][l][q]);
         out[m][q] += ldexp(v, s_ea[buf][16 * m + 4 * lg + q] + fcol - 16);
       }
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
-      for (int l = 0; l < 5; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
     if (b + 1 < nblk) {
       store_a(buf ^ 1);
       take_b(src1);
