@@ -346,14 +346,14 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// FP32 path on BF16 matrix cores with FP32-accurate products (ne_dtype 3).
+// FP32 path on BF16 matrix cores with products exact to 2^-34 of the block maxima (ne_dtype 3).
 //
 // Every operand value v of a 64-sample block is written as v = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2)
 // + r with integers |s0| <= 256, |s1|, |s2| <= 128 (exact in BF16) and |r| <= 2^(e-25), e the
 // block exponent of its column (max |v| < 2^e): a relative truncation of at most 2^-24 of the
 // column's block maximum, the size of FP32 rounding.  A product of two such values is the sum
-// of nine slice products s_s t_t 2^(-8(s+t)); the six of levels l = s + t <= 2 are formed
-// (kX3Levels), and the three dropped ones are below 2^-24 of the product of the block maxima.
+// of nine slice products s_s t_t 2^(-8(s+t)); the eight of levels l = s + t <= 3 are formed
+// (kX3Levels), and the dropped s2 t2 is below 2^-34 of the product of the block maxima.
 // Each level's sum over the 64 samples is an integer below 2^24, so the FP32 accumulation of
 // the BF16 matrix cores is exact.  After each block the level sums are combined and scaled by
 // 2^(e_row + e_col - 16) in FP64 and added to FP64 accumulators.
@@ -441,11 +441,12 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
 constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
                            // of 16 rows fall on distinct banks)
 // Slice products kept: level l = si + ti of s_si t_ti weighs 2^(-8 l) against the leading
-// product, and levels 0 .. kX3Levels - 1 are multiplied (six products of nine).  The dropped
-// levels 3 and 4 (s1 t2 + s2 t1 + s2 t2, integers below 2^15 + 2^14) leave a product error
-// below 2^-24 of |a| |t| at the block maxima per sample: the accuracy of an FP32 product, the
-// FP32 inputs' own rounding.
-constexpr int kX3Levels = 3;
+// product, and levels 0 .. kX3Levels - 1 are multiplied (eight products of nine).  The dropped
+// level 4 (s2 t2, an integer below 2^14) is below 2^-34 of the product of the two block maxima,
+// far under the FP32 inputs' own rounding (2^-24).  Dropping level 3 as well (six products) was
+// measured 2% faster but a perturbation of that size (2^-25) in H and B separately is amplified
+// by cond(A)^2 in the solution (video cores 4.8e-7 -> 9.8e-6 against the oracle).
+constexpr int kX3Levels = 4;
 
 // One tile of k_normal_eq_x3; GRAM selects the column operand (the two paths' registers are
 // allocated separately).  Data tiles gather their fibers two blocks ahead (the block loop is
