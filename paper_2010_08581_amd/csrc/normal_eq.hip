@@ -389,44 +389,44 @@ __device__ __forceinline__ Slices3 split3(float v, int e) {
   return Slices3{{(__bf16)a0, (__bf16)a1, (__bf16)a2}};
 }
 
-// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup.  Thread
-// (column c, quarter q) takes the column's maximum and splits 16 samples; the slices pass
-// through LDS so that eight lanes store one column's 64 samples (128 contiguous bytes).
+// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup, no LDS.
+// Wave w takes columns 16 w .. 16 w + 15 of the tile; lane (li, q) = (lane % 16, lane / 16)
+// holds samples 16 q .. 16 q + 15 of column li, so a column's 64 samples sit in four lanes of one
+// wave: its block maximum takes two lane exchanges, and each lane stores its 16 samples of each
+// slice as 32 contiguous bytes (the four lanes of a column fill its 128-byte run).
 __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ A, int64_t J, int P,
                                                       __bf16* __restrict__ S3, int64_t ld, int* __restrict__ E,
                                                       const int* status) {
-  __shared__ float tile[kSplitBlock][kSplitBlock + 1];
-  __shared__ float cmax[4][kSplitBlock];
-  __shared__ __align__(16) __bf16 out[3][kSplitBlock][kSplitBlock + 8];
   if (*status != kDevOk) return;
-  const int p0 = blockIdx.x * 64;
-  const int64_t j0 = (int64_t)blockIdx.y * kSplitBlock;
-  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;  // column, quarter of the samples
-  const int p = p0 + c;
-  for (int r = q; r < kSplitBlock; r += 4) {
-    const int64_t j = j0 + r;
-    tile[r][c] = (j < J && p < P) ? A[j * P + p] : 0.f;
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int p = blockIdx.x * 64 + 16 * wave + li;
+  const int64_t j0 = (int64_t)blockIdx.y * kSplitBlock + 16 * q;
+  const bool pin = p < P;
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = (pin && j0 + r < J) ? A[(j0 + r) * P + p] : 0.f;
   float mx = 0.f;
-  for (int r = 16 * q; r < 16 * q + 16; ++r) mx = fmaxf(mx, fabsf(tile[r][c]));
-  cmax[q][c] = mx;
-  __syncthreads();
-  const int e = block_exponent((double)fmaxf(fmaxf(cmax[0][c], cmax[1][c]), fmaxf(cmax[2][c], cmax[3][c])));
-  if (q == 0 && p < P) E[(int64_t)blockIdx.y * P + p] = e;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(v[r]));
+  mx = fmaxf(mx, __shfl_xor(mx, 16));
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  const int e = block_exponent((double)mx);
+  if (q == 0 && pin) E[(int64_t)blockIdx.y * P + p] = e;
+  bf8 o[3][2];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const Slices3 x = split3(tile[16 * q + r][c], e);
+    const Slices3 x = split3(v[r], e);
 #pragma unroll
-    for (int sl = 0; sl < 3; ++sl) out[sl][c][16 * q + r] = x.s[sl];
+    for (int sl = 0; sl < 3; ++sl) o[sl][r >> 3][r & 7] = x.s[sl];
   }
-  __syncthreads();
-  // 3 slices x 64 columns x 8 pieces of 16 bytes: 6 per thread, eight lanes per column row
-  for (int u = threadIdx.x; u < 3 * 64 * 8; u += 256) {
-    const int sl = u / 512, rem = u - sl * 512, cc = rem >> 3, pc = rem & 7;
-    if (p0 + cc < P)
-      *(bf8*)(S3 + ((int64_t)sl * P + p0 + cc) * ld + j0 + 8 * pc) = *(const bf8*)(&out[sl][cc][8 * pc]);
-  }
+  if (pin)
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      bf8* dst = (bf8*)(S3 + ((int64_t)sl * P + p) * ld + j0);
+      dst[0] = o[sl][0];
+      dst[1] = o[sl][1];
+    }
 }
 
 // Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
