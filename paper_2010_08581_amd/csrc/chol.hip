@@ -1227,7 +1227,7 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     // with the panel wave), sixteen above
     const bool small = nblk <= 4;
     if (beside && beside->count > 0) {
-      const int64_t nred = (beside->count + kRedElems - 1) / kRedElems;
+      const int64_t nred = reduce_blocks(*beside, args.P);
       if (small)
         k_chol_reduce<8><<<(unsigned)(1 + (nred + 1) / 2), 512, lds, s>>>(args, *beside, nparts);
       else

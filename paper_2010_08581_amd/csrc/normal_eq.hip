@@ -849,7 +849,7 @@ hipError_t launch_sketch_split(const float* A, int64_t J, int P, void* S3, int64
 
 hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
                                hipStream_t s) {
-  const int64_t na = (a.count + kRedElems - 1) / kRedElems, nb = (b.count + kRedElems - 1) / kRedElems;
+  const int64_t na = reduce_blocks(a, P), nb = reduce_blocks(b, P);
   if (na + nb == 0) return hipSuccess;
   k_reduce_parts<<<(unsigned)(na + nb), 256, 0, s>>>(a, b, na, nparts, P, status);
   return hipGetLastError();
