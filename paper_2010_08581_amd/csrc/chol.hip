@@ -616,19 +616,20 @@ __device__ __forceinline__ void trail_block(double* __restrict__ Lg, double* __r
   store_acc(Aij, acc, lane);
 }
 
-// band I (blocks 4I .. 4I + nbI - 1), one workgroup per band J < I: 8 waves, wave (r, c) the
-// output blocks (4I + r, 4J + c) and (4I + r + 2, 4J + c); L read from Lp
+// band I (blocks 4I .. 4I + nbI - 1), two workgroups per band J < I, workgroup `half` taking
+// the block columns 4J + 2 half and 4J + 2 half + 1: 8 waves, wave (r, c) the output block
+// (4I + r, 4J + c) (one chain of block products per wave: two per wave left the matrix cores of
+// a band's workgroup the longest part of the last step); L read from Lp
 __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double* __restrict__ W, int nblk, int I,
-                                          int J) {
+                                          int J, int half) {
   extern __shared__ double lds[];
   double* const stage = lds;  // 16 blocks (kWrowLdsBytes)
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
-  const int r0 = wave >> 2, c = wave & 3;
+  const int r = wave >> 1, c = 2 * half + (wave & 1);
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
   const int bj = 4 * J + c;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = r0 + 2 * h, bi = 4 * I + r;
+  const int bi = 4 * I + r;
+  {
     d4 sacc = {0.0, 0.0, 0.0, 0.0};
     if (r < nbI) {
       for (int M = J; M < I; ++M)
@@ -641,9 +642,7 @@ __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double*
     store_acc(stage + (4 * r + c) * kBlk, sacc, lane);
   }
   __syncthreads();
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = r0 + 2 * h, bi = 4 * I + r;
+  {
     if (r < nbI) {
       d4 w = {0.0, 0.0, 0.0, 0.0};
       for (int r2 = 0; r2 <= r; ++r2)
@@ -658,12 +657,12 @@ __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double*
 __global__ __launch_bounds__(64 * kCholWaves) void k_big_wrow(const double* __restrict__ Lp, double* __restrict__ W,
                                                               int nblk, int I, const int* status, const int* fail) {
   if (*status != kDevOk || (fail && *fail)) return;
-  wrow_body(Lp, W, nblk, I, blockIdx.x);
+  wrow_body(Lp, W, nblk, I, (int)blockIdx.x >> 1, (int)blockIdx.x & 1);
 }
 
 // Step a.b0 / 4 > 0 of the factorisation in one launch.  Workgroup 0 forms the previous step's
 // panel for the rows of the diagonal region, applies that step's trailing update to the region,
-// then factors and inverts it; workgroups 1 .. I take band I of W (I = 0: none); the rest apply
+// then factors and inverts it; workgroups 1 .. 2I take band I of W (I = 0: none); the rest apply
 // the previous step's trailing update to the blocks below the region, one block per wave,
 // forming the panel rows they need themselves.  Only workgroup 0 reads the status word: it may
 // set it meanwhile, and the others' indexing does not depend on the data.
@@ -673,11 +672,11 @@ __global__ __launch_bounds__(64 * kCholWaves) void k_chol_step(CholArgs a, int I
     chol_body<true, kCholWaves>(a);
     return;
   }
-  if ((int)blockIdx.x <= I) {
-    wrow_body(a.Lp, a.W, nblk, I, (int)blockIdx.x - 1);
+  if ((int)blockIdx.x <= 2 * I) {
+    wrow_body(a.Lp, a.W, nblk, I, ((int)blockIdx.x - 1) >> 1, ((int)blockIdx.x - 1) & 1);
     return;
   }
-  const int q = ((int)blockIdx.x - 1 - I) * kCholWaves + (int)(threadIdx.x >> 6);
+  const int q = ((int)blockIdx.x - 1 - 2 * I) * kCholWaves + (int)(threadIdx.x >> 6);
   const int rem = nblk - a.b0;  // the previous step's trailing blocks start at this region
   if (q >= rem * (rem + 1) / 2) return;
   int ii, jj;
@@ -1259,16 +1258,17 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     if (K == 0) {
       k_chol<true, kCholWaves><<<1, 64 * kCholWaves, lds, s>>>(a);
     } else {
-      // band K - 1 of W: K - 1 workgroups (none when only the factor's regions are needed)
+      // band K - 1 of W: 2 (K - 1) workgroups (none when only the factor's regions are needed)
       const int band = (K >= 2 && !a.factor_only) ? K - 1 : 0;
       if (band > 0 && lds < kWrowLdsBytes) lds = kWrowLdsBytes;
       const int rem = nblk - a.b0;
       const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
-      k_chol_step<<<(unsigned)(1 + band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
+      k_chol_step<<<(unsigned)(1 + 2 * band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
     }
   }
   if (nb64 >= 2 && !a.factor_only)
-    k_big_wrow<<<(unsigned)(nb64 - 1), 64 * kCholWaves, kWrowLdsBytes, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status, a.fail);
+    k_big_wrow<<<(unsigned)(2 * (nb64 - 1)), 64 * kCholWaves, kWrowLdsBytes, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status,
+                                                                               a.fail);
   return hipGetLastError();
 }
 
