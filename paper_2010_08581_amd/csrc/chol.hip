@@ -32,6 +32,7 @@ constexpr int kLd = 17;         // padded row stride of a 16 x 16 block (doubles
 constexpr int kBlk = 16 * kLd;  // doubles per stored block
 constexpr int kLdsBlocks = 9;   // nblk up to which a factor is staged in LDS (45 blocks, 98 KB)
 constexpr int kCholWaves = 8;  // waves per workgroup of the large-P steps
+static_assert(kCholWaves % 4 == 0, "band workgroups split 4, 2 or 1 rows over the waves");
 // dynamic LDS of a large-P step: a four-block region (10 blocks), its staging blocks (4), the
 // previous step's panel rows (16), that panel's operands (10 + 16); the band workgroups of the
 // same launch use the first 16 blocks.  With the static arrays of the factorisation (about
@@ -616,53 +617,64 @@ __device__ __forceinline__ void trail_block(double* __restrict__ Lg, double* __r
   store_acc(Aij, acc, lane);
 }
 
-// band I (blocks 4I .. 4I + nbI - 1), two workgroups per band J < I, workgroup `half` taking
-// the block columns 4J + 2 half and 4J + 2 half + 1: 8 waves, wave (r, c) the output block
-// (4I + r, 4J + c) (one chain of block products per wave: two per wave left the matrix cores of
-// a band's workgroup the longest part of the last step); L read from Lp
+// band I (blocks 4I .. 4I + nbI - 1), four workgroups per band J < I, workgroup q taking the
+// block column bj = 4J + q.  Its 8 waves share the nbI output blocks (4I + r, bj): each block's
+// chain of products L(4I + r, bm) W(bm, bj), bm = bj .. 4I - 1, is cut into `parts` contiguous
+// pieces (8 waves over nbI rows: 2, 4 or 8 pieces), one per wave, and the pieces' sums are added
+// in order; then W(4I + r, bj) = -sum_{r2 <= r} W(4I + r, 4I + r2) S(4I + r2, bj).  One output
+// per workgroup column keeps the chains short: a band's workgroups are otherwise the longest
+// part of the last step.
 __device__ __forceinline__ void wrow_body(const double* __restrict__ Lp, double* __restrict__ W, int nblk, int I,
-                                          int J, int half) {
+                                          int J, int q) {
   extern __shared__ double lds[];
-  double* const stage = lds;  // 16 blocks (kWrowLdsBytes)
+  double* const stage = lds;      // 8 partial blocks
+  double* const sums = lds + 8 * kBlk;  // 4 summed blocks (kWrowLdsBytes: 16 blocks)
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
-  const int r = wave >> 1, c = 2 * half + (wave & 1);
   const int nbI = nblk - 4 * I < 4 ? nblk - 4 * I : 4;
-  const int bj = 4 * J + c;
+  const int rows = nbI > 2 ? 4 : nbI;  // row slots: 4, 2 or 1
+  const int parts = kCholWaves / rows;
+  const int r = wave / parts, part = wave - r * parts;
+  const int bj = 4 * J + q;
   const int bi = 4 * I + r;
+  const int n = 4 * I - bj;                // products of a chain (>= 1)
+  const int len = (n + parts - 1) / parts;  // per piece
   {
     d4 sacc = {0.0, 0.0, 0.0, 0.0};
-    if (r < nbI) {
-      for (int M = J; M < I; ++M)
-        for (int m = 0; m < 4; ++m) {
-          const int bm = 4 * M + m;
-          if (bm < bj) continue;  // W(bm, bj) is zero above the diagonal
-          sacc = mma_ab(Lp + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
-        }
-    }
-    store_acc(stage + (4 * r + c) * kBlk, sacc, lane);
+    if (r < nbI)
+      for (int bm = bj + part * len; bm < bj + (part + 1) * len && bm < 4 * I; ++bm)
+        sacc = mma_ab(Lp + (int64_t)slot(bi, bm) * kBlk, W + (int64_t)slot(bm, bj) * kBlk, sacc, lane);
+    store_acc(stage + wave * kBlk, sacc, lane);
   }
   __syncthreads();
-  {
-    if (r < nbI) {
-      d4 w = {0.0, 0.0, 0.0, 0.0};
-      for (int r2 = 0; r2 <= r; ++r2)
-        w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, stage + (4 * r2 + c) * kBlk, w, lane);
+  if (part == 0 && r < nbI) {
+    d4 v = load_acc(stage + wave * kBlk, lane);
+    for (int p = 1; p < parts; ++p) {
+      const d4 u = load_acc(stage + (wave + p) * kBlk, lane);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = -w[q];
-      store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
+      for (int k = 0; k < 4; ++k) v[k] += u[k];
     }
+    store_acc(sums + r * kBlk, v, lane);
+  }
+  __syncthreads();
+  if (part == 0 && r < nbI) {
+    d4 w = {0.0, 0.0, 0.0, 0.0};
+    for (int r2 = 0; r2 <= r; ++r2)
+      w = mma_ab(W + (int64_t)slot(bi, 4 * I + r2) * kBlk, sums + r2 * kBlk, w, lane);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = -w[k];
+    store_acc(W + (int64_t)slot(bi, bj) * kBlk, w, lane);
   }
 }
 
 __global__ __launch_bounds__(64 * kCholWaves) void k_big_wrow(const double* __restrict__ Lp, double* __restrict__ W,
                                                               int nblk, int I, const int* status, const int* fail) {
   if (*status != kDevOk || (fail && *fail)) return;
-  wrow_body(Lp, W, nblk, I, (int)blockIdx.x >> 1, (int)blockIdx.x & 1);
+  wrow_body(Lp, W, nblk, I, (int)blockIdx.x >> 2, (int)blockIdx.x & 3);
 }
 
 // Step a.b0 / 4 > 0 of the factorisation in one launch.  Workgroup 0 forms the previous step's
 // panel for the rows of the diagonal region, applies that step's trailing update to the region,
-// then factors and inverts it; workgroups 1 .. 2I take band I of W (I = 0: none); the rest apply
+// then factors and inverts it; workgroups 1 .. 4I take band I of W (I = 0: none); the rest apply
 // the previous step's trailing update to the blocks below the region, one block per wave,
 // forming the panel rows they need themselves.  Only workgroup 0 reads the status word: it may
 // set it meanwhile, and the others' indexing does not depend on the data.
@@ -672,11 +684,11 @@ __global__ __launch_bounds__(64 * kCholWaves) void k_chol_step(CholArgs a, int I
     chol_body<true, kCholWaves>(a);
     return;
   }
-  if ((int)blockIdx.x <= 2 * I) {
-    wrow_body(a.Lp, a.W, nblk, I, ((int)blockIdx.x - 1) >> 1, ((int)blockIdx.x - 1) & 1);
+  if ((int)blockIdx.x <= 4 * I) {
+    wrow_body(a.Lp, a.W, nblk, I, ((int)blockIdx.x - 1) >> 2, ((int)blockIdx.x - 1) & 3);
     return;
   }
-  const int q = ((int)blockIdx.x - 1 - 2 * I) * kCholWaves + (int)(threadIdx.x >> 6);
+  const int q = ((int)blockIdx.x - 1 - 4 * I) * kCholWaves + (int)(threadIdx.x >> 6);
   const int rem = nblk - a.b0;  // the previous step's trailing blocks start at this region
   if (q >= rem * (rem + 1) / 2) return;
   int ii, jj;
@@ -1258,16 +1270,16 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     if (K == 0) {
       k_chol<true, kCholWaves><<<1, 64 * kCholWaves, lds, s>>>(a);
     } else {
-      // band K - 1 of W: 2 (K - 1) workgroups (none when only the factor's regions are needed)
+      // band K - 1 of W: 4 (K - 1) workgroups (none when only the factor's regions are needed)
       const int band = (K >= 2 && !a.factor_only) ? K - 1 : 0;
       if (band > 0 && lds < kWrowLdsBytes) lds = kWrowLdsBytes;
       const int rem = nblk - a.b0;
       const int tgroups = (rem * (rem + 1) / 2 + kCholWaves - 1) / kCholWaves;
-      k_chol_step<<<(unsigned)(1 + 2 * band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
+      k_chol_step<<<(unsigned)(1 + 4 * band + tgroups), 64 * kCholWaves, lds, s>>>(a, band);
     }
   }
   if (nb64 >= 2 && !a.factor_only)
-    k_big_wrow<<<(unsigned)(2 * (nb64 - 1)), 64 * kCholWaves, kWrowLdsBytes, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status,
+    k_big_wrow<<<(unsigned)(4 * (nb64 - 1)), 64 * kCholWaves, kWrowLdsBytes, s>>>(a.Lp, a.W, nblk, nb64 - 1, a.status,
                                                                                a.fail);
   return hipGetLastError();
 }
