@@ -539,9 +539,11 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
     }
     if (GRAM) ncol_e = a.E[(eb0 + b) * P + bcg];
   };
-  bf8 cb[2][3];  // this block's column operand
-  int fcol = 0;
-  auto take_b = [&](const float (&src)[2][8]) {
+  // the column operand in two buffers (block b in one, b + 1 in the other): the next block's
+  // operand is formed while this block's products are still in the matrix cores
+  bf8 cbuf[2][2][3];
+  int fbuf[2] = {0, 0};  // its column exponent
+  auto take_b = [&](const float (&src)[2][8], bf8 (&cb)[2][3], int& fcol) {
     if (GRAM) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -580,18 +582,33 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   load_a(0);
   load_b(0, nx[0]);
   store_a(0);
-  take_b(nx[0]);
+  take_b(nx[0], cbuf[0], fbuf[0]);
   if (nblk > 1) load_b(1, nx[1]);  // data tiles: block 1 in flight from the start
   __syncthreads();
   // block b: its operands are staged (buffer b & 1, cb); the gather of block b + 1 is in
-  // src1 (data) and block b + 2 goes into src2
-  auto step = [&](int b, float (&src1)[2][8], float (&src2)[2][8]) {
+  // src1 (data) and block b + 2 goes into src2.  The next block's column operand goes into cbn:
+  // for data tiles its exponent is taken before the products and its 16 values per lane are
+  // split in MB pieces, one after each row block's products, so that the vector work of one
+  // wave runs beside the matrix-core work of the other wave on the SIMD.
+  auto step = [&](int b, float (&src1)[2][8], float (&src2)[2][8], bf8 (&cb)[2][3], int fcol, bf8 (&cbn)[2][3],
+                  int& fcoln) {
     const int buf = b & 1;
-    if (b + 1 < nblk) {
+    const bool more = b + 1 < nblk;
+    if (more) {
       load_a(b + 1);
       if (GRAM) load_b(b + 1, src2);
     }
     if (!GRAM && b + 2 < nblk) load_b(b + 2, src2);
+    if (!GRAM && more) {
+      float mx = 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(src1[h][e]));
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      fcoln = block_exponent((double)mx);
+    }
     const __bf16* As = Ab + buf * kBufElems;
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
@@ -608,8 +625,24 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
             if (si + ti < kX3Levels)
               acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
       }
+      if (!GRAM && more) {
+        // piece m of the next block's split: flattened values u = 8 h + e in [16 m / MB, 16 (m + 1) / MB)
+#pragma unroll
+        for (int u = 16 * m / MB; u < 16 * (m + 1) / MB; ++u) {
+          const Slices3 x = split3(src1[u >> 3][u & 7], fcoln);
+#pragma unroll
+          for (int sl = 0; sl < 3; ++sl) cbn[u >> 3][sl][u & 7] = x.s[sl];
+        }
+      }
       // one row block's operands live at a time (the loads of the next blocks stay in flight)
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if (GRAM && more) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) cbn[h][sl] = nb3[h][sl];
+      fcoln = ncol_e;
     }
     // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
 #pragma unroll
@@ -625,15 +658,12 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
-    if (b + 1 < nblk) {
-      store_a(buf ^ 1);
-      take_b(src1);
-    }
+    if (more) store_a(buf ^ 1);
     __syncthreads();
   };
   for (int b = 0; b < nblk; b += 2) {
-    step(b, nx[1], nx[0]);
-    if (b + 1 < nblk) step(b + 1, nx[0], nx[1]);
+    step(b, nx[1], nx[0], cbuf[0], fbuf[0], cbuf[1], fbuf[1]);
+    if (b + 1 < nblk) step(b + 1, nx[0], nx[1], cbuf[1], fbuf[1], cbuf[0], fbuf[0]);
   }
   const int col = col0 + wave * 16 + li;
   if (GRAM) {
