@@ -326,15 +326,17 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
         double nr[RM];
 #pragma unroll
         for (int co = 0; co < RM; ++co) nr[co] = 0.0;
-        // Rows and columns past rin x rout read an element of the slice (finite) and add 0, or
-        // land in entries of nr that are never read: no branches, so the LDS reads of every
-        // step can be in flight together.
+        // Rows past rin read the last row (finite) and add 0; columns past rout read the next
+        // entries of the sample's slot (at most index RM^2 - 1 < kSlice, but not staged: any
+        // value) and land only in entries of nr that are never read.  No branches and no
+        // clamped column index, so each row's RM reads pair into wide LDS reads and the reads of
+        // every step can be in flight together.
 #pragma unroll
         for (int ci = 0; ci < RM; ++ci) {
           const double v = ci < rin ? row[ci] : 0.0;
           const double* Sr = Sj + (ci < rin ? ci : rin - 1) * rout;
 #pragma unroll
-          for (int co = 0; co < RM; ++co) nr[co] = fma(v, Sr[co < rout ? co : rout - 1], nr[co]);
+          for (int co = 0; co < RM; ++co) nr[co] = fma(v, Sr[co], nr[co]);
         }
 #pragma unroll
         for (int c = 0; c < RM; ++c) row[c] = nr[c];
