@@ -72,16 +72,23 @@ __device__ void lds_scan_u64(uint64_t* t, int n, uint64_t* wsum) {
   __syncthreads();
 }
 
+// Staged slices: row stride kRowLd(RM) (even, >= RM) and one slot of kSliceLd(RM) doubles per
+// sample (even, so every row starts on 16 bytes; slots RM^2 + 2 doubles apart fall on distinct
+// LDS banks for the instance sizes).
+__host__ __device__ constexpr int kRowLd(int RM) { return (RM + 1) & ~1; }
+__host__ __device__ constexpr int kSliceLd(int RM) { return RM * kRowLd(RM) + 2; }
+
 template <typename TA, int RM, bool CHAIN>
 __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
   __shared__ uint64_t s_wsum[kThreads / 64];
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   if (*a.status != kDevOk) return;
   const int N = a.ring.N;
   const int K = N - 1;
   const int n = a.n;
   const int jb = a.jb;
-  constexpr int kSlice = RM * RM + 1;  // odd stride in doubles: samples fall on distinct banks
+  constexpr int kSlice = kSliceLd(RM), kLdR = kRowLd(RM);
+  static_assert(RM % 2 == 0, "slice rows are read as pairs");
   constexpr int kB = 16;               // loads in flight per thread while staging
   double* S = lds;                                    // jb * kSlice
   double* s_w = S + (size_t)jb * kSlice;              // jb
@@ -232,12 +239,12 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       s_w[tid] = w;
       if (j < a.J) a.w[j] = w;
     }
-    // stage the jb slices (rin x rout each, contiguous in slice-major storage).  Element e is
-    // sample e / ssz, entry e mod ssz; the quotient comes from a float reciprocal, exact here
-    // (e < 256 ssz: the rounding stays below 1/(2 ssz), the distance of (e + 1/2)/ssz from an
-    // integer; checked for every ssz <= 32^2)
+    // stage the jb slices (rin x rout each, contiguous in slice-major storage) with row stride
+    // kLdR.  Element e is sample e / ssz, entry o = e mod ssz, row o / rout; the quotients come
+    // from float reciprocals, exact here (e < 256 ssz and o < 32^2: the rounding stays below
+    // the distance of (e + 1/2)/ssz, (o + 1/2)/rout from an integer; checked for every ssz <= 32^2)
     const int tot = jb * ssz;
-    const float rs = 1.0f / (float)ssz;
+    const float rs = 1.0f / (float)ssz, rr = 1.0f / (float)rout;
     for (int base = 0; base < tot; base += kB * kThreads) {
       double v[kB];
       int dst[kB];
@@ -250,8 +257,9 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
           const int e = base + tid + kThreads * q;
           const int ec = e < tot ? e : tot - 1;  // clamped: every load is in bounds
           const int smp = (int)(((float)ec + 0.5f) * rs), o = ec - smp * ssz;
+          const int orow = (int)(((float)o + 0.5f) * rr);
           v[q] = core[(int64_t)s_idx[smp * K + k] * ssz + o];
-          dst[q] = e < tot ? smp * kSlice + o : -1;
+          dst[q] = e < tot ? smp * kSlice + orow * kLdR + (o - orow * rout) : -1;
         }
       }
 #pragma unroll
@@ -264,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       for (int q = 0; q < kSPW; ++q) {
         const int sq = wave + 4 * q;
         if (sq >= jb) continue;  // wave-uniform
-        const double* Sj = S + sq * kSlice;  // rin x rout, row-major
+        const double* Sj = S + sq * kSlice;  // rin x rout, row-major, row stride kLdR
         if (k == 0) {
           // D_0 = S_0^T (rout x Rn): entry (i, j) = S_0(j, i)
 #pragma unroll
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int i = 16 * tr + 4 * l4 + r, j = 16 * tc + l16;
-                D[q][tr][tc][r] = (i < rout && j < rin) ? (float)Sj[j * rout + i] : 0.f;
+                D[q][tr][tc][r] = (i < rout && j < rin) ? (float)Sj[j * kLdR + i] : 0.f;
               }
         } else {
           // B operand: D_{k-1} (rin x Rn), slots as above; A operand: S_k^T (rout x rin).  Each
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
               const int kk = t < 4 ? 4 * l4 + t : 16 + 4 * l4 + (t - 4);
-              const double v = (i < rout && kk < rin) ? Sj[kk * rout + i] : 0.0;
+              const double v = (i < rout && kk < rin) ? Sj[kk * kLdR + i] : 0.0;
               ah[t] = (__bf16)v;
               al[t] = (__bf16)(v - (double)ah[t]);
             }
@@ -321,22 +329,26 @@ __global__ __launch_bounds__(kThreads) void k_draw(DrawArgs a) {
       if (k == 0) {
 #pragma unroll
         for (int c = 0; c < RM; ++c)
-          if (c < rout) row[c] = Sj[b * rout + c];
+          if (c < rout) row[c] = Sj[b * kLdR + c];
       } else {
         double nr[RM];
 #pragma unroll
         for (int co = 0; co < RM; ++co) nr[co] = 0.0;
-        // Rows past rin read the last row (finite) and add 0; columns past rout read the next
-        // entries of the sample's slot (at most index RM^2 - 1 < kSlice, but not staged: any
-        // value) and land only in entries of nr that are never read.  No branches and no
-        // clamped column index, so each row's RM reads pair into wide LDS reads and the reads of
-        // every step can be in flight together.
+        // Rows past rin read the last row (finite) and add 0; columns past rout read the row's
+        // padding or unstaged entries of the sample's slot (at most index RM kLdR - 1 < kSlice:
+        // any value) and land only in entries of nr that are never read.  No branches and no
+        // clamped column index: each row is RM / 2 aligned 16-byte LDS reads, all of a step in
+        // flight together.
 #pragma unroll
         for (int ci = 0; ci < RM; ++ci) {
           const double v = ci < rin ? row[ci] : 0.0;
-          const double* Sr = Sj + (ci < rin ? ci : rin - 1) * rout;
+          const double2* Sr = (const double2*)(Sj + (ci < rin ? ci : rin - 1) * kLdR);
 #pragma unroll
-          for (int co = 0; co < RM; ++co) nr[co] = fma(v, Sr[co], nr[co]);
+          for (int co = 0; co < RM / 2; ++co) {
+            const double2 sv = Sr[co];
+            nr[2 * co] = fma(v, sv.x, nr[2 * co]);
+            nr[2 * co + 1] = fma(v, sv.y, nr[2 * co + 1]);
+          }
         }
 #pragma unroll
         for (int c = 0; c < RM; ++c) row[c] = nr[c];
@@ -442,7 +454,7 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   const int Rn = a.ring.ranks[a.n];
   // samples per workgroup: one thread per (sample, row b); slice staging within 64 KB
   int jb = kThreads / Rn;
-  const int cap = (int)((64 * 1024) / ((RM * RM + 1) * sizeof(double)));
+  const int cap = (int)((64 * 1024) / (kSliceLd(RM) * sizeof(double)));
   jb = jb < cap ? jb : cap;
   // BF16 form: the chain tiles of at most kChainSPW samples per wave live in registers
   if (std::is_same<TA, __bf16>::value && a.mfma_chain && jb > 4 * kChainSPW(RM)) jb = 4 * kChainSPW(RM);
@@ -453,7 +465,7 @@ hipError_t draw_dispatch(DrawArgs a, hipStream_t s) {
   for (int k = 0; k < K; ++k) tbytes += (size_t)a.ring.dims[(a.n + 1 + k) % a.ring.N] * 8;
   a.tables_in_lds = tbytes <= kDrawTableBytes;
   if (a.draw && a.weights && !a.tables_in_lds) return hipErrorInvalidValue;
-  const size_t head = ((size_t)jb * (RM * RM + 1) + jb + (jb * K + 1) / 2 + (size_t)jb * K) * sizeof(double);
+  const size_t head = ((size_t)jb * kSliceLd(RM) + jb + (jb * K + 1) / 2 + (size_t)jb * K) * sizeof(double);
   const size_t lds = head + (a.draw && a.tables_in_lds ? tbytes : 0);
   // a resident round of workgroups (LDS-bound, at most four per compute unit), each looping
   // over its batches
