@@ -68,7 +68,8 @@ struct NormalEqArgs {
   int64_t chunk;              // sample rows per split
   int P, In;
   int gram_tiles;             // column tiles of the Gram part (64 wide; 128, three-slice form)
-  int col_tiles, tiles, splits;  // filled in by launch_normal_eq
+  int col_tiles, tiles, splits;  // filled in by launch_normal_eq (three-slice form: tiles = the
+  int row_tiles;                 // tiles a split computes, strictly upper Gram tiles left out)
   double* Hpart;              // splits x P x P (lower triangle written)
   double* Bpart;              // splits x P x I_n
   int direct;                 // 1: the fiber of sample j is row j of `panel` (I_n wide)

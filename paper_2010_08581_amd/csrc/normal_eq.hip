@@ -696,19 +696,37 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   __shared__ int s_ea[2][RT];
   if (*a.status != kDevOk) return;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
-  const int s = lb / a.tiles, t = lb - s * a.tiles;
-  // row tiles vary fastest: the row tiles of one column tile (which gather the same fibers) run
-  // side by side on one XCD and share them through its L2
-  const int row_tiles = a.tiles / a.col_tiles;
-  const int rt = t % row_tiles, ct = t / row_tiles;
-  const int row0 = rt * RT;
-  if (ct < a.gram_tiles) {
-    const int col0 = ct * kX3ColTile;
-    if (col0 >= row0 + RT) return;  // strictly above the diagonal
-    x3_tile<MB, true>(a, s, row0, col0, s_roff, s_w, s_ea, x3_smem);
-  } else {
-    x3_tile<MB, false>(a, s, row0, (ct - a.gram_tiles) * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+  const int s = lb / a.tiles;
+  int t = lb - s * a.tiles;
+  // the grid holds only the tiles on or below the diagonal, so that every workgroup computes
+  // and the rounds of workgroups per XCD are the ones the planner counted.  Row tiles vary
+  // fastest: the row tiles of one column tile (which gather the same fibers) run side by side on
+  // one XCD and share them through its L2.  Gram column tile c keeps the row tiles from
+  // floor(128 c / RT) on (those reaching column 128 c).
+  const int row_tiles = a.row_tiles;
+  for (int c = 0; c < a.gram_tiles; ++c) {
+    const int first = (c * kX3ColTile) / RT < row_tiles ? (c * kX3ColTile) / RT : row_tiles;
+    const int n = row_tiles - first;
+    if (t < n) {
+      x3_tile<MB, true>(a, s, (first + t) * RT, c * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+      return;
+    }
+    t -= n;
   }
+  const int rt = t % row_tiles, ct = t / row_tiles;
+  x3_tile<MB, false>(a, s, rt * RT, ct * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+}
+
+// Tiles one split of the three-slice kernel computes: every data tile and the Gram tiles on or
+// below the diagonal.
+int x3_live_tiles(const NormalEqPlan& pl) {
+  const int RT = 16 * pl.mb;
+  int n = pl.row_tiles * pl.data_tiles;
+  for (int c = 0; c < pl.gram_tiles; ++c) {
+    const int first = (c * kX3ColTile) / RT;
+    n += pl.row_tiles - (first < pl.row_tiles ? first : pl.row_tiles);
+  }
+  return n;
 }
 
 size_t x3_dyn_lds(int mb) {
@@ -752,6 +770,41 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s,
 
 }  // namespace
 
+// Splits of the three-slice kernel.  Its workgroups hold a CU each for the whole split (one per
+// CU), so a launch takes ceil(workgroups on an XCD / CUs per XCD) rounds, each as long as one
+// split's 64-sample blocks; every split adds its FP64 partials of H and B, written once and read
+// once by the reduction.  The split count minimises
+//     rounds * (blocks per split + 1) + splits * partial bytes / 12 MB
+// (12 MB: what the reduction moves in about the time of one block; the 1 a workgroup's prologue
+// and epilogue), over chunks of at most kMaxChunkX3 rows, ties to fewer splits.
+static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu) {
+  const int live = x3_live_tiles(pl);
+  const int P = 16 * pl.mb * pl.row_tiles;  // bound on the partial rows, padding included
+  const double part_blocks = 16.0 * ((double)P * (P + 1) / 2 + (double)P * 128 * pl.data_tiles) / 12e6;
+  const int per_xcd = num_cu / kXcds > 0 ? num_cu / kXcds : 1;
+  const int64_t s_lo = (J + kMaxChunkX3 - 1) / kMaxChunkX3;
+  int64_t s_hi = 4 * (int64_t)num_cu / live + 2;
+  if (s_hi > (J + kSplitBlock - 1) / kSplitBlock) s_hi = (J + kSplitBlock - 1) / kSplitBlock;
+  if (s_hi < s_lo) s_hi = s_lo;
+  double best = 1e300;
+  int64_t best_chunk = 0;
+  for (int64_t S = s_lo; S <= s_hi; ++S) {
+    const int64_t chunk = ((J + S - 1) / S + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+    if (chunk > kMaxChunkX3) continue;
+    const int64_t splits = (J + chunk - 1) / chunk;
+    const int64_t grid = splits * live;
+    const int64_t rounds = ((grid + kXcds - 1) / kXcds + per_xcd - 1) / per_xcd;
+    const double cost = (double)rounds * (double)(chunk / kSplitBlock + 1) + part_blocks * (double)splits;
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_chunk = chunk;
+    }
+  }
+  pl.chunk = best_chunk;
+  pl.splits = (int)((J + best_chunk - 1) / best_chunk);
+  return pl;
+}
+
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) {
   NormalEqPlan pl;
   // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding.
@@ -781,15 +834,13 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   const int ctile = ne_dtype == 3 ? kX3ColTile : kColTile;
   pl.gram_tiles = (P + ctile - 1) / ctile;
   pl.data_tiles = (In + ctile - 1) / ctile;
+  if (ne_dtype == 3) return plan_x3_splits(pl, J, num_cu);
   const int64_t tiles = (int64_t)pl.row_tiles * (pl.gram_tiles + pl.data_tiles);
   // workgroups resident per CU (LDS-bound) and the rows one split must be a multiple of
   int per_cu, quantum;
   if (ne_dtype == 2) {
     per_cu = 2;  // register bound (196 of 512 registers per lane: two waves per SIMD)
     quantum = kKB16;
-  } else if (ne_dtype == 3) {
-    per_cu = 2;  // register bound
-    quantum = kSplitBlock;
   } else {
     const int kg = ne_dtype == 1 ? 2 : 1;
     const int esz = ne_dtype == 1 ? 4 : 8;
@@ -805,12 +856,11 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   if (S < 1) S = 1;
   if (S > J / quantum) S = J / quantum;
   if (S < 1) S = 1;
-  const int64_t maxchunk = (ne_dtype == 3 ? kMaxChunkX3 : kMaxChunk) - quantum;
+  const int64_t maxchunk = kMaxChunk - quantum;
   if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
   int64_t chunk = (J + S - 1) / S;
-  // the BF16 form reads its transposed sketch in 16-byte groups, the three-slice form in
-  // 64-sample exponent blocks: splits start on a quantum
-  if (ne_dtype >= 2) chunk = (chunk + quantum - 1) / quantum * quantum;
+  // the BF16 form reads its transposed sketch in 16-byte groups: splits start on a quantum
+  if (ne_dtype == 2) chunk = (chunk + quantum - 1) / quantum * quantum;
   pl.chunk = chunk;
   pl.splits = (int)((J + chunk - 1) / chunk);
   return pl;
@@ -820,7 +870,8 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
                             hipEvent_t e0, hipEvent_t e1) {
   NormalEqArgs a = args;
   a.col_tiles = pl.gram_tiles + pl.data_tiles;
-  a.tiles = pl.row_tiles * a.col_tiles;
+  a.row_tiles = pl.row_tiles;
+  a.tiles = ne_dtype == 3 ? x3_live_tiles(pl) : pl.row_tiles * a.col_tiles;
   a.splits = pl.splits;
   if ((int64_t)pl.splits * a.tiles > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(pl.splits * a.tiles);
