@@ -35,7 +35,7 @@ struct Layout {
   // and the transfer-matrix work area
   size_t tcore[kMaxOrder];
   size_t Tm, Xg, inner, inner_res;
-  size_t idx, w, A, S3, E3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, qalt, ysol, partial, scal, total;
+  size_t idx, w, A, S3, E3, D3, ED3, Hpart, Bpart, Bred, M, M2, F, F2, gauge, qr, qalt, ysol, partial, scal, total;
   int64_t partial_count;
 };
 
@@ -224,6 +224,9 @@ void plan(const Problem& p, Layout* L) {
     const size_t ld = (size_t)(p.J + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
     L->S3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Pmax * ld * 2 : 0);
     L->E3 = take(p.ne_dt == 3 ? (size_t)p.Pmax * (ld / kSplitBlock) * 4 : 0);
+    // the weighted fibers in the same form (the contraction's column operand)
+    L->D3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Imax * ld * 2 : 0);
+    L->ED3 = take(p.ne_dt == 3 ? (size_t)p.Imax * (ld / kSplitBlock) * 4 : 0);
   }
   L->Hpart = take(hpart * 8);  // FP64 split-K partials
   L->Bpart = take(bpart * 8);
@@ -579,6 +582,8 @@ int run_update(trals_ctx* h) {
     na.S3 = h->at<const void>(h->L.S3);
     na.E = h->at<const int>(h->L.E3);
     na.ld = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
+    na.D3 = h->at<void>(h->L.D3);
+    na.ED = h->at<int>(h->L.ED3);
   }
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
   // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the

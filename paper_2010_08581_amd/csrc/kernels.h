@@ -79,6 +79,11 @@ struct NormalEqArgs {
   // block exponents E[b P + p] (launch_sketch_split writes both)
   const void* S3;
   const int* E;
+  // and the weighted fibers w_j X(j, i) in the same form, slice s of column i at
+  // D3 + (s I_n + i) ld, exponents ED[b I_n + i]: launch_normal_eq writes them (fiber split)
+  // before the contraction reads them
+  void* D3;
+  int* ED;
 };
 struct NormalEqPlan {
   int mb;          // row tile = 16 * mb rows of P
@@ -95,7 +100,9 @@ constexpr int kSketchPadRows = 64;
 // (two transposed BF16 sketches, BF16 panel, BF16 matrix cores with FP32 accumulation within
 // a split); 3: FP32 path on BF16 matrix cores with exact products: the FP32 sketch and the
 // weighted FP32 fibers in three 8-bit slices per 64-sample block and column (one exponent
-// each), slice products exact in FP32, block sums added in FP64.
+// each), slice products exact in FP32, block sums added in FP64.  For ne_dtype 3 the launch is
+// two kernels: the fiber split (gather and slices of w_j X(j, :), into D3 / ED), then the
+// contraction; e0 stamps the first one's start, e1 the second one's end.
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
 // e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,

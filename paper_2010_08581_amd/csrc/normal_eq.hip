@@ -35,8 +35,6 @@ constexpr int kColTile = 64;
 constexpr int kX3ColTile = 128;  // column tile of the three-slice kernel (eight waves of 16)
 constexpr int kKB = 32;          // sample rows per LDS stage (8 MFMA k-steps)
 constexpr int kMaxChunk = 1024;  // sample rows per split, padding included (row offsets and weights in LDS)
-// the three-slice kernel keeps one workgroup per CU either way: longer splits, fewer FP64 partials
-constexpr int kMaxChunkX3 = 4096;
 constexpr int kLdsBytes = 160 * 1024;
 
 // LDS bytes of the FP64 / FP32 kernel: KG groups x double-buffered A and B stages.
@@ -429,15 +427,74 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
     }
 }
 
+// grid (ceil(I_n / 64), ceil(J / 64)): the weighted fibers w_j X(j, :) (FP32 product of the
+// FP32 weight and the panel entry) of one 64-sample block and 64 columns, gathered and split as
+// the sketch is: lane (li, q) of wave w holds samples 16 q .. 16 q + 15 of column 16 w + li
+// (the 16 lanes of one q read 64 contiguous bytes of a fiber), the column's exponent takes two
+// lane exchanges, and each lane stores 32 contiguous bytes per slice.  Samples past J have
+// weight 0 and row 0.
+__global__ __launch_bounds__(256) void k_fiber_split(NormalEqArgs a) {
+  __shared__ int64_t s_off[kSplitBlock];
+  __shared__ float s_w[kSplitBlock];
+  if (*a.status != kDevOk) return;
+  const int64_t jb = (int64_t)blockIdx.y * kSplitBlock;
+  const int In = a.In;
+  if (threadIdx.x < kSplitBlock) {
+    const int64_t j = jb + threadIdx.x;
+    int64_t off = 0;
+    float w = 0.f;
+    if (j < a.J) {
+      if (a.direct) {
+        off = j;
+      } else {
+        const int32_t* ij = a.idx + j * a.K;
+        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      }
+      w = (float)a.w[j];
+    }
+    s_off[threadIdx.x] = off * In;
+    s_w[threadIdx.x] = w;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int i = blockIdx.x * 64 + 16 * wave + li;
+  const bool in = i < In;
+  const int ic = in ? i : In - 1;
+  const float* X = (const float*)a.panel;
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = s_w[16 * q + r] * X[s_off[16 * q + r] + ic];
+  float mx = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fabsf(v[r]));
+  mx = fmaxf(mx, __shfl_xor(mx, 16));
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  const int e = block_exponent((double)mx);
+  if (q == 0 && in) a.ED[(int64_t)blockIdx.y * In + i] = e;
+  bf8 o[3][2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const Slices3 x = split3(v[r], e);
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) o[sl][r >> 3][r & 7] = x.s[sl];
+  }
+  if (in)
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      bf8* dst = (bf8*)((__bf16*)a.D3 + ((int64_t)sl * In + i) * a.ld + jb + 16 * q);
+      dst[0] = o[sl][0];
+      dst[1] = o[sl][1];
+    }
+}
+
 // Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
 // MB row blocks and both 32-sample halves (matrix-core k-steps) of every 64-sample block, so
-// that its level sums cover 64 samples between FP64 flushes (each stays below 2^22 in
+// that its level sums cover 64 samples between FP64 flushes (each stays below 2^23 in
 // magnitude, exact in FP32).  The sketch rows of the tile (three slices, both halves) are staged
 // in LDS by the whole workgroup, double-buffered with one barrier per block; each wave loads the
 // column operand of its own columns directly into the matrix-core registers, one block ahead:
-// Gram tiles read the sketch slices, data tiles gather the fibers and split them (exponent per
-// column and 64-sample block, as the sketch's: a column's 64 samples sit in lanes li, li + 16,
-// li + 32, li + 48, sixteen each).
+// Gram tiles read the sketch slices, data tiles the fiber slices (k_fiber_split).
 constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
                            // of 16 rows fall on distinct banks)
 // Slice products kept: level l = si + ti of s_si t_ti weighs 2^(-8 l) against the leading
@@ -448,13 +505,11 @@ constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 
 // by cond(A)^2 in the solution (video cores 4.8e-7 -> 9.8e-6 against the oracle).
 constexpr int kX3Levels = 4;
 
-// One tile of k_normal_eq_x3; GRAM selects the column operand (the two paths' registers are
-// allocated separately).  Data tiles gather their fibers two blocks ahead (the block loop is
-// unrolled by two so that the two gather buffers keep static indices); Gram tiles read their
-// column slices one block ahead.
+// One tile of k_normal_eq_x3; GRAM selects the column operand (sketch or fiber slices) and the
+// output (H or B partials).
 template <int MB, bool GRAM>
-__device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, int col0, int64_t* s_roff,
-                                        float* s_w, int (*s_ea)[16 * MB], unsigned char* smem) {
+__device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, int col0, int (*s_ea)[16 * MB],
+                                        unsigned char* smem) {
   constexpr int RT = 16 * MB;
   constexpr int kBufElems = 3 * RT * kX3Ld;            // one buffer of staged sketch slices
   constexpr int kChunks = 3 * RT * (kSplitBlock / 8);  // 16-byte pieces of a buffer
@@ -468,25 +523,6 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int li = lane & 15, lg = lane >> 4;
   __bf16* Ab = (__bf16*)smem;  // [2][3][RT][kX3Ld]
-  const float* X = (const float*)a.panel;
-  if (!GRAM) {
-    // row offsets and (FP32) weights of the chunk's samples; past the chunk the weight is zero
-    for (int r = tid; r < nblk * kSplitBlock; r += 512) {
-      int64_t off = 0;
-      float w = 0.f;
-      if (r < nrows) {
-        if (a.direct) {
-          off = r0 + r;
-        } else {
-          const int32_t* ij = a.idx + (r0 + r) * a.K;
-          for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
-        }
-        w = (float)a.w[r0 + r];
-      }
-      s_roff[r] = off * In;
-      s_w[r] = w;
-    }
-  }
   const __bf16* S3 = (const __bf16*)a.S3;
   const int64_t ld = a.ld, sstride = (int64_t)P * ld;
   const int64_t eb0 = r0 / kSplitBlock;
@@ -517,57 +553,24 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
     }
     if (tid < RT) s_ea[buf][tid] = stg_ea;
   };
-  // column operand of this wave: Gram tiles, sketch column bcg; data tiles, fiber entry bcol
+  // column operand of this wave: sketch column (Gram tiles) or fiber column (data tiles) bcc
   const int bc = col0 + 16 * wave + li;
-  const int bcg = bc < P ? bc : P - 1;
-  const int bcol = bc < In ? bc : In - 1;
-  const __bf16* brow = S3 + (int64_t)bcg * ld + r0;
-  bf8 nb3[2][3];      // Gram tiles: next block's column slices, both halves
+  const int ncols = GRAM ? P : In;
+  const int bcc = bc < ncols ? bc : ncols - 1;
+  const __bf16* C3 = GRAM ? S3 : (const __bf16*)a.D3;
+  const int* CE = GRAM ? a.E : a.ED;
+  const int64_t cstride = (int64_t)ncols * ld;
+  const __bf16* brow = C3 + (int64_t)bcc * ld + r0;
+  bf8 nb3[2][3];  // next block's column slices, both halves
   int ncol_e = 0;
-  float nx[2][2][8];  // data tiles: two blocks' fiber values, both halves
-  auto load_b = [&](int b, float (&dst)[2][8]) {
+  auto load_b = [&](int b) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int k0 = b * kSplitBlock + 32 * h + 8 * lg;  // this lane's 8 samples of half h
-      if (GRAM) {
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl) nb3[h][sl] = *(const bf8*)(brow + sl * sstride + k0);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dst[h][e] = s_w[k0 + e] * X[s_roff[k0 + e] + bcol];
-      }
+      for (int sl = 0; sl < 3; ++sl) nb3[h][sl] = *(const bf8*)(brow + sl * cstride + k0);
     }
-    if (GRAM) ncol_e = a.E[(eb0 + b) * P + bcg];
-  };
-  // the column operand in two buffers (block b in one, b + 1 in the other): the next block's
-  // operand is formed while this block's products are still in the matrix cores
-  bf8 cbuf[2][2][3];
-  int fbuf[2] = {0, 0};  // its column exponent
-  auto take_b = [&](const float (&src)[2][8], bf8 (&cb)[2][3], int& fcol) {
-    if (GRAM) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int sl = 0; sl < 3; ++sl) cb[h][sl] = nb3[h][sl];
-      fcol = ncol_e;
-    } else {
-      float mx = 0.f;
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(src[h][e]));
-      mx = fmaxf(mx, __shfl_xor(mx, 16));
-      mx = fmaxf(mx, __shfl_xor(mx, 32));
-      fcol = block_exponent((double)mx);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const Slices3 x = split3(src[h][e], fcol);
-#pragma unroll
-          for (int sl = 0; sl < 3; ++sl) cb[h][sl][e] = x.s[sl];
-        }
-    }
+    ncol_e = CE[(eb0 + b) * ncols + bcc];
   };
   f4 acc[MB][kX3Levels];
   double out[MB][4];
@@ -578,36 +581,22 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
   }
-  if (!GRAM) __syncthreads();  // row offsets and weights
   load_a(0);
-  load_b(0, nx[0]);
+  load_b(0);
   store_a(0);
-  take_b(nx[0], cbuf[0], fbuf[0]);
-  if (nblk > 1) load_b(1, nx[1]);  // data tiles: block 1 in flight from the start
   __syncthreads();
-  // block b: its operands are staged (buffer b & 1, cb); the gather of block b + 1 is in
-  // src1 (data) and block b + 2 goes into src2.  The next block's column operand goes into cbn:
-  // for data tiles its exponent is taken before the products and its 16 values per lane are
-  // split in MB pieces, one after each row block's products, so that the vector work of one
-  // wave runs beside the matrix-core work of the other wave on the SIMD.
-  auto step = [&](int b, float (&src1)[2][8], float (&src2)[2][8], bf8 (&cb)[2][3], int fcol, bf8 (&cbn)[2][3],
-                  int& fcoln) {
+  for (int b = 0; b < nblk; ++b) {
     const int buf = b & 1;
     const bool more = b + 1 < nblk;
+    bf8 cb[2][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int sl = 0; sl < 3; ++sl) cb[h][sl] = nb3[h][sl];
+    const int fcol = ncol_e;
     if (more) {
       load_a(b + 1);
-      if (GRAM) load_b(b + 1, src2);
-    }
-    if (!GRAM && b + 2 < nblk) load_b(b + 2, src2);
-    if (!GRAM && more) {
-      float mx = 0.f;
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(src1[h][e]));
-      mx = fmaxf(mx, __shfl_xor(mx, 16));
-      mx = fmaxf(mx, __shfl_xor(mx, 32));
-      fcoln = block_exponent((double)mx);
+      load_b(b + 1);
     }
     const __bf16* As = Ab + buf * kBufElems;
 #pragma unroll
@@ -625,24 +614,6 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
             if (si + ti < kX3Levels)
               acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
       }
-      if (!GRAM && more) {
-        // piece m of the next block's split: flattened values u = 8 h + e in [16 m / MB, 16 (m + 1) / MB)
-#pragma unroll
-        for (int u = 16 * m / MB; u < 16 * (m + 1) / MB; ++u) {
-          const Slices3 x = split3(src1[u >> 3][u & 7], fcoln);
-#pragma unroll
-          for (int sl = 0; sl < 3; ++sl) cbn[u >> 3][sl][u & 7] = x.s[sl];
-        }
-      }
-      // one row block's operands live at a time (the loads of the next blocks stay in flight)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (GRAM && more) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int sl = 0; sl < 3; ++sl) cbn[h][sl] = nb3[h][sl];
-      fcoln = ncol_e;
     }
     // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
 #pragma unroll
@@ -660,10 +631,6 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
       for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
     if (more) store_a(buf ^ 1);
     __syncthreads();
-  };
-  for (int b = 0; b < nblk; b += 2) {
-    step(b, nx[1], nx[0], cbuf[0], fbuf[0], cbuf[1], fbuf[1]);
-    if (b + 1 < nblk) step(b + 1, nx[0], nx[1], cbuf[1], fbuf[1], cbuf[0], fbuf[0]);
   }
   const int col = col0 + wave * 16 + li;
   if (GRAM) {
@@ -691,8 +658,6 @@ template <int MB>
 __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
   extern __shared__ __align__(16) unsigned char x3_smem[];
-  __shared__ int64_t s_roff[kMaxChunkX3];
-  __shared__ float s_w[kMaxChunkX3];
   __shared__ int s_ea[2][RT];
   if (*a.status != kDevOk) return;
   const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
@@ -708,13 +673,13 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
     const int first = (c * kX3ColTile) / RT < row_tiles ? (c * kX3ColTile) / RT : row_tiles;
     const int n = row_tiles - first;
     if (t < n) {
-      x3_tile<MB, true>(a, s, (first + t) * RT, c * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+      x3_tile<MB, true>(a, s, (first + t) * RT, c * kX3ColTile, s_ea, x3_smem);
       return;
     }
     t -= n;
   }
   const int rt = t % row_tiles, ct = t / row_tiles;
-  x3_tile<MB, false>(a, s, rt * RT, ct * kX3ColTile, s_roff, s_w, s_ea, x3_smem);
+  x3_tile<MB, false>(a, s, rt * RT, ct * kX3ColTile, s_ea, x3_smem);
 }
 
 // Tiles one split of the three-slice kernel computes: every data tile and the Gram tiles on or
@@ -776,13 +741,13 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s,
 // once by the reduction.  The split count minimises
 //     rounds * (blocks per split + 1) + splits * partial bytes / 12 MB
 // (12 MB: what the reduction moves in about the time of one block; the 1 a workgroup's prologue
-// and epilogue), over chunks of at most kMaxChunkX3 rows, ties to fewer splits.
+// and epilogue), ties to fewer splits.
 static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu) {
   const int live = x3_live_tiles(pl);
   const int P = 16 * pl.mb * pl.row_tiles;  // bound on the partial rows, padding included
   const double part_blocks = 16.0 * ((double)P * (P + 1) / 2 + (double)P * 128 * pl.data_tiles) / 12e6;
   const int per_xcd = num_cu / kXcds > 0 ? num_cu / kXcds : 1;
-  const int64_t s_lo = (J + kMaxChunkX3 - 1) / kMaxChunkX3;
+  const int64_t s_lo = 1;
   int64_t s_hi = 4 * (int64_t)num_cu / live + 2;
   if (s_hi > (J + kSplitBlock - 1) / kSplitBlock) s_hi = (J + kSplitBlock - 1) / kSplitBlock;
   if (s_hi < s_lo) s_hi = s_lo;
@@ -790,7 +755,6 @@ static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu) {
   int64_t best_chunk = 0;
   for (int64_t S = s_lo; S <= s_hi; ++S) {
     const int64_t chunk = ((J + S - 1) / S + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
-    if (chunk > kMaxChunkX3) continue;
     const int64_t splits = (J + chunk - 1) / chunk;
     const int64_t grid = splits * live;
     const int64_t rounds = ((grid + kXcds - 1) / kXcds + per_xcd - 1) / per_xcd;
@@ -878,11 +842,17 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 3) {
+    if (!a.D3 || !a.ED || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
+    const dim3 sgrid((unsigned)((a.In + 63) / 64), (unsigned)((a.J + kSplitBlock - 1) / kSplitBlock));
+    if (e0)
+      hipExtLaunchKernelGGL(k_fiber_split, sgrid, dim3(256), 0, s, e0, nullptr, 0, a);
+    else
+      k_fiber_split<<<sgrid, 256, 0, s>>>(a);
     switch (pl.mb) {
 #define TRALS_NE3_CASE(MB)                                                                  \
   case MB:                                                                                  \
-    if (e0)                                                                                 \
-      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(512), x3_dyn_lds(MB), s, e0, e1, 0, a); \
+    if (e1)                                                                                 \
+      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(512), x3_dyn_lds(MB), s, nullptr, e1, 0, a); \
     else                                                                                    \
       k_normal_eq_x3<MB><<<grid, 512, x3_dyn_lds(MB), s>>>(a);                              \
     break;
