@@ -565,11 +565,6 @@ int run_update(trals_ctx* h) {
     fa.status = h->status();
     HIPTRY(launch_fibers(fa, p.panel_dt, h->stream));
   }
-  if (p.ne_dt == 3) {
-    const int64_t ld3 = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
-    HIPTRY(launch_sketch_split(h->at<const float>(h->L.A), Jn, P, h->at<void>(h->L.S3), ld3, h->at<int>(h->L.E3),
-                               h->status(), h->stream));
-  }
   PROF_END(TRALS_K_DRAW);
 
   const NormalEqPlan pl = plan_normal_eq(P, In, Jn, p.ne_dt, kPlanCUs);
@@ -579,8 +574,8 @@ int run_update(trals_ctx* h) {
   na.A2 = da.A2;
   na.ld = da.ldt;
   if (p.ne_dt == 3) {
-    na.S3 = h->at<const void>(h->L.S3);
-    na.E = h->at<const int>(h->L.E3);
+    na.S3 = h->at<__bf16>(h->L.S3);
+    na.E = h->at<int>(h->L.E3);
     na.ld = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
     na.D3 = h->at<void>(h->L.D3);
     na.ED = h->at<int>(h->L.ED3);
@@ -655,11 +650,6 @@ int run_update(trals_ctx* h) {
     DrawArgs dr = da;
     dr.status = g;
     HIPTRY(launch_draw(dr, p.sk_dt, h->stream));
-    if (p.ne_dt == 3) {
-      const int64_t ld3 = (Jn + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
-      HIPTRY(launch_sketch_split(h->at<const float>(h->L.A), Jn, P, h->at<void>(h->L.S3), ld3,
-                                 h->at<int>(h->L.E3), g, h->stream));
-    }
     NormalEqArgs nr = na;
     nr.status = g;
     HIPTRY(launch_normal_eq(nr, pl, p.ne_dt, h->stream, nullptr, nullptr));

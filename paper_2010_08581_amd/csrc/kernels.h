@@ -74,14 +74,13 @@ struct NormalEqArgs {
   double* Bpart;              // splits x P x I_n
   int direct;                 // 1: the fiber of sample j is row j of `panel` (I_n wide)
   const int* status;
-  // FP32 path (ne_dtype 3): the sketch in three BF16 slices per 64-sample block and column,
-  // slice s of column p at S3 + (s P + p) ld (ld samples per column, a multiple of 64), and the
-  // block exponents E[b P + p] (launch_sketch_split writes both)
-  const void* S3;
-  const int* E;
-  // and the weighted fibers w_j X(j, i) in the same form, slice s of column i at
-  // D3 + (s I_n + i) ld, exponents ED[b I_n + i]: launch_normal_eq writes them (fiber split)
-  // before the contraction reads them
+  // FP32 path (ne_dtype 3): the sketch rows A (FP32, J x P row-major) in three BF16 slices per
+  // 64-sample block and column, slice s of column p at S3 + (s P + p) ld (ld samples per
+  // column, a multiple of 64), with block exponents E[b P + p]; the weighted fibers w_j X(j, i)
+  // in the same form, slice s of column i at D3 + (s I_n + i) ld, exponents ED[b I_n + i].
+  // launch_normal_eq writes all four (split pass) before the contraction reads them.
+  __bf16* S3;
+  int* E;
   void* D3;
   int* ED;
 };
@@ -101,18 +100,17 @@ constexpr int kSketchPadRows = 64;
 // a split); 3: FP32 path on BF16 matrix cores with exact products: the FP32 sketch and the
 // weighted FP32 fibers in three 8-bit slices per 64-sample block and column (one exponent
 // each), slice products exact in FP32, block sums added in FP64.  For ne_dtype 3 the launch is
-// two kernels: the fiber split (gather and slices of w_j X(j, :), into D3 / ED), then the
-// contraction; e0 stamps the first one's start, e1 the second one's end.
+// two kernels: the split pass (slices of the sketch into S3 / E and of the gathered weighted
+// fibers w_j X(j, :) into D3 / ED), then the contraction; e0 stamps the first one's start, e1
+// the second one's end.
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
 // e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// Three-slice form of the FP32 sketch rows A (J x P, row-major) for ne_dtype 3: per block b of
-// 64 samples and column p, E[b P + p] = e with max_j |A(j, p)| < 2^e over the block, and
-// A(j, p) = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2) + r, |r| <= 2^(e-25), with integers |s0| <= 256,
-// |s1|, |s2| <= 128 stored as BF16 (exact): S3[(s P + p) ld + j].  Samples past J are zero.
-hipError_t launch_sketch_split(const float* A, int64_t J, int P, void* S3, int64_t ld, int* E, const int* status,
-                               hipStream_t s);
+// Three-slice form of an FP32 operand (the sketch rows, the weighted fibers) for ne_dtype 3:
+// per block b of 64 samples and column p, e = E[b ncols + p] with max_j |V(j, p)| < 2^e over
+// the block, and V(j, p) = 2^(e-8) (s0 + 2^-8 s1 + 2^-16 s2) + r, |r| <= 2^(e-25), with
+// integers |s0| <= 256, |s1|, |s2| <= 128 stored as BF16 (exact).  Samples past J are zero.
 constexpr int kSplitBlock = 64;  // samples per exponent block of the three-slice sketch
 
 // out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:

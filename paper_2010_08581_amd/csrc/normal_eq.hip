@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
 // the BF16 matrix cores is exact.  After each block the level sums are combined and scaled by
 // 2^(e_row + e_col - 16) in FP64 and added to FP64 accumulators.
 //
-// The sketch side has one representation (launch_sketch_split), used both as the row operand
+// The sketch side has one representation (sketch_split_tile), used both as the row operand
 // and, in the Gram tiles, as the column operand: H is exactly R(A)^T R(A).  The data side is the
 // weighted fiber w_j X(j, i), split in the kernel with the block maximum of its column (the 64
 // samples of a column sit in four lanes: a max over the lane's 16 values and two exchanges).  So
@@ -387,19 +387,18 @@ __device__ __forceinline__ Slices3 split3(float v, int e) {
   return Slices3{{(__bf16)a0, (__bf16)a1, (__bf16)a2}};
 }
 
-// grid (ceil(P / 64), ceil(J / 64)): one 64 x 64 tile of the sketch per workgroup, no LDS.
+// One 64 x 64 tile (bx, by) of the sketch per workgroup, no LDS.
 // Wave w takes columns 16 w .. 16 w + 15 of the tile; lane (li, q) = (lane % 16, lane / 16)
 // holds samples 16 q .. 16 q + 15 of column li, so a column's 64 samples sit in four lanes of one
 // wave: its block maximum takes two lane exchanges, and each lane stores its 16 samples of each
 // slice as 32 contiguous bytes (the four lanes of a column fill its 128-byte run).
-__global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ A, int64_t J, int P,
-                                                      __bf16* __restrict__ S3, int64_t ld, int* __restrict__ E,
-                                                      const int* status) {
-  if (*status != kDevOk) return;
+__device__ __forceinline__ void sketch_split_tile(const float* __restrict__ A, int64_t J, int P,
+                                                  __bf16* __restrict__ S3, int64_t ld, int* __restrict__ E, int bx,
+                                                  int by) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
-  const int p = blockIdx.x * 64 + 16 * wave + li;
-  const int64_t j0 = (int64_t)blockIdx.y * kSplitBlock + 16 * q;
+  const int p = bx * 64 + 16 * wave + li;
+  const int64_t j0 = (int64_t)by * kSplitBlock + 16 * q;
   const bool pin = p < P;
   float v[16];
 #pragma unroll
@@ -410,7 +409,7 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
   mx = fmaxf(mx, __shfl_xor(mx, 16));
   mx = fmaxf(mx, __shfl_xor(mx, 32));
   const int e = block_exponent((double)mx);
-  if (q == 0 && pin) E[(int64_t)blockIdx.y * P + p] = e;
+  if (q == 0 && pin) E[(int64_t)by * P + p] = e;
   bf8 o[3][2];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -427,17 +426,15 @@ __global__ __launch_bounds__(256) void k_sketch_split(const float* __restrict__ 
     }
 }
 
-// grid (ceil(I_n / 64), ceil(J / 64)): the weighted fibers w_j X(j, :) (FP32 product of the
-// FP32 weight and the panel entry) of one 64-sample block and 64 columns, gathered and split as
-// the sketch is: lane (li, q) of wave w holds samples 16 q .. 16 q + 15 of column 16 w + li
+// Tile (bx, by) of the weighted fibers w_j X(j, :) (FP32 product of the FP32 weight and the
+// panel entry): one 64-sample block and 64 columns, gathered and split as the sketch is: lane (li, q) of wave w holds samples 16 q .. 16 q + 15 of column 16 w + li
 // (the 16 lanes of one q read 64 contiguous bytes of a fiber), the column's exponent takes two
 // lane exchanges, and each lane stores 32 contiguous bytes per slice.  Samples past J have
 // weight 0 and row 0.
-__global__ __launch_bounds__(256) void k_fiber_split(NormalEqArgs a) {
+__device__ __forceinline__ void fiber_split_tile(const NormalEqArgs& a, int bx, int by) {
   __shared__ int64_t s_off[kSplitBlock];
   __shared__ float s_w[kSplitBlock];
-  if (*a.status != kDevOk) return;
-  const int64_t jb = (int64_t)blockIdx.y * kSplitBlock;
+  const int64_t jb = (int64_t)by * kSplitBlock;
   const int In = a.In;
   if (threadIdx.x < kSplitBlock) {
     const int64_t j = jb + threadIdx.x;
@@ -458,7 +455,7 @@ __global__ __launch_bounds__(256) void k_fiber_split(NormalEqArgs a) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, q = lane >> 4;
-  const int i = blockIdx.x * 64 + 16 * wave + li;
+  const int i = bx * 64 + 16 * wave + li;
   const bool in = i < In;
   const int ic = in ? i : In - 1;
   const float* X = (const float*)a.panel;
@@ -471,7 +468,7 @@ __global__ __launch_bounds__(256) void k_fiber_split(NormalEqArgs a) {
   mx = fmaxf(mx, __shfl_xor(mx, 16));
   mx = fmaxf(mx, __shfl_xor(mx, 32));
   const int e = block_exponent((double)mx);
-  if (q == 0 && in) a.ED[(int64_t)blockIdx.y * In + i] = e;
+  if (q == 0 && in) a.ED[(int64_t)by * In + i] = e;
   bf8 o[3][2];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -486,6 +483,20 @@ __global__ __launch_bounds__(256) void k_fiber_split(NormalEqArgs a) {
       dst[0] = o[sl][0];
       dst[1] = o[sl][1];
     }
+}
+
+// Both split passes of an update in one launch: workgroups [0, sk_tiles) take the sketch's
+// tiles (ceil(P / 64) per 64-sample block), the rest the fibers' (ceil(I_n / 64) per block).
+__global__ __launch_bounds__(256) void k_x3_split(NormalEqArgs a, int sk_tiles) {
+  if (*a.status != kDevOk) return;
+  const int b = blockIdx.x;
+  if (b < sk_tiles) {
+    const int cx = (a.P + 63) / 64;
+    sketch_split_tile((const float*)a.A, a.J, a.P, a.S3, a.ld, a.E, b % cx, b / cx);
+  } else {
+    const int cx = (a.In + 63) / 64, t = b - sk_tiles;
+    fiber_split_tile(a, t % cx, t / cx);
+  }
 }
 
 // Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
@@ -842,12 +853,14 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 3) {
-    if (!a.D3 || !a.ED || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
-    const dim3 sgrid((unsigned)((a.In + 63) / 64), (unsigned)((a.J + kSplitBlock - 1) / kSplitBlock));
+    if (!a.A || !a.S3 || !a.E || !a.D3 || !a.ED || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
+    const int64_t jb = (a.J + kSplitBlock - 1) / kSplitBlock;
+    const int64_t sk = (int64_t)((a.P + 63) / 64) * jb, fb = (int64_t)((a.In + 63) / 64) * jb;
+    if (sk + fb > 0x7fffffff) return hipErrorInvalidValue;
     if (e0)
-      hipExtLaunchKernelGGL(k_fiber_split, sgrid, dim3(256), 0, s, e0, nullptr, 0, a);
+      hipExtLaunchKernelGGL(k_x3_split, dim3((unsigned)(sk + fb)), dim3(256), 0, s, e0, nullptr, 0, a, (int)sk);
     else
-      k_fiber_split<<<sgrid, 256, 0, s>>>(a);
+      k_x3_split<<<(unsigned)(sk + fb), 256, 0, s>>>(a, (int)sk);
     switch (pl.mb) {
 #define TRALS_NE3_CASE(MB)                                                                  \
   case MB:                                                                                  \
@@ -890,13 +903,6 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_sketch_split(const float* A, int64_t J, int P, void* S3, int64_t ld, int* E, const int* status,
-                               hipStream_t s) {
-  if (J < 1 || P < 1 || ld % kSplitBlock || ld < J) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((P + 63) / 64), (unsigned)((J + kSplitBlock - 1) / kSplitBlock));
-  k_sketch_split<<<grid, 256, 0, s>>>(A, J, P, (__bf16*)S3, ld, E, status);
-  return hipGetLastError();
-}
 
 hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
                                hipStream_t s) {
