@@ -435,10 +435,10 @@ def main():
                 "frac": achieved / peak, "traffic": traffic["total"] if traffic else None,
                 "traffic_fetch_write": [traffic["fetch"], traffic["write"]] if traffic else None,
                 "algorithmic_flops": flops, "algorithmic_bytes": gbytes,
-                "kernel": ("k_fiber_split + k_normal_eq_x3 (fibers gathered, weighted and split into three "
-                           "8-bit slices once per update, then [A^T A | A^T X~] from the slices on BF16 matrix "
-                           "cores, eight slice products, FP64 block sums; timed from the first kernel's start "
-                           "to the second's end)") if three_slice else
+                "kernel": ("k_x3_split + k_normal_eq_x3 (the sketch rows and the gathered, weighted fibers "
+                           "split into three 8-bit slices once per update, then [A^T A | A^T X~] from the slices "
+                           "on BF16 matrix cores, eight slice products, FP64 block sums; timed from the first "
+                           "kernel's start to the second's end)") if three_slice else
                           "k_normal_eq (fiber gather + [A^T A | A^T X~] on FP64 matrix cores)",
                 "kernel_share_of_sweep": kern["contract"]["ms_per_sweep"] / res["ms_per_sweep"],
                 "gather_GBps": gbytes / avg_s / 1e9,
