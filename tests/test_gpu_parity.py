@@ -257,3 +257,17 @@ def test_fp32_three_slice_lockstep():
     t = TR(torch.tensor(X, device="cuda"), ranks, 1500, precision="f32", init_cores=init)
     worst = lockstep(t, X.astype(np.float64), 4, 1500)
     say(f"worst slice {worst:.3e}")
+
+
+def test_fp32_three_slice_few_samples():
+    # P = 110, 130, 143 (one above 128: the handle takes the three-slice path for every mode) with
+    # J = 300: the split pass and the contraction on five 64-sample blocks, the last holding 44
+    # samples, few splits per tile; I_n = 70, 5, 129 (ragged column tiles, a wide core)
+    say("case: fp32 70x5x129 R=(10,13,11) J=300 lockstep 3 updates (three-slice, few samples)")
+    dims, ranks = (70, 5, 129), (10, 13, 11)
+    X = ring_tensor(random_cores(dims, ranks, rng_for(71, 1)))
+    X = (X + 0.01 * np.linalg.norm(X) / np.sqrt(X.size) * rng_for(71, 2).standard_normal(dims)).astype(np.float32)
+    init = random_cores(dims, ranks, rng_for(71, 3))
+    t = TR(torch.tensor(X, device="cuda"), ranks, 300, precision="f32", init_cores=init)
+    worst = lockstep(t, X.astype(np.float64), 3, 300)
+    say(f"worst slice {worst:.3e}")
