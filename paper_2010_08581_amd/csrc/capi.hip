@@ -224,8 +224,9 @@ void plan(const Problem& p, Layout* L) {
     const size_t ld = (size_t)(p.J + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
     L->S3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Pmax * ld * 2 : 0);
     L->E3 = take(p.ne_dt == 3 ? (size_t)p.Pmax * (ld / kSplitBlock) * 4 : 0);
-    // the weighted fibers in the same form (the contraction's column operand)
-    L->D3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Imax * ld * 2 : 0);
+    // the weighted fibers in the same form (the contraction's column operand); for the BF16
+    // form the gathered raw BF16 fibers, one slice
+    L->D3 = take((p.ne_dt == 3 ? 3 : p.ne_dt == 2 ? 1 : 0) * (size_t)p.Imax * ld * 2);
     L->ED3 = take(p.ne_dt == 3 ? (size_t)p.Imax * (ld / kSplitBlock) * 4 : 0);
   }
   L->Hpart = take(hpart * 8);  // FP64 split-K partials
@@ -580,6 +581,7 @@ int run_update(trals_ctx* h) {
     na.D3 = h->at<void>(h->L.D3);
     na.ED = h->at<int>(h->L.ED3);
   }
+  if (p.ne_dt == 2) na.D3 = h->at<void>(h->L.D3);
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
   // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the
   // panel's rows: row r of the sketch pairs with fiber row r

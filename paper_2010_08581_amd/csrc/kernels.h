@@ -78,7 +78,8 @@ struct NormalEqArgs {
   // 64-sample block and column, slice s of column p at S3 + (s P + p) ld (ld samples per
   // column, a multiple of 64), with block exponents E[b P + p]; the weighted fibers w_j X(j, i)
   // in the same form, slice s of column i at D3 + (s I_n + i) ld, exponents ED[b I_n + i].
-  // launch_normal_eq writes all four (split pass) before the contraction reads them.
+  // launch_normal_eq writes all four (split pass) before the contraction reads them.  The BF16
+  // form uses D3 alone: the gathered raw BF16 fibers, I_n x ld.
   __bf16* S3;
   int* E;
   void* D3;
@@ -96,13 +97,14 @@ constexpr int kPlanCUs = 256;  // MI355X compute units (launch sizing)
 constexpr int kSketchPadRows = 64;
 // ne_dtype 0: FP64 sketch and panel (FP64 matrix cores); 1: FP32 sketch and panel, widened
 // exactly to FP64 and multiplied on the FP64 matrix cores (FP64 accumulation); 2: BF16 form
-// (two transposed BF16 sketches, BF16 panel, BF16 matrix cores with FP32 accumulation within
-// a split); 3: FP32 path on BF16 matrix cores with exact products: the FP32 sketch and the
-// weighted FP32 fibers in three 8-bit slices per 64-sample block and column (one exponent
-// each), slice products exact in FP32, block sums added in FP64.  For ne_dtype 3 the launch is
-// two kernels: the split pass (slices of the sketch into S3 / E and of the gathered weighted
-// fibers w_j X(j, :) into D3 / ED), then the contraction; e0 stamps the first one's start, e1
-// the second one's end.
+// (two transposed BF16 sketches A = bf16(w M), A2 = bf16(w^2 M), P x ld, BF16 panel, BF16
+// matrix cores with FP32 accumulation over each 64-sample block, FP64 across blocks); 3: FP32
+// path on BF16 matrix cores with exact products: the FP32 sketch and the weighted FP32 fibers
+// in three 8-bit slices per 64-sample block and column (one exponent each), slice products
+// exact in FP32, block sums added in FP64.  For ne_dtype 2 and 3 the launch is two kernels: the
+// gather pass (the raw BF16 fibers into D3, I_n x ld) or the split pass (slices of the sketch
+// into S3 / E and of the gathered weighted fibers w_j X(j, :) into D3 / ED), then the products;
+// e0 stamps the first one's start, e1 the second one's end.
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu);
 // e0/e1 (optional, for measurement): events stamped at the kernel's own start and end
 hipError_t launch_normal_eq(const NormalEqArgs& a, const NormalEqPlan& pl, int ne_dtype, hipStream_t s,

@@ -36,6 +36,7 @@ constexpr int kX3ColTile = 128;  // column tile of the three-slice kernel (eight
 constexpr int kKB = 32;          // sample rows per LDS stage (8 MFMA k-steps)
 constexpr int kMaxChunk = 1024;  // sample rows per split, padding included (row offsets and weights in LDS)
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kX1PerCU = 2;  // workgroups of the one-slice (BF16) products per CU (register bound)
 
 // LDS bytes of the FP64 / FP32 kernel: KG groups x double-buffered A and B stages.
 constexpr size_t ne_dyn_lds(int mb, int kg, int esz) {
@@ -213,135 +214,15 @@ __global__ __launch_bounds__(256 * KG) void k_normal_eq(NormalEqArgs a) {
   }
 }
 
-// BF16 form of the same products on v_mfma_f32_16x16x32_bf16.  The draw kernel writes the sketch
-// twice in BF16 and transposed (column c's samples contiguous): bf16(w_j M_j) for the Gram tiles
-// and bf16(w_j^2 M_j) for the data tiles, so that B = sum_j w_j^2 M_j^T x_j meets the raw BF16
-// panel rows (x~_j = w_j x_j, Definition 5) unmodified.  Products are accumulated in FP32 within
-// a split and the partial tiles written in FP64.  Each lane feeds the matrix cores 8 consecutive
-// samples of one operand row: a 16-byte load from a transposed sketch, or, for the data side, 8
-// gathered 2-byte panel entries (16 lanes read 32 contiguous bytes of each fiber).  No operand
-// passes through LDS.
+// BF16 form of the same products (k_normal_eq_x3 with one slice).  The draw kernel writes the
+// sketch twice in BF16 and transposed (column c's samples contiguous): bf16(w_j M_j) for the Gram
+// tiles and bf16(w_j^2 M_j) for the data tiles, so that B = sum_j w_j^2 M_j^T x_j meets the raw
+// BF16 panel rows (x~_j = w_j x_j, Definition 5) unmodified; a gather pass (k_x1_gather) writes
+// the sampled fibers transposed beside them.  Products are accumulated in FP32 over each
+// 64-sample block and the block sums added in FP64.
 //   v_mfma_f32_16x16x32_bf16 layouts: A(i, k) at lane i + 16 (k / 8), element k % 8;
 //   B(k, j) at lane j + 16 (k / 8), element k % 8; D(i, j) at lane j + 16 (i / 4), register i % 4.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-constexpr int kKB16 = 64;  // sample rows per split quantum (two MFMA k-steps of 32)
-
-template <int MB>
-__global__ __launch_bounds__(256) void k_normal_eq_bf16(NormalEqArgs a) {
-  constexpr int RT = 16 * MB;
-  __shared__ int64_t s_roff[kMaxChunk];
-  if (*a.status != kDevOk) return;
-  const int P = a.P, In = a.In;
-  const int lb = xcd_linear_block(blockIdx.x, gridDim.x);  // a split's tiles share an XCD
-  const int s = lb / a.tiles, t = lb - s * a.tiles;
-  // row tiles vary fastest: the row tiles of one column tile (which gather the same fibers) run
-  // side by side on one XCD and share them through its L2
-  const int row_tiles = a.tiles / a.col_tiles;
-  const int rt = t % row_tiles, ct = t / row_tiles;
-  const int row0 = rt * RT;
-  const bool gram = ct < a.gram_tiles;
-  const int col0 = gram ? ct * kColTile : (ct - a.gram_tiles) * kColTile;
-  if (gram && col0 >= row0 + RT) return;
-  const int64_t r0 = (int64_t)s * a.chunk;  // a multiple of kKB16
-  const int64_t r1 = r0 + a.chunk < a.J ? r0 + a.chunk : a.J;
-  const int nrows = (int)(r1 - r0);
-  const int npad = (nrows + kKB16 - 1) / kKB16 * kKB16;  // r0 + npad <= ld
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
-  const int li = lane & 15, lg = lane >> 4;
-  const int64_t ld = a.ld;
-  const __bf16* X = (const __bf16*)a.panel;
-  if (!gram) {
-    for (int r = threadIdx.x; r < npad; r += 256) {
-      int64_t off = 0;  // rows past the split read fiber row 0 (their sketch factor is zero)
-      if (r < nrows) {
-        if (a.direct) {
-          off = r0 + r;
-        } else {
-          const int32_t* ij = a.idx + (r0 + r) * a.K;
-          for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
-        }
-      }
-      s_roff[r] = off * In;
-    }
-    __syncthreads();
-  }
-  // operand rows of this lane (clamped: rows and columns past P or I_n are computed, not stored)
-  const __bf16* SA = (const __bf16*)(gram ? a.A : a.A2) + r0;
-  const __bf16* arow[MB];
-#pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int rr = row0 + 16 * m + li;
-    arow[m] = SA + (int64_t)(rr < P ? rr : P - 1) * ld;
-  }
-  const int bc = col0 + 16 * wave + li;
-  const __bf16* brow = (const __bf16*)a.A + r0 + (int64_t)(bc < P ? bc : P - 1) * ld;  // Gram side
-  const int bcol = bc < In ? bc : In - 1;                                                // data side
-  f4 acc[MB];
-#pragma unroll
-  for (int m = 0; m < MB; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
-  // one k-step = 32 samples; the operands of later steps are loaded while the matrix cores work
-  // on the current one
-  auto load = [&](int base, bf8(&av)[MB], bf8& bv) {
-    const int k0 = base + 8 * lg;  // this lane's 8 samples
-#pragma unroll
-    for (int m = 0; m < MB; ++m) av[m] = *(const bf8*)(arow[m] + k0);
-    if (gram) {
-      bv = *(const bf8*)(brow + k0);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) bv[e] = X[s_roff[k0 + e] + bcol];
-    }
-  };
-  auto step = [&](int base, bf8(&av)[MB], const bf8& bv) {
-    if (base + 32 > nrows) {
-      // samples past the split: their sketch entries may hold an earlier, longer update's rows
-      const int k0 = base + 8 * lg;
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (k0 + e >= nrows)
-#pragma unroll
-          for (int m = 0; m < MB; ++m) av[m][e] = (__bf16)0.f;
-    }
-#pragma unroll
-    for (int m = 0; m < MB; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m], 0, 0, 0);
-  };
-  // kRing k-steps in flight: step k uses buffer k % kRing, which is then reloaded with step
-  // k + kRing (the loop runs kRing steps per iteration so that the buffers keep static indices)
-  constexpr int kRing = 4;
-  bf8 av[kRing][MB], bv[kRing];
-#pragma unroll
-  for (int d = 0; d < kRing; ++d)
-    if (32 * d < npad) load(32 * d, av[d], bv[d]);
-  for (int base = 0; base < npad; base += 32 * kRing) {
-#pragma unroll
-    for (int d = 0; d < kRing; ++d) {
-      const int kb = base + 32 * d;
-      if (kb < npad) step(kb, av[d], bv[d]);
-      if (kb + 32 * kRing < npad) load(kb + 32 * kRing, av[d], bv[d]);
-    }
-  }
-  const int col = col0 + wave * 16 + li;
-  if (gram) {
-    double* H = a.Hpart + (int64_t)s * P * P;
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * lg + r;
-        if (row < P && col < P && col <= row) H[(int64_t)row * P + col] = (double)acc[m][r];
-      }
-  } else {
-    double* B = a.Bpart + (int64_t)s * P * In;
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + m * 16 + 4 * lg + r;
-        if (row < P && col < In) B[(int64_t)row * In + col] = (double)acc[m][r];
-      }
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 // FP32 path on BF16 matrix cores with products exact to 2^-34 of the block maxima (ne_dtype 3).
@@ -499,6 +380,62 @@ __global__ __launch_bounds__(256) void k_x3_split(NormalEqArgs a, int sk_tiles) 
   }
 }
 
+// The BF16 form's gather pass: workgroups [0, fb_tiles) gather the raw BF16 fibers of one
+// 64-sample block and 64 columns into D3 (I_n x ld, samples contiguous per column; zero past J),
+// lane (li, q) of wave w taking samples 16 q .. 16 q + 15 of column 16 w + li; the last
+// workgroup zeroes the sketches' columns J .. ld - 1 (row p of bf16(w M) and bf16(w^2 M) at
+// p ld), which the draws do not write.
+__global__ __launch_bounds__(256) void k_x1_gather(NormalEqArgs a, int fb_tiles) {
+  __shared__ int64_t s_off[kSplitBlock];
+  if (*a.status != kDevOk) return;
+  const int In = a.In;
+  if ((int)blockIdx.x == fb_tiles) {
+    const int pad = (int)(a.ld - a.J);
+    __bf16* A = (__bf16*)a.A;
+    __bf16* A2 = (__bf16*)a.A2;
+    for (int e = threadIdx.x; e < a.P * pad; e += 256) {
+      const int p = e / pad;
+      const int64_t j = a.J + (e - p * pad);
+      A[(int64_t)p * a.ld + j] = (__bf16)0.f;
+      A2[(int64_t)p * a.ld + j] = (__bf16)0.f;
+    }
+    return;
+  }
+  const int cx = (In + 63) / 64;
+  const int bx = (int)blockIdx.x % cx, by = (int)blockIdx.x / cx;
+  const int64_t jb = (int64_t)by * kSplitBlock;
+  if (threadIdx.x < kSplitBlock) {
+    const int64_t j = jb + threadIdx.x;
+    int64_t off = -1;
+    if (j < a.J) {
+      off = 0;
+      if (a.direct) {
+        off = j;
+      } else {
+        const int32_t* ij = a.idx + j * a.K;
+        for (int k = 0; k < a.K; ++k) off += (int64_t)ij[k] * a.stride[k];
+      }
+      off *= In;
+    }
+    s_off[threadIdx.x] = off;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, q = lane >> 4;
+  const int i = bx * 64 + 16 * wave + li;
+  if (i >= In) return;
+  const __bf16* X = (const __bf16*)a.panel;
+  bf8 o[2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t off = s_off[16 * q + r];
+    o[r >> 3][r & 7] = off >= 0 ? X[off + i] : (__bf16)0.f;
+  }
+  bf8* dst = (bf8*)((__bf16*)a.D3 + (int64_t)i * a.ld + jb + 16 * q);
+  dst[0] = o[0];
+  dst[1] = o[1];
+}
+
 // Workgroup of 8 waves on a (16 MB) x 128 tile: wave c owns tile columns 16c .. 16c + 15, all
 // MB row blocks and both 32-sample halves (matrix-core k-steps) of every 64-sample block, so
 // that its level sums cover 64 samples between FP64 flushes (each stays below 2^23 in
@@ -517,13 +454,18 @@ constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 
 constexpr int kX3Levels = 4;
 
 // One tile of k_normal_eq_x3; GRAM selects the column operand (sketch or fiber slices) and the
-// output (H or B partials).
-template <int MB, bool GRAM>
+// output (H or B partials).  NS = 3: the FP32 path's slices (S3 / D3, block exponents); NS = 1:
+// the BF16 form, whose operands are BF16 values already (row operand bf16(w M) for Gram tiles,
+// bf16(w^2 M) for data tiles, P x ld; column operand bf16(w M) or the gathered raw fibers D3,
+// I_n x ld), one product per k-step, no exponents.
+template <int MB, bool GRAM, int NS>
 __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, int col0, int (*s_ea)[16 * MB],
                                         unsigned char* smem) {
+  static_assert(NS == 1 || NS == 3, "three slices (FP32 path) or one (BF16 form)");
+  constexpr int NL = NS == 3 ? kX3Levels : 1;           // level sums per output
   constexpr int RT = 16 * MB;
-  constexpr int kBufElems = 3 * RT * kX3Ld;            // one buffer of staged sketch slices
-  constexpr int kChunks = 3 * RT * (kSplitBlock / 8);  // 16-byte pieces of a buffer
+  constexpr int kBufElems = NS * RT * kX3Ld;            // one buffer of staged row operands
+  constexpr int kChunks = NS * RT * (kSplitBlock / 8);  // 16-byte pieces of a buffer
   constexpr int kCPT = (kChunks + 511) / 512;          // per thread
   const int P = a.P, In = a.In;
   const int64_t r0 = (int64_t)s * a.chunk;  // a multiple of kSplitBlock
@@ -533,8 +475,8 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int li = lane & 15, lg = lane >> 4;
-  __bf16* Ab = (__bf16*)smem;  // [2][3][RT][kX3Ld]
-  const __bf16* S3 = (const __bf16*)a.S3;
+  __bf16* Ab = (__bf16*)smem;  // [2][NS][RT][kX3Ld]
+  const __bf16* S3 = NS == 3 ? (const __bf16*)a.S3 : GRAM ? (const __bf16*)a.A : (const __bf16*)a.A2;
   const int64_t ld = a.ld, sstride = (int64_t)P * ld;
   const int64_t eb0 = r0 / kSplitBlock;
   // staging of the sketch rows: piece q = (slice, row, 8-sample group)
@@ -550,7 +492,7 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
       const int pr = row0 + r < P ? row0 + r : P - 1;
       stg[u] = *(const bf8*)(S3 + sl * sstride + (int64_t)pr * ld + base + 8 * c8);
     }
-    if (tid < RT) stg_ea = a.E[(eb0 + b) * P + (row0 + tid < P ? row0 + tid : P - 1)];
+    if (NS == 3 && tid < RT) stg_ea = a.E[(eb0 + b) * P + (row0 + tid < P ? row0 + tid : P - 1)];
   };
   auto store_a = [&](int buf) {
     __bf16* dst = Ab + buf * kBufElems;
@@ -562,33 +504,33 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
         *(bf8*)(dst + (sl * RT + r) * kX3Ld + 8 * c8) = stg[u];
       }
     }
-    if (tid < RT) s_ea[buf][tid] = stg_ea;
+    if (NS == 3 && tid < RT) s_ea[buf][tid] = stg_ea;
   };
   // column operand of this wave: sketch column (Gram tiles) or fiber column (data tiles) bcc
   const int bc = col0 + 16 * wave + li;
   const int ncols = GRAM ? P : In;
   const int bcc = bc < ncols ? bc : ncols - 1;
   const __bf16* C3 = GRAM ? S3 : (const __bf16*)a.D3;
-  const int* CE = GRAM ? a.E : a.ED;
+  const int* CE = GRAM ? a.E : a.ED;  // (NS = 3)
   const int64_t cstride = (int64_t)ncols * ld;
   const __bf16* brow = C3 + (int64_t)bcc * ld + r0;
-  bf8 nb3[2][3];  // next block's column slices, both halves
+  bf8 nb3[2][NS];  // next block's column slices, both halves
   int ncol_e = 0;
   auto load_b = [&](int b) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int k0 = b * kSplitBlock + 32 * h + 8 * lg;  // this lane's 8 samples of half h
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) nb3[h][sl] = *(const bf8*)(brow + sl * cstride + k0);
+      for (int sl = 0; sl < NS; ++sl) nb3[h][sl] = *(const bf8*)(brow + sl * cstride + k0);
     }
-    ncol_e = CE[(eb0 + b) * ncols + bcc];
+    if (NS == 3) ncol_e = CE[(eb0 + b) * ncols + bcc];
   };
-  f4 acc[MB][kX3Levels];
+  f4 acc[MB][NL];
   double out[MB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
 #pragma unroll
-    for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int l = 0; l < NL; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[m][q] = 0.0;
   }
@@ -599,11 +541,11 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   for (int b = 0; b < nblk; ++b) {
     const int buf = b & 1;
     const bool more = b + 1 < nblk;
-    bf8 cb[2][3];
+    bf8 cb[2][NS];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int sl = 0; sl < 3; ++sl) cb[h][sl] = nb3[h][sl];
+      for (int sl = 0; sl < NS; ++sl) cb[h][sl] = nb3[h][sl];
     const int fcol = ncol_e;
     if (more) {
       load_a(b + 1);
@@ -614,32 +556,37 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
     for (int m = 0; m < MB; ++m) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        bf8 av[3];
+        bf8 av[NS];
 #pragma unroll
-        for (int sl = 0; sl < 3; ++sl)
+        for (int sl = 0; sl < NS; ++sl)
           av[sl] = *(const bf8*)(As + (sl * RT + 16 * m + li) * kX3Ld + 32 * h + 8 * lg);
 #pragma unroll
-        for (int si = 0; si < 3; ++si)
+        for (int si = 0; si < NS; ++si)
 #pragma unroll
-          for (int ti = 0; ti < 3; ++ti)
-            if (si + ti < kX3Levels)
+          for (int ti = 0; ti < NS; ++ti)
+            if (si + ti < NL)
               acc[m][si + ti] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[si], cb[h][ti], acc[m][si + ti], 0, 0, 0);
       }
     }
-    // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16)
+    // block sums into FP64: sum_l acc_l 2^(-8 l), times 2^(e_row + e_col - 16) (NS = 3); the
+    // BF16 form's FP32 block sums as they are
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        double v = (double)acc[m][kX3Levels - 1][q];
+        if (NS == 3) {
+          double v = (double)acc[m][NL - 1][q];
 #pragma unroll
-        for (int l = kX3Levels - 2; l >= 0; --l) v = fma(v, 0.00390625, (double)acc[m][l][q]);
-        out[m][q] += ldexp(v, s_ea[buf][16 * m + 4 * lg + q] + fcol - 16);
+          for (int l = NL - 2; l >= 0; --l) v = fma(v, 0.00390625, (double)acc[m][l][q]);
+          out[m][q] += ldexp(v, s_ea[buf][16 * m + 4 * lg + q] + fcol - 16);
+        } else {
+          out[m][q] += (double)acc[m][0][q];
+        }
       }
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
-      for (int l = 0; l < kX3Levels; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int l = 0; l < NL; ++l) acc[m][l] = f4{0.f, 0.f, 0.f, 0.f};
     if (more) store_a(buf ^ 1);
     __syncthreads();
   }
@@ -665,7 +612,7 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   }
 }
 
-template <int MB>
+template <int MB, int NS>
 __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
   constexpr int RT = 16 * MB;
   extern __shared__ __align__(16) unsigned char x3_smem[];
@@ -684,13 +631,13 @@ __global__ __launch_bounds__(512) void k_normal_eq_x3(NormalEqArgs a) {
     const int first = (c * kX3ColTile) / RT < row_tiles ? (c * kX3ColTile) / RT : row_tiles;
     const int n = row_tiles - first;
     if (t < n) {
-      x3_tile<MB, true>(a, s, (first + t) * RT, c * kX3ColTile, s_ea, x3_smem);
+      x3_tile<MB, true, NS>(a, s, (first + t) * RT, c * kX3ColTile, s_ea, x3_smem);
       return;
     }
     t -= n;
   }
   const int rt = t % row_tiles, ct = t / row_tiles;
-  x3_tile<MB, false>(a, s, rt * RT, ct * kX3ColTile, s_ea, x3_smem);
+  x3_tile<MB, false, NS>(a, s, rt * RT, ct * kX3ColTile, s_ea, x3_smem);
 }
 
 // Tiles one split of the three-slice kernel computes: every data tile and the Gram tiles on or
@@ -705,8 +652,8 @@ int x3_live_tiles(const NormalEqPlan& pl) {
   return n;
 }
 
-size_t x3_dyn_lds(int mb) {
-  return (size_t)2 * 3 * 16 * mb * kX3Ld * 2;  // two buffers of sketch slices
+size_t x3_dyn_lds(int mb, int ns) {
+  return (size_t)2 * ns * 16 * mb * kX3Ld * 2;  // two buffers of staged row operands
 }
 
 // Two reductions in one launch: blocks [0, nb0) take job 0, the rest job 1.
@@ -746,20 +693,20 @@ hipError_t dispatch(const NormalEqArgs& a, int mb, unsigned grid, hipStream_t s,
 
 }  // namespace
 
-// Splits of the three-slice kernel.  Its workgroups hold a CU each for the whole split (one per
-// CU), so a launch takes ceil(workgroups on an XCD / CUs per XCD) rounds, each as long as one
+// Splits of the slice-operand kernel.  Its workgroups hold a CU (per_cu of them) for the whole
+// split, so a launch takes ceil(workgroups on an XCD / their slots per XCD) rounds, each as long as one
 // split's 64-sample blocks; every split adds its FP64 partials of H and B, written once and read
 // once by the reduction.  The split count minimises
 //     rounds * (blocks per split + 1) + splits * partial bytes / 12 MB
 // (12 MB: what the reduction moves in about the time of one block; the 1 a workgroup's prologue
 // and epilogue), ties to fewer splits.
-static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu) {
+static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu, int per_cu) {
   const int live = x3_live_tiles(pl);
   const int P = 16 * pl.mb * pl.row_tiles;  // bound on the partial rows, padding included
   const double part_blocks = 16.0 * ((double)P * (P + 1) / 2 + (double)P * 128 * pl.data_tiles) / 12e6;
-  const int per_xcd = num_cu / kXcds > 0 ? num_cu / kXcds : 1;
+  const int per_xcd = per_cu * (num_cu / kXcds > 0 ? num_cu / kXcds : 1);
   const int64_t s_lo = 1;
-  int64_t s_hi = 4 * (int64_t)num_cu / live + 2;
+  int64_t s_hi = 4 * (int64_t)per_cu * num_cu / live + 2;
   if (s_hi > (J + kSplitBlock - 1) / kSplitBlock) s_hi = (J + kSplitBlock - 1) / kSplitBlock;
   if (s_hi < s_lo) s_hi = s_lo;
   double best = 1e300;
@@ -786,7 +733,8 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   // The three-slice kernel holds its accumulators without spilling up to mb = 4: one tile when
   // P <= 64, else the mb in [3, 4] with the fewest row tiles (each gathers the fibers again),
   // then the least padding.
-  const int mb_max = ne_dtype == 3 ? 4 : 8, mb_min = ne_dtype == 3 ? 3 : 4;
+  const bool x3 = ne_dtype == 2 || ne_dtype == 3;  // the slice-operand products (k_normal_eq_x3)
+  const int mb_max = x3 ? 4 : 8, mb_min = x3 ? 3 : 4;
   if (P <= 16 * mb_max) {
     pl.mb = (P + 15) / 16;
   } else {
@@ -795,8 +743,7 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
       const int rt = 16 * mb;
       const int tiles = (P + rt - 1) / rt;
       const int pad = tiles * rt - P;
-      const bool better = ne_dtype == 3 ? (tiles < best_tiles || (tiles == best_tiles && pad < best_pad))
-                                        : pad < best_pad;
+      const bool better = x3 ? (tiles < best_tiles || (tiles == best_tiles && pad < best_pad)) : pad < best_pad;
       if (better) {
         best_pad = pad;
         best_tiles = tiles;
@@ -806,25 +753,19 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
     pl.mb = best;
   }
   pl.row_tiles = (P + 16 * pl.mb - 1) / (16 * pl.mb);
-  const int ctile = ne_dtype == 3 ? kX3ColTile : kColTile;
+  const int ctile = x3 ? kX3ColTile : kColTile;
   pl.gram_tiles = (P + ctile - 1) / ctile;
   pl.data_tiles = (In + ctile - 1) / ctile;
-  if (ne_dtype == 3) return plan_x3_splits(pl, J, num_cu);
+  if (x3) return plan_x3_splits(pl, J, num_cu, ne_dtype == 2 ? kX1PerCU : 1);
   const int64_t tiles = (int64_t)pl.row_tiles * (pl.gram_tiles + pl.data_tiles);
   // workgroups resident per CU (LDS-bound) and the rows one split must be a multiple of
-  int per_cu, quantum;
-  if (ne_dtype == 2) {
-    per_cu = 2;  // register bound (196 of 512 registers per lane: two waves per SIMD)
-    quantum = kKB16;
-  } else {
-    const int kg = ne_dtype == 1 ? 2 : 1;
-    const int esz = ne_dtype == 1 ? 4 : 8;
-    const size_t lds = ne_dyn_lds(pl.mb, kg, esz) + (size_t)kMaxChunk * 16;
-    per_cu = (int)(kLdsBytes / lds);
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 2) per_cu = 2;
-    quantum = kg * kKB;
-  }
+  const int kg = ne_dtype == 1 ? 2 : 1;
+  const int esz = ne_dtype == 1 ? 4 : 8;
+  const size_t lds = ne_dyn_lds(pl.mb, kg, esz) + (size_t)kMaxChunk * 16;
+  int per_cu = (int)(kLdsBytes / lds);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 2) per_cu = 2;
+  const int quantum = kg * kKB;
   // one round of workgroups over the chip: splits = resident slots / tiles, at least one
   // quantum of rows per split and at most kMaxChunk rows with the padding of the last round
   int64_t S = ((int64_t)per_cu * num_cu) / tiles;
@@ -833,9 +774,7 @@ NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) 
   if (S < 1) S = 1;
   const int64_t maxchunk = kMaxChunk - quantum;
   if ((J + S - 1) / S > maxchunk) S = (J + maxchunk - 1) / maxchunk;
-  int64_t chunk = (J + S - 1) / S;
-  // the BF16 form reads its transposed sketch in 16-byte groups: splits start on a quantum
-  if (ne_dtype == 2) chunk = (chunk + quantum - 1) / quantum * quantum;
+  const int64_t chunk = (J + S - 1) / S;
   pl.chunk = chunk;
   pl.splits = (int)((J + chunk - 1) / chunk);
   return pl;
@@ -846,56 +785,50 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
   NormalEqArgs a = args;
   a.col_tiles = pl.gram_tiles + pl.data_tiles;
   a.row_tiles = pl.row_tiles;
-  a.tiles = ne_dtype == 3 ? x3_live_tiles(pl) : pl.row_tiles * a.col_tiles;
+  a.tiles = ne_dtype >= 2 ? x3_live_tiles(pl) : pl.row_tiles * a.col_tiles;
   a.splits = pl.splits;
   if ((int64_t)pl.splits * a.tiles > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(pl.splits * a.tiles);
   if (ne_dtype == 0) return dispatch<double, 1>(a, pl.mb, grid, s, e0, e1);
   if (ne_dtype == 1) return dispatch<float, 2>(a, pl.mb, grid, s, e0, e1);
-  if (ne_dtype == 3) {
-    if (!a.A || !a.S3 || !a.E || !a.D3 || !a.ED || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
+  if (ne_dtype == 2 || ne_dtype == 3) {
+    const int ns = ne_dtype == 3 ? 3 : 1;
+    if (!a.A || !a.D3 || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
+    if (ns == 3 && (!a.S3 || !a.E || !a.ED)) return hipErrorInvalidValue;
+    if (ns == 1 && !a.A2) return hipErrorInvalidValue;
     const int64_t jb = (a.J + kSplitBlock - 1) / kSplitBlock;
-    const int64_t sk = (int64_t)((a.P + 63) / 64) * jb, fb = (int64_t)((a.In + 63) / 64) * jb;
-    if (sk + fb > 0x7fffffff) return hipErrorInvalidValue;
-    if (e0)
-      hipExtLaunchKernelGGL(k_x3_split, dim3((unsigned)(sk + fb)), dim3(256), 0, s, e0, nullptr, 0, a, (int)sk);
-    else
-      k_x3_split<<<(unsigned)(sk + fb), 256, 0, s>>>(a, (int)sk);
-    switch (pl.mb) {
-#define TRALS_NE3_CASE(MB)                                                                  \
-  case MB:                                                                                  \
-    if (e1)                                                                                 \
-      hipExtLaunchKernelGGL((k_normal_eq_x3<MB>), dim3(grid), dim3(512), x3_dyn_lds(MB), s, nullptr, e1, 0, a); \
-    else                                                                                    \
-      k_normal_eq_x3<MB><<<grid, 512, x3_dyn_lds(MB), s>>>(a);                              \
-    break;
-      TRALS_NE3_CASE(1)
-      TRALS_NE3_CASE(2)
-      TRALS_NE3_CASE(3)
-      TRALS_NE3_CASE(4)
-#undef TRALS_NE3_CASE
-      default: return hipErrorInvalidValue;
+    const int64_t sk = ns == 3 ? (int64_t)((a.P + 63) / 64) * jb : 0, fb = (int64_t)((a.In + 63) / 64) * jb;
+    if (sk + fb + 1 > 0x7fffffff) return hipErrorInvalidValue;
+    // the split pass (FP32 path) or the gather pass (BF16 form), then the products
+    if (ns == 3) {
+      if (e0)
+        hipExtLaunchKernelGGL(k_x3_split, dim3((unsigned)(sk + fb)), dim3(256), 0, s, e0, nullptr, 0, a, (int)sk);
+      else
+        k_x3_split<<<(unsigned)(sk + fb), 256, 0, s>>>(a, (int)sk);
+    } else {
+      if (e0)
+        hipExtLaunchKernelGGL(k_x1_gather, dim3((unsigned)(fb + 1)), dim3(256), 0, s, e0, nullptr, 0, a, (int)fb);
+      else
+        k_x1_gather<<<(unsigned)(fb + 1), 256, 0, s>>>(a, (int)fb);
     }
-    return hipGetLastError();
-  }
-  if (ne_dtype == 2) {
-    switch (pl.mb) {
-#define TRALS_NE16_CASE(MB)                                                                  \
-  case MB:                                                                                   \
-    if (e0)                                                                                  \
-      hipExtLaunchKernelGGL((k_normal_eq_bf16<MB>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a); \
-    else                                                                                     \
-      k_normal_eq_bf16<MB><<<grid, 256, 0, s>>>(a);                                          \
+    switch (pl.mb * 4 + ns) {
+#define TRALS_NE3_CASE(MB, NS)                                                                     \
+  case MB * 4 + NS:                                                                                \
+    if (e1)                                                                                        \
+      hipExtLaunchKernelGGL((k_normal_eq_x3<MB, NS>), dim3(grid), dim3(512), x3_dyn_lds(MB, NS), s, nullptr, e1, \
+                            0, a);                                                                 \
+    else                                                                                           \
+      k_normal_eq_x3<MB, NS><<<grid, 512, x3_dyn_lds(MB, NS), s>>>(a);                             \
     break;
-      TRALS_NE16_CASE(1)
-      TRALS_NE16_CASE(2)
-      TRALS_NE16_CASE(3)
-      TRALS_NE16_CASE(4)
-      TRALS_NE16_CASE(5)
-      TRALS_NE16_CASE(6)
-      TRALS_NE16_CASE(7)
-      TRALS_NE16_CASE(8)
-#undef TRALS_NE16_CASE
+      TRALS_NE3_CASE(1, 3)
+      TRALS_NE3_CASE(2, 3)
+      TRALS_NE3_CASE(3, 3)
+      TRALS_NE3_CASE(4, 3)
+      TRALS_NE3_CASE(1, 1)
+      TRALS_NE3_CASE(2, 1)
+      TRALS_NE3_CASE(3, 1)
+      TRALS_NE3_CASE(4, 1)
+#undef TRALS_NE3_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
