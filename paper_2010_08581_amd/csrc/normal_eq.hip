@@ -239,8 +239,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 //
 // The sketch side has one representation (sketch_split_tile), used both as the row operand
 // and, in the Gram tiles, as the column operand: H is exactly R(A)^T R(A).  The data side is the
-// weighted fiber w_j X(j, i), split in the kernel with the block maximum of its column (the 64
-// samples of a column sit in four lanes: a max over the lane's 16 values and two exchanges).  So
+// weighted fiber w_j X(j, i), split the same way by the split pass (fiber_split_tile) with the
+// block maximum of its column.  So
 // B = R(A)^T R(diag(w) X) up to the dropped levels: both products are those of one slightly
 // perturbed problem, whose solution moves by cond(A) times the perturbation, as with FP32
 // storage alone.
@@ -308,10 +308,10 @@ __device__ __forceinline__ void sketch_split_tile(const float* __restrict__ A, i
 }
 
 // Tile (bx, by) of the weighted fibers w_j X(j, :) (FP32 product of the FP32 weight and the
-// panel entry): one 64-sample block and 64 columns, gathered and split as the sketch is: lane (li, q) of wave w holds samples 16 q .. 16 q + 15 of column 16 w + li
-// (the 16 lanes of one q read 64 contiguous bytes of a fiber), the column's exponent takes two
-// lane exchanges, and each lane stores 32 contiguous bytes per slice.  Samples past J have
-// weight 0 and row 0.
+// panel entry): one 64-sample block and 64 columns, gathered and split as the sketch is.  Lane
+// (li, q) of wave w holds samples 16 q .. 16 q + 15 of column 16 w + li (the 16 lanes of one q
+// read 64 contiguous bytes of a fiber), the column's exponent takes two lane exchanges, and each
+// lane stores 32 contiguous bytes per slice.  Samples past J have weight 0 and row 0.
 __device__ __forceinline__ void fiber_split_tile(const NormalEqArgs& a, int bx, int by) {
   __shared__ int64_t s_off[kSplitBlock];
   __shared__ float s_w[kSplitBlock];
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_x1_gather(NormalEqArgs a, int fb_tiles)
 // magnitude, exact in FP32).  The sketch rows of the tile (three slices, both halves) are staged
 // in LDS by the whole workgroup, double-buffered with one barrier per block; each wave loads the
 // column operand of its own columns directly into the matrix-core registers, one block ahead:
-// Gram tiles read the sketch slices, data tiles the fiber slices (k_fiber_split).
+// Gram tiles read the sketch slices, data tiles the fiber slices (both written by k_x3_split).
 constexpr int kX3Ld = 72;  // LDS row stride of a staged slice (64 samples + 8: 16-byte reads
                            // of 16 rows fall on distinct banks)
 // Slice products kept: level l = si + ti of s_si t_ti weighs 2^(-8 l) against the leading
@@ -730,9 +730,9 @@ static NormalEqPlan plan_x3_splits(NormalEqPlan pl, int64_t J, int num_cu, int p
 NormalEqPlan plan_normal_eq(int P, int In, int64_t J, int ne_dtype, int num_cu) {
   NormalEqPlan pl;
   // row tile of 16 * mb rows: one tile when P <= 128, else the mb in [4, 8] with least padding.
-  // The three-slice kernel holds its accumulators without spilling up to mb = 4: one tile when
-  // P <= 64, else the mb in [3, 4] with the fewest row tiles (each gathers the fibers again),
-  // then the least padding.
+  // The slice-operand kernel (FP32 three-slice path, BF16 form) holds its accumulators without
+  // spilling up to mb = 4: one tile when P <= 64, else the mb in [3, 4] with the fewest row
+  // tiles (each reads the column operand again), then the least padding.
   const bool x3 = ne_dtype == 2 || ne_dtype == 3;  // the slice-operand products (k_normal_eq_x3)
   const int mb_max = x3 ? 4 : 8, mb_min = x3 ? 3 : 4;
   if (P <= 16 * mb_max) {
