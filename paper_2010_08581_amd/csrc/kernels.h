@@ -67,8 +67,8 @@ struct NormalEqArgs {
   int64_t J;
   int64_t chunk;              // sample rows per split
   int P, In;
-  int gram_tiles;             // column tiles of the Gram part (64 wide; 128, three-slice form)
-  int col_tiles, tiles, splits;  // filled in by launch_normal_eq (three-slice form: tiles = the
+  int gram_tiles;             // column tiles of the Gram part (64 wide; 128, ne_dtype 2 and 3)
+  int col_tiles, tiles, splits;  // filled in by launch_normal_eq (ne_dtype 2 and 3: tiles = the
   int row_tiles;                 // tiles a split computes, strictly upper Gram tiles left out)
   double* Hpart;              // splits x P x P (lower triangle written)
   double* Bpart;              // splits x P x I_n
