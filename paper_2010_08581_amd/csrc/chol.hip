@@ -1238,7 +1238,7 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
     // with the panel wave), sixteen above
     const bool small = nblk <= 4;
     if (beside && beside->count > 0) {
-      const int64_t nred = reduce_blocks(*beside, args.P);
+      const int64_t nred = reduce_blocks(*beside, args.P, nparts);
       if (small)
         k_chol_reduce<8><<<(unsigned)(1 + (nred + 1) / 2), 512, lds, s>>>(args, *beside, nparts);
       else

@@ -839,7 +839,7 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
 
 hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int nparts, int P, const int* status,
                                hipStream_t s) {
-  const int64_t na = reduce_blocks(a, P), nb = reduce_blocks(b, P);
+  const int64_t na = reduce_blocks(a, P, nparts), nb = reduce_blocks(b, P, nparts);
   if (na + nb == 0) return hipSuccess;
   k_reduce_parts<<<(unsigned)(na + nb), 256, 0, s>>>(a, b, na, nparts, P, status);
   return hipGetLastError();

@@ -6,25 +6,32 @@
 
 namespace trals {
 
-constexpr int kRedElems = 64;  // elements per 256-thread reduction block
+constexpr int kRedElems = 64;  // elements per set (a 256-thread block takes one set, or four)
 
-// Elements [64 blk, 64 blk + 64) of job jb, by the 256 threads t = 0..255 of one reduction
-// block (red: its own 4 x 64 doubles of LDS; every thread of the workgroup must reach this
-// call, it holds a barrier).  out = sum over s of parts[s * count + e], in a fixed order: four
-// threads per element sum the partials s = g, g + 4, ... (g = 0..3) and the four sums are added
-// in the order g = 0, 1, 2, 3.  mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from
-// its lower triangle, out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n
-// partials are written transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P);
-// there block blk is the 8 x 8 tile (p, i) in [8 tp, 8 tp + 8) x [8 ti, 8 ti + 8), read as 8
-// runs of 8 consecutive i and written as 8 runs of 8 consecutive p.
-// reduction blocks of job jb (launch sizing)
-__host__ __device__ inline int64_t reduce_blocks(const ReduceJob& jb, int P) {
+// Reduction block blk of job jb, run by the 256 threads t = 0..255 of one block (red: its own
+// 4 x 64 doubles of LDS; every thread of the workgroup must reach this call, it may hold a
+// barrier).  An element set is 64 elements: [64 e, 64 e + 64) for modes 0 and 1, the 8 x 8
+// tile (p, i) in [8 tp, 8 tp + 8) x [8 ti, 8 ti + 8) for mode 2.  out = sum over s of
+// parts[s * count + e], in a fixed order: with more than four partials, a block takes one set
+// and four threads per element sum the partials s = g, g + 4, ... (g = 0..3), the four sums
+// added in the order g = 0, 1, 2, 3; with at most four, a block takes four sets (one per
+// 64-thread group g) and each thread adds its element's partials in the order s = 0, 1, ...,
+// the same sums.  mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower
+// triangle, out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n partials are
+// written transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P), a tile read as
+// 8 runs of 8 consecutive i and written as 8 runs of 8 consecutive p.
+__host__ __device__ inline int64_t reduce_sets(const ReduceJob& jb, int P) {
   if (jb.count <= 0) return 0;
   if (jb.mode == 2) {
     const int64_t n = jb.count / P;
     return (int64_t)((P + 7) / 8) * ((n + 7) / 8);
   }
   return (jb.count + kRedElems - 1) / kRedElems;
+}
+// reduction blocks of job jb (launch sizing)
+__host__ __device__ inline int64_t reduce_blocks(const ReduceJob& jb, int P, int nparts) {
+  const int64_t sets = reduce_sets(jb, P);
+  return nparts <= 4 ? (sets + 3) / 4 : sets;
 }
 
 __device__ __forceinline__ void reduce_block(const ReduceJob& jb, int64_t blk, int nparts, int P, int t,
@@ -34,35 +41,45 @@ __device__ __forceinline__ void reduce_block(const ReduceJob& jb, int64_t blk, i
   const int64_t count = jb.count;
   const int mode = jb.mode;
   const int g = t / kRedElems, el = t % kRedElems;
+  const bool few = nparts <= 4;
+  const int64_t set = few ? 4 * blk + g : blk;  // this thread's element set
+  const bool live = set < reduce_sets(jb, P);
+  const int s0 = few ? 0 : g, ds = few ? 1 : 4;  // partials of this thread: s0, s0 + ds, ...
+  const int row = few ? g : 0;                   // the LDS row its set is read back from
   if (mode == 2) {
     const int64_t n = count / P, tiles_i = (n + 7) / 8;
-    const int64_t tp = blk / tiles_i, ti = blk - tp * tiles_i;
+    const int64_t tp = set / tiles_i, ti = set - tp * tiles_i;
     const int64_t p = 8 * tp + (el >> 3), i = 8 * ti + (el & 7);
     double acc = 0.0;
-    if (p < P && i < n) {
+    if (live && p < P && i < n) {
 #pragma unroll 4
-      for (int s = g; s < nparts; s += 4) acc += parts[s * count + p * n + i];
+      for (int s = s0; s < nparts; s += ds) acc += parts[s * count + p * n + i];
     }
     red[g][el] = acc;
     __syncthreads();
-    if (g == 0) {
+    if (live && (few || g == 0)) {
       const int ep = el & 7, ei = el >> 3;  // element (ep, ei) of the tile, at red index 8 ep + ei
       const int64_t p2 = 8 * tp + ep, i2 = 8 * ti + ei;
       const int e2 = 8 * ep + ei;
-      if (p2 < P && i2 < n) out[i2 * P + p2] = ((red[0][e2] + red[1][e2]) + red[2][e2]) + red[3][e2];
+      if (p2 < P && i2 < n)
+        out[i2 * P + p2] = few ? red[row][e2] : ((red[0][e2] + red[1][e2]) + red[2][e2]) + red[3][e2];
     }
     return;
   }
-  const int64_t e = blk * kRedElems + el;
+  const int64_t e = set * kRedElems + el;
   double acc = 0.0;
-  if (e < count) {
+  if (live && e < count) {
     int64_t src = e;
     if (mode == 1) {
       const int i = (int)(e / P), j = (int)(e % P);
       src = i >= j ? e : (int64_t)j * P + i;
     }
 #pragma unroll 4
-    for (int s = g; s < nparts; s += 4) acc += parts[s * count + src];
+    for (int s = s0; s < nparts; s += ds) acc += parts[s * count + src];
+  }
+  if (few) {
+    if (live && e < count) out[e] = acc;
+    return;
   }
   red[g][el] = acc;
   __syncthreads();
