@@ -17,7 +17,9 @@ constexpr int kRedElems = 64;  // elements per set (a 256-thread block takes one
 // added in the order g = 0, 1, 2, 3; with at most four, a block takes four sets (one per
 // 64-thread group g) and each thread adds its element's partials in the order s = 0, 1, ...,
 // the same sums.  mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower
-// triangle, out(i, j) = sum_s parts_s(max(i, j), min(i, j)).  mode 2: the P x n partials are
+// triangle, out(i, j) = sum_s parts_s(max(i, j), min(i, j)), for the entries its readers (the
+// factorisations: lower 16 x 16 blocks, diagonal blocks whole) use; entries in blocks strictly
+// above the diagonal are not written.  mode 2: the P x n partials are
 // written transposed, out[i * P + p] = sum_s parts_s[p * n + i] (n = count / P), a tile read as
 // 8 runs of 8 consecutive i and written as 8 runs of 8 consecutive p.
 __host__ __device__ inline int64_t reduce_sets(const ReduceJob& jb, int P) {
@@ -67,23 +69,25 @@ __device__ __forceinline__ void reduce_block(const ReduceJob& jb, int64_t blk, i
     return;
   }
   const int64_t e = set * kRedElems + el;
+  bool use = live && e < count;
+  int64_t src = e;
+  if (mode == 1 && use) {
+    const int i = (int)(e / P), j = (int)(e % P);
+    use = j / 16 <= i / 16;
+    src = i >= j ? e : (int64_t)j * P + i;
+  }
   double acc = 0.0;
-  if (live && e < count) {
-    int64_t src = e;
-    if (mode == 1) {
-      const int i = (int)(e / P), j = (int)(e % P);
-      src = i >= j ? e : (int64_t)j * P + i;
-    }
+  if (use) {
 #pragma unroll 4
     for (int s = s0; s < nparts; s += ds) acc += parts[s * count + src];
   }
   if (few) {
-    if (live && e < count) out[e] = acc;
+    if (use) out[e] = acc;
     return;
   }
   red[g][el] = acc;
   __syncthreads();
-  if (g == 0 && e < count) {
+  if (g == 0 && use) {
     out[e] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
   }
 }
