@@ -222,7 +222,8 @@ void plan(const Problem& p, Layout* L) {
   {
     // three-slice sketch (BF16) and its block exponents
     const size_t ld = (size_t)(p.J + kSplitBlock - 1) / kSplitBlock * kSplitBlock;
-    L->S3 = take(p.ne_dt == 3 ? 3 * (size_t)p.Pmax * ld * 2 : 0);
+    // (the BF16 form: its two transposed sketches, rounded from the draw's FP32 rows)
+    L->S3 = take((p.ne_dt == 3 ? 3 : p.ne_dt == 2 && !p.bf16_chains ? 2 : 0) * (size_t)p.Pmax * ld * 2);
     L->E3 = take(p.ne_dt == 3 ? (size_t)p.Pmax * (ld / kSplitBlock) * 4 : 0);
     // the weighted fibers in the same form (the contraction's column operand); for the BF16
     // form the gathered raw BF16 fibers, one slice
@@ -522,7 +523,11 @@ int run_update(trals_ctx* h) {
   da.idx = h->at<int32_t>(h->L.idx);
   da.w = h->at<double>(h->L.w);
   da.A = h->at<void>(h->L.A);
-  if (p.sk_dt == 2) {
+  // the BF16 form's draw writes FP32 rows (rounded and transposed by the gather pass); with the
+  // chain products on BF16 matrix cores it writes the two transposed BF16 sketches itself
+  const bool rows32 = p.sk_dt == 2 && !p.bf16_chains;
+  const int draw_dt = rows32 ? 1 : p.sk_dt;
+  if (p.sk_dt == 2 && !rows32) {
     da.ldt = (Jn + 63) / 64 * 64;
     da.A2 = h->at<char>(h->L.A) + (size_t)P * da.ldt * 2;
   }
@@ -533,7 +538,7 @@ int run_update(trals_ctx* h) {
   da.enumerate = exact ? 1 : 0;
   for (int k = 0; k < N - 1; ++k) da.en_stride[k] = pstride[k];
   PROF_BEGIN(TRALS_K_DRAW);
-  HIPTRY(launch_draw(da, p.sk_dt, h->stream));
+  HIPTRY(launch_draw(da, draw_dt, h->stream));
   if (p.generated) {
     // the sampled fibers of X = TR(G*) + sigma Z: true-core subchain rows for the same
     // indices, then the fibers themselves
@@ -581,7 +586,14 @@ int run_update(trals_ctx* h) {
     na.D3 = h->at<void>(h->L.D3);
     na.ED = h->at<int>(h->L.ED3);
   }
-  if (p.ne_dt == 2) na.D3 = h->at<void>(h->L.D3);
+  if (p.ne_dt == 2) {
+    na.D3 = h->at<void>(h->L.D3);
+    na.ld = (Jn + 63) / 64 * 64;
+    if (rows32) {
+      na.S3 = h->at<__bf16>(h->L.S3);
+      na.x1_rows = 1;
+    }
+  }
   na.panel = p.generated ? h->at<const void>(h->L.Xg) : h->at<const void>(h->L.panel[n]);
   // generated fibers are stored in sample order, and the enumerated rows of Algorithm 1 are the
   // panel's rows: row r of the sketch pairs with fiber row r
@@ -651,7 +663,7 @@ int run_update(trals_ctx* h) {
     int* g = h->redo_word();
     DrawArgs dr = da;
     dr.status = g;
-    HIPTRY(launch_draw(dr, p.sk_dt, h->stream));
+    HIPTRY(launch_draw(dr, draw_dt, h->stream));
     NormalEqArgs nr = na;
     nr.status = g;
     HIPTRY(launch_normal_eq(nr, pl, p.ne_dt, h->stream, nullptr, nullptr));

@@ -79,11 +79,15 @@ struct NormalEqArgs {
   // column, a multiple of 64), with block exponents E[b P + p]; the weighted fibers w_j X(j, i)
   // in the same form, slice s of column i at D3 + (s I_n + i) ld, exponents ED[b I_n + i].
   // launch_normal_eq writes all four (split pass) before the contraction reads them.  The BF16
-  // form uses D3 alone: the gathered raw BF16 fibers, I_n x ld.
+  // form uses D3 for the gathered raw BF16 fibers, I_n x ld, and, with x1_rows, S3 for its two
+  // sketches bf16(w M) and bf16(w^2 M) (P x ld each, one after the other), rounded and
+  // transposed by the gather pass from the FP32 rows A = w M (J x P); without x1_rows the draw
+  // wrote them transposed into A and A2.
   __bf16* S3;
   int* E;
   void* D3;
   int* ED;
+  int x1_rows;
 };
 struct NormalEqPlan {
   int mb;          // row tile = 16 * mb rows of P

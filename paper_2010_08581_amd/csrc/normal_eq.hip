@@ -382,13 +382,41 @@ __global__ __launch_bounds__(256) void k_x3_split(NormalEqArgs a, int sk_tiles) 
 
 // The BF16 form's gather pass: workgroups [0, fb_tiles) gather the raw BF16 fibers of one
 // 64-sample block and 64 columns into D3 (I_n x ld, samples contiguous per column; zero past J),
-// lane (li, q) of wave w taking samples 16 q .. 16 q + 15 of column 16 w + li; the last
-// workgroup zeroes the sketches' columns J .. ld - 1 (row p of bf16(w M) and bf16(w^2 M) at
-// p ld), which the draws do not write.
+// lane (li, q) of wave w taking samples 16 q .. 16 q + 15 of column 16 w + li.  With x1_rows the
+// rest take one 64 x 64 tile each of the FP32 rows A = w M (J x P): S3 gets bf16(w M) and
+// S3 + P ld gets bf16(w^2 M), transposed (zero past J); without, the last workgroup zeroes the
+// columns J .. ld - 1 of the transposed sketches the draw wrote (row p of bf16(w M) and
+// bf16(w^2 M) at p ld), which the draw does not write.
 __global__ __launch_bounds__(256) void k_x1_gather(NormalEqArgs a, int fb_tiles) {
   __shared__ int64_t s_off[kSplitBlock];
   if (*a.status != kDevOk) return;
   const int In = a.In;
+  if ((int)blockIdx.x >= fb_tiles && a.x1_rows) {
+    const int cx = (a.P + 63) / 64, t = (int)blockIdx.x - fb_tiles;
+    const int bx = t % cx, by = t / cx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, q = lane >> 4;
+    const int p = bx * 64 + 16 * wave + li;
+    if (p >= a.P) return;
+    const int64_t j0 = (int64_t)by * kSplitBlock + 16 * q;
+    const float* A = (const float*)a.A;
+    bf8 o1[2], o2[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const bool in = j0 + r < a.J;
+      const float v = in ? A[(j0 + r) * a.P + p] : 0.f;
+      const double w = in ? a.w[j0 + r] : 0.0;
+      o1[r >> 3][r & 7] = (__bf16)v;
+      o2[r >> 3][r & 7] = (__bf16)(w * (double)v);
+    }
+    bf8* d1 = (bf8*)(a.S3 + (int64_t)p * a.ld + j0);
+    bf8* d2 = (bf8*)(a.S3 + ((int64_t)a.P + p) * a.ld + j0);
+    d1[0] = o1[0];
+    d1[1] = o1[1];
+    d2[0] = o2[0];
+    d2[1] = o2[1];
+    return;
+  }
   if ((int)blockIdx.x == fb_tiles) {
     const int pad = (int)(a.ld - a.J);
     __bf16* A = (__bf16*)a.A;
@@ -476,7 +504,10 @@ __device__ __forceinline__ void x3_tile(const NormalEqArgs& a, int s, int row0, 
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
   const int li = lane & 15, lg = lane >> 4;
   __bf16* Ab = (__bf16*)smem;  // [2][NS][RT][kX3Ld]
-  const __bf16* S3 = NS == 3 ? (const __bf16*)a.S3 : GRAM ? (const __bf16*)a.A : (const __bf16*)a.A2;
+  const __bf16* S3 = NS == 3     ? (const __bf16*)a.S3
+                     : a.x1_rows ? (const __bf16*)a.S3 + (GRAM ? 0 : (int64_t)a.P * a.ld)
+                     : GRAM      ? (const __bf16*)a.A
+                                 : (const __bf16*)a.A2;
   const int64_t ld = a.ld, sstride = (int64_t)P * ld;
   const int64_t eb0 = r0 / kSplitBlock;
   // staging of the sketch rows: piece q = (slice, row, 8-sample group)
@@ -795,9 +826,10 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
     const int ns = ne_dtype == 3 ? 3 : 1;
     if (!a.A || !a.D3 || a.ld % kSplitBlock || a.ld < a.J) return hipErrorInvalidValue;
     if (ns == 3 && (!a.S3 || !a.E || !a.ED)) return hipErrorInvalidValue;
-    if (ns == 1 && !a.A2) return hipErrorInvalidValue;
+    if (ns == 1 && (a.x1_rows ? !a.S3 || !a.w : !a.A2)) return hipErrorInvalidValue;
     const int64_t jb = (a.J + kSplitBlock - 1) / kSplitBlock;
-    const int64_t sk = ns == 3 ? (int64_t)((a.P + 63) / 64) * jb : 0, fb = (int64_t)((a.In + 63) / 64) * jb;
+    const int64_t sk = ns == 3 || a.x1_rows ? (int64_t)((a.P + 63) / 64) * jb : 0;
+    const int64_t fb = (int64_t)((a.In + 63) / 64) * jb;
     if (sk + fb + 1 > 0x7fffffff) return hipErrorInvalidValue;
     // the split pass (FP32 path) or the gather pass (BF16 form), then the products
     if (ns == 3) {
@@ -806,10 +838,11 @@ hipError_t launch_normal_eq(const NormalEqArgs& args, const NormalEqPlan& pl, in
       else
         k_x3_split<<<(unsigned)(sk + fb), 256, 0, s>>>(a, (int)sk);
     } else {
+      const unsigned g1 = (unsigned)(fb + (a.x1_rows ? sk : 1));
       if (e0)
-        hipExtLaunchKernelGGL(k_x1_gather, dim3((unsigned)(fb + 1)), dim3(256), 0, s, e0, nullptr, 0, a, (int)fb);
+        hipExtLaunchKernelGGL(k_x1_gather, dim3(g1), dim3(256), 0, s, e0, nullptr, 0, a, (int)fb);
       else
-        k_x1_gather<<<(unsigned)(fb + 1), 256, 0, s>>>(a, (int)fb);
+        k_x1_gather<<<g1, 256, 0, s>>>(a, (int)fb);
     }
     switch (pl.mb * 4 + ns) {
 #define TRALS_NE3_CASE(MB, NS)                                                                     \
