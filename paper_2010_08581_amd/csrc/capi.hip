@@ -621,7 +621,13 @@ int run_update(trals_ctx* h) {
   double* M = h->at<double>(h->L.M);
   double* F = h->at<double>(h->L.F);
   double* Bred = h->at<double>(h->L.Bred);  // I_n x P: row i = b_i
-  const ReduceJob jobH{na.Hpart, (int64_t)P * P, 1, M}, jobB{na.Bpart, (int64_t)P * In, 2, Bred};
+  // large P (a multiple of 16): H is reduced straight into the blocked factorisation's packed
+  // work matrix, which then needs no packing launch
+  const bool prepack = chol_prepack_ok(P);
+  const int64_t packed = (int64_t)((P + 15) / 16) * ((P + 15) / 16 + 1) / 2 * kPackBlk;
+  const ReduceJob jobH = prepack ? ReduceJob{na.Hpart, packed, 3, chol_packed_input(F, P)}
+                                 : ReduceJob{na.Hpart, (int64_t)P * P, 1, M};
+  const ReduceJob jobB{na.Bpart, (int64_t)P * In, 2, Bred};
   // eq. (3): the new core's leverage table.  Its unfolding is G_(2) = B^T H^{-1} (rows z_i =
   // H^{-1} b_i) with H nonsingular, so G_(2) and B^T have the same column space, hence the same
   // rank and the same leverage scores (Definition 4).  When both factorisations fit one
@@ -639,6 +645,7 @@ int run_update(trals_ctx* h) {
   ca.P = P;
   ca.H = M;
   ca.W = F;
+  ca.prepacked = prepack ? 1 : 0;
   ca.status = h->status();
   TriArgs ta;
   memset(&ta, 0, sizeof(ta));

@@ -28,8 +28,8 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLd = 17;         // padded row stride of a 16 x 16 block (doubles)
-constexpr int kBlk = 16 * kLd;  // doubles per stored block
+constexpr int kLd = kPackLd;    // padded row stride of a 16 x 16 block (doubles)
+constexpr int kBlk = kPackBlk;  // doubles per stored block
 constexpr int kLdsBlocks = 9;   // nblk up to which a factor is staged in LDS (45 blocks, 98 KB)
 constexpr int kCholWaves = 8;  // waves per workgroup of the large-P steps
 static_assert(kCholWaves % 4 == 0, "band workgroups split 4, 2 or 1 rows over the waves");
@@ -42,16 +42,6 @@ constexpr size_t kWrowLdsBytes = (size_t)16 * kBlk * sizeof(double);
 static_assert(kRegionLdsBytes + 16384 <= 160 * 1024, "large-P step LDS");
 constexpr int kMaxBlk = 64;     // P <= 1024
 constexpr int kMaxSolveParts = 8;  // workgroups per 16-row group and half of a split solve
-
-__device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
-
-__device__ __forceinline__ void slot_ij(int sl, int& i, int& j) {
-  int r = (int)((sqrtf(8.0f * (float)sl + 1.0f) - 1.0f) * 0.5f);
-  while ((r + 1) * (r + 2) / 2 <= sl) ++r;
-  while (r * (r + 1) / 2 > sl) --r;
-  i = r;
-  j = sl - r * (r + 1) / 2;
-}
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
 // (each step squares the relative error), instead of the longer correctly-rounded sqrt and
@@ -308,7 +298,23 @@ __device__ __forceinline__ bool chol_body(const CholArgs& a) {
   }
   __syncthreads();
   if (kRegion) {
-    if (threadIdx.x == 0) {
+    if (a.prepacked && a.b0 == 0) {
+      // the first step of a matrix a reduction packed (no k_big_init) takes the tolerance from
+      // the largest diagonal entry itself, for the steps after it too
+      if (wave == 0) {
+        double mx = 0.0;
+        for (int i = lane; i < P; i += 64)
+          mx = fmax(mx, a.Lg[(int64_t)slot(i >> 4, i >> 4) * kBlk + (i & 15) * kLd + (i & 15)]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        if (lane == 0) {
+          const double tol = (a.rel_tol > 0.0 ? a.rel_tol : (double)P * 2.220446049250313e-16) * mx;
+          s_tol = tol;
+          a.scal[0] = tol;
+          s_fail = !(mx > 0.0) || !isfinite(mx);
+        }
+      }
+    } else if (threadIdx.x == 0) {
       s_tol = a.scal[0];
       s_fail = 0;
     }
@@ -1255,8 +1261,10 @@ hipError_t launch_chol(const CholArgs& args, hipStream_t s, const ReduceJob* bes
   a.Lp = a.W + 2 * chol_factor_doubles(a.P);
   a.scal = a.W + 3 * chol_factor_doubles(a.P);
   const int nslots = nblk * (nblk + 1) / 2;
-  k_big_init<<<(unsigned)((nslots * kBlk + 255) / 256 < 1024 ? (nslots * kBlk + 255) / 256 : 1024), 256, 0, s>>>(
-      a.H, a.P, a.Lg, a.scal, a.status, a.fail ? a.fail : a.status, a.rel_tol);
+  if (a.prepacked && !chol_prepack_ok(a.P)) return hipErrorInvalidValue;
+  if (!a.prepacked)
+    k_big_init<<<(unsigned)((nslots * kBlk + 255) / 256 < 1024 ? (nslots * kBlk + 255) / 256 : 1024), 256, 0, s>>>(
+        a.H, a.P, a.Lg, a.scal, a.status, a.fail ? a.fail : a.status, a.rel_tol);
   const int nb64 = (nblk + 3) / 4;
   for (int K = 0; K < nb64; ++K) {
     a.b0 = 4 * K;
@@ -1366,6 +1374,9 @@ hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   return launch_lev_fallback(a.G, a.I, a.P, a.qr_work, a.Q, a.fail, a.status, s);
 }
+
+bool chol_prepack_ok(int P) { return !chol_single_workgroup(P) && P % 16 == 0 && (P + 15) / 16 <= kMaxBlk; }
+double* chol_packed_input(double* W, int P) { return W + chol_factor_doubles(P); }
 
 size_t solve_split_doubles(int In, int P) { return (size_t)((In + 15) / 16) * ((P + 15) / 16) * 256; }
 

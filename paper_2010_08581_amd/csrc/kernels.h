@@ -121,7 +121,9 @@ constexpr int kSplitBlock = 64;  // samples per exponent block of the three-slic
 
 // out = fixed-order sum of nparts partial arrays of count doubles.  mode 0: as is; mode 1:
 // symmetrise a P x P matrix from its lower triangle; mode 2: transpose P x (count / P) to
-// (count / P) x P.  Two independent reductions share one launch.
+// (count / P) x P; mode 3: P x P partials (P % 16 == 0, lower triangle read) into the
+// block-packed lower blocks of the symmetric matrix (count = its packed doubles, padding column
+// zero).  Two independent reductions share one launch.
 struct ReduceJob {
   const double* parts;
   int64_t count;
@@ -143,6 +145,19 @@ hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const in
 // block-packed).  A pivot of row k < P at or below the tolerance (rel_tol, or P eps when
 // rel_tol is 0, times the largest diagonal entry of H) is a breakdown: it sets *fail if fail is
 // given (the handle goes on: a table factorisation then falls back), else *status.
+// Block-packed lower-triangular storage of the factorisations: 16 x 16 blocks of kPackLd
+// doubles per row (column 16 is padding), block (i, j), i >= j, at slot i (i + 1) / 2 + j.
+constexpr int kPackLd = 17;
+constexpr int kPackBlk = 16 * kPackLd;
+__host__ __device__ __forceinline__ int slot(int i, int j) { return i * (i + 1) / 2 + j; }
+__device__ __forceinline__ void slot_ij(int sl, int& i, int& j) {
+  int r = (int)((sqrtf(8.0f * (float)sl + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= sl) ++r;
+  while (r * (r + 1) / 2 > sl) --r;
+  i = r;
+  j = sl - r * (r + 1) / 2;
+}
+
 struct CholArgs {
   int P;
   const double* H;  // P x P, row-major (lower triangle and diagonal read)
@@ -152,6 +167,8 @@ struct CholArgs {
   double rel_tol;    // 0: P eps
   int factor_only;   // 1: only the factor's diagonal regions of W are needed (large P: the
                      // off-diagonal bands of W are skipped)
+  int prepacked;     // large P with P % 16 == 0: the work matrix (chol_packed_input(W, P))
+                     // already holds H block-packed; the first step takes the tolerance
   // set by launch_chol for large P: work matrix, panel blocks of L, tolerance, and the diagonal
   // region of a step
   double* Lg;
@@ -167,6 +184,10 @@ size_t chol_work_doubles(int P);    // W plus the staging blocks k_chol uses (si
 // workgroups of the same launch, independent of the factorisation
 hipError_t launch_chol(const CholArgs& a, hipStream_t s, const ReduceJob* beside = nullptr, int nparts = 0);
 bool chol_single_workgroup(int P);  // the factorisation runs as one workgroup (P <= 144)
+// large P: where the blocked factorisation keeps its block-packed work matrix inside W (the
+// destination of a reduction of H in mode 3, CholArgs.prepacked), and whether it may be used
+bool chol_prepack_ok(int P);
+double* chol_packed_input(double* W, int P);
 
 // With inverse factors: solve rows z_i = W^T W b_i of Bsol (In_sol x P) into core (row i), and
 // table weights Q_i = floor(||W g_i||^2 / P * 2^52) of the rows of Blev (In_lev x P, a core

@@ -16,7 +16,8 @@ constexpr int kRedElems = 64;  // elements per set (a 256-thread block takes one
 // and four threads per element sum the partials s = g, g + 4, ... (g = 0..3), the four sums
 // added in the order g = 0, 1, 2, 3; with at most four, a block takes four sets (one per
 // 64-thread group g) and each thread adds its element's partials in the order s = 0, 1, ...,
-// the same sums.  mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower
+// the same sums (mode 3: the partials are P x P each, element e of the output is the packed
+// entry (slot, r, c) of the symmetric matrix, its column 16 zero).  mode 0: out[e] = sum.  mode 1: P x P matrix symmetrised from its lower
 // triangle, out(i, j) = sum_s parts_s(max(i, j), min(i, j)), for the entries its readers (the
 // factorisations: lower 16 x 16 blocks, diagonal blocks whole) use; entries in blocks strictly
 // above the diagonal are not written.  mode 2: the P x n partials are
@@ -70,16 +71,28 @@ __device__ __forceinline__ void reduce_block(const ReduceJob& jb, int64_t blk, i
   }
   const int64_t e = set * kRedElems + el;
   bool use = live && e < count;
-  int64_t src = e;
+  int64_t src = e, stride = count;
   if (mode == 1 && use) {
     const int i = (int)(e / P), j = (int)(e % P);
     use = j / 16 <= i / 16;
     src = i >= j ? e : (int64_t)j * P + i;
   }
+  bool pad = false;
+  if (mode == 3) {
+    stride = (int64_t)P * P;
+    if (use) {
+      int bi, bj;
+      slot_ij((int)(e / kPackBlk), bi, bj);
+      const int rc = (int)(e % kPackBlk), r = rc / kPackLd, c = rc % kPackLd;
+      pad = c == 16;
+      const int i = 16 * bi + r, j = 16 * bj + c;
+      src = i >= j ? (int64_t)i * P + j : (int64_t)j * P + i;
+    }
+  }
   double acc = 0.0;
-  if (use) {
+  if (use && !pad) {
 #pragma unroll 4
-    for (int s = s0; s < nparts; s += ds) acc += parts[s * count + src];
+    for (int s = s0; s < nparts; s += ds) acc += parts[s * stride + src];
   }
   if (few) {
     if (use) out[e] = acc;
