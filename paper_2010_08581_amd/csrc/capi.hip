@@ -392,12 +392,16 @@ int table_launches(trals_ctx* h, int m, const double* G, hipStream_t s) {
   double* M2 = h->at<double>(h->L.M2);
   double* F2 = h->at<double>(h->L.F2);
   if (p.method == TRALS_LEVERAGE && I > P) {
-    HIPTRY(launch_syrk(G, I, P, M2, h->status(), s, /*trans=*/false, h->table_fail()));
+    // a blocked factorisation (P > 144, a multiple of 16) takes the Gram block-packed
+    const bool prepack = chol_prepack_ok(P);
+    HIPTRY(launch_syrk(G, I, P, prepack ? chol_packed_input(F2, P) : M2, h->status(), s, /*trans=*/false,
+                       h->table_fail(), prepack));
     CholArgs ca;
     memset(&ca, 0, sizeof(ca));
     ca.P = P;
     ca.H = M2;
     ca.W = F2;
+    ca.prepacked = prepack ? 1 : 0;
     ca.status = h->status();
     ca.fail = h->table_fail();
     ca.rel_tol = kTableRelTol;

@@ -149,7 +149,7 @@ constexpr int kSyrkWaves = 16;
 template <bool kTrans>
 __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restrict__ A, int64_t rows, int P,
                                                           double* __restrict__ Kout, const int* status,
-                                                          int* clear) {
+                                                          int* clear, int packed) {
   __shared__ double red[kSyrkWaves - 1][4][64];
   if (*status != kDevOk) return;
   if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
@@ -184,7 +184,14 @@ __global__ __launch_bounds__(64 * kSyrkWaves) void k_syrk(const double* __restri
     double v = acc[q];
     for (int w = 0; w < kSyrkWaves - 1; ++w) v += red[w][q][lane];
     const int row = 16 * bi + 4 * q + k4, col = 16 * bj + r16;
-    if (row < P && col < P) Kout[(int64_t)row * P + col] = v;
+    if (packed) {
+      // block-packed (P % 16 == 0): the blocked factorisation's work matrix, padding column zero
+      double* blk = Kout + (int64_t)blockIdx.x * kBlk + (4 * q + k4) * kLd;
+      blk[r16] = v;
+      if (r16 == 0) blk[16] = 0.0;
+    } else if (row < P && col < P) {
+      Kout[(int64_t)row * P + col] = v;
+    }
   }
 }
 
@@ -1221,14 +1228,14 @@ size_t chol_work_doubles(int P) {
 }
 
 hipError_t launch_syrk(const double* A, int64_t rows, int P, double* Kout, const int* status, hipStream_t s,
-                       bool trans, int* clear) {
+                       bool trans, int* clear, bool packed) {
   const int nblk = (P + 15) / 16;
-  if (nblk > kMaxBlk || rows < 1) return hipErrorInvalidValue;
+  if (nblk > kMaxBlk || rows < 1 || (packed && P % 16)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(nblk * (nblk + 1) / 2);
   if (trans)
-    k_syrk<true><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear);
+    k_syrk<true><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear, packed ? 1 : 0);
   else
-    k_syrk<false><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear);
+    k_syrk<false><<<grid, 64 * kSyrkWaves, 0, s>>>(A, rows, P, Kout, status, clear, packed ? 1 : 0);
   return hipGetLastError();
 }
 

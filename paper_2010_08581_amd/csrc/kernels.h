@@ -136,9 +136,11 @@ hipError_t launch_reduce_parts(const ReduceJob& a, const ReduceJob& b, int npart
 // K = A^T A (P x P row-major, lower blocks incl. full diagonal blocks) of an FP64 rows x P
 // matrix A, row-major (trans = false) or column-major (trans = true: then K = G G^T of the
 // row-major P x rows matrix G that A's storage holds).  clear (optional): a word the launch
-// sets to 0 (the failure word of the factorisation that follows).
+// sets to 0 (the failure word of the factorisation that follows).  packed (P % 16 == 0): K is
+// written block-packed instead (kPackBlk doubles per lower block, padding column zero), as the
+// blocked factorisation's work matrix (chol_packed_input, CholArgs.prepacked).
 hipError_t launch_syrk(const double* A, int64_t rows, int P, double* K, const int* status, hipStream_t s,
-                       bool trans = false, int* clear = nullptr);
+                       bool trans = false, int* clear = nullptr, bool packed = false);
 
 // Cholesky factorisation of an SPD P x P matrix H (full storage, lower triangle read,
 // P <= 1024) into the inverse factor W = L^{-1} (chol_factor_doubles(P) doubles,
