@@ -451,14 +451,19 @@ bool table_ahead_applies(const trals_ctx* h, int m) {
   return p.method == TRALS_LEVERAGE && !p.generated && I <= P_of(p, m) && !chol_single_workgroup(I);
 }
 
+// the handle's second stream (default priority) and its fork / join events, made on first use
+hipError_t aux_stream(trals_ctx* h) {
+  if (h->aux) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+  return e;
+}
+
 int table_ahead(trals_ctx* h, int m) {
   const Problem& p = h->p;
   const int I = (int)p.dims[m];
-  if (!h->aux) {
-    HIPTRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-    HIPTRY(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-    HIPTRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-  }
+  HIPTRY(aux_stream(h));
   uint64_t* Q = h->at<uint64_t>(h->L.cdf[m]);
   uint64_t* Qalt = h->at<uint64_t>(h->L.qalt);
   HIPTRY(hipEventRecord(h->ev_fork, h->stream));
@@ -680,6 +685,21 @@ int run_update(trals_ctx* h) {
     HIPTRY(launch_normal_eq(nr, pl, p.ne_dt, h->stream, nullptr, nullptr));
     HIPTRY(launch_reduce_parts(jobH, b_beside ? ReduceJob{nullptr, 0, 2, nullptr} : jobB, pl.splits, P, g, h->stream));
   }
+  // a wide core of at most 144 rows whose update factors H in blocks (P > 144): its row rank
+  // (full: the uniform table) from the rows b_i of B^T (the same rank), checked on the second
+  // stream beside the factorisation of H; a breakdown leaves the table to the new core after
+  // the solve
+  const bool wide_beside = p.method == TRALS_LEVERAGE && !p.generated && !pair && In <= P &&
+                           chol_single_workgroup(In) && !chol_single_workgroup(P);
+  if (wide_beside) {
+    HIPTRY(aux_stream(h));
+    HIPTRY(hipEventRecord(h->ev_fork, h->stream));
+    HIPTRY(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    LevWideArgs lb = wide_table_args(h, n, Bred);
+    lb.qr_work = nullptr;  // the breakdown word only
+    HIPTRY(launch_lev_wide(lb, h->aux));
+    HIPTRY(hipEventRecord(h->ev_join, h->aux));
+  }
   if (pair) {
     CholArgs ck;
     memset(&ck, 0, sizeof(ck));
@@ -721,6 +741,15 @@ int run_update(trals_ctx* h) {
   PROF_BEGIN(TRALS_K_SOLVE);
   HIPTRY(launch_trisolve(ta, h->stream));
   PROF_END(TRALS_K_SOLVE);
+  if (wide_beside) {
+    PROF_BEGIN(TRALS_K_TABLE);
+    HIPTRY(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    LevWideArgs lf = wide_table_args(h, n, h->at<const double>(h->L.core[n]));
+    lf.run_if = h->table_fail();  // only after a breakdown of the check from B^T
+    HIPTRY(launch_lev_wide(lf, h->stream));
+    if (!p.tables_as_weights) HIPTRY(launch_scan_u64(Qn, In, h->status(), h->stream));
+    PROF_END(TRALS_K_TABLE);
+  }
   if (pair && !p.tables_as_weights) {
     PROF_BEGIN(TRALS_K_TABLE);
     HIPTRY(launch_scan_u64(Qn, In, h->status(), h->stream));
@@ -734,7 +763,7 @@ int run_update(trals_ctx* h) {
                         h->at<double>(h->L.gauge), h->status(), h->stream));
     PROF_END(TRALS_K_SOLVE);
   }
-  if (pair) {
+  if (pair || wide_beside) {
     h->table_valid[n] = true;
   } else if (table_ahead_applies(h, n)) {
     const int rc = table_ahead(h, n);  // checked beside the next update

@@ -1099,7 +1099,7 @@ template <int kW>
 __device__ __forceinline__ void lev_wide_body(const LevWideArgs& a, const CholArgs& ca) {
   extern __shared__ double lw_smem[];
   __shared__ int s_wide_fail;
-  if (*a.status != kDevOk) return;
+  if (*a.status != kDevOk || (a.run_if && *a.run_if == 0)) return;
   const int I = a.I, P = a.P;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loops
   const int r16 = lane & 15, k4 = lane >> 4;

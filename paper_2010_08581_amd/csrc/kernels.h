@@ -240,6 +240,7 @@ struct LevWideArgs {
   int* status;
   int* fail;
   double rel_tol;
+  const int* run_if;  // optional: the launch does nothing unless *run_if != 0
 };
 hipError_t launch_lev_wide(const LevWideArgs& a, hipStream_t s);
 // table from *fail: uniform (1/I) if it is clear, else the pivoted QR of G (one workgroup)

@@ -115,18 +115,22 @@ def test_degenerate_core_tables_match_oracle(name, dims, ranks, mutate, start, J
     say(f"{name}: worst slice {worst:.3e}")
 
 
+@pytest.mark.parametrize("rows", [200, 100], ids=["200 rows", "100 rows"])
 @pytest.mark.parametrize("dup", [False, True], ids=["full rank", "two equal slices"])
-def test_wide_table_checked_beside_next_update(dup):
-    # A 200 x 256 wide core (past the single-workgroup factorisation): its table is written
-    # uniform at once and its rank checked beside the next update's draws, within one call.
-    # With two equal slices of X along mode 0, the new core 0 has two equal rows (rank 199): the
-    # check breaks down, the pivoted-QR table replaces the uniform one, and update 1 must repeat
-    # its draws and contraction from it.  Update 1 is compared with the oracle's update from the
-    # GPU's new core 0 (indices bit for bit).
+def test_wide_table_checked_beside_next_update(dup, rows):
+    # A wide core at P = 256 (H factored in blocks).  With 200 rows (past the single-workgroup
+    # factorisation) its table is written uniform at once and its rank checked beside the next
+    # update's draws, within one call; with 100 rows the rank is checked from the rows of B^T
+    # beside the factorisation of H, and the new core's own table follows the solve only if that
+    # check breaks down.  With two equal slices of X along mode 0, the new core 0 has two equal
+    # rows (rank rows - 1): the checks break down, the pivoted-QR table is taken (for 200 rows
+    # replacing the uniform one, so that update 1 repeats its draws and contraction from it).
+    # Update 1 is compared with the oracle's update from the GPU's new core 0 (indices bit for
+    # bit).
     from oracle import als as oals
     from paper_2010_08581_amd import TRALS
     from tests.gpu_helpers import assert_core_close, to_np
-    dims, ranks, J = (200, 20, 20), (16, 16, 16), 600
+    dims, ranks, J = (rows, 20, 20), (16, 16, 16), 600
     say(f"case: table beside the next update, dims {dims} ranks {ranks} J={J}, equal slices {dup}")
     X = rng_for(91, 0).standard_normal(dims)
     if dup:
