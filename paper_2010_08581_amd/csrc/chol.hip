@@ -559,7 +559,9 @@ __global__ __launch_bounds__(64 * kW) void k_chol_reduce(CholArgs a, ReduceJob j
 // and only the last band after the factorisation.
 
 // Lg <- H in blocks (identity on the padded diagonal); scal[0] <- tol max_i H_ii (tol = rel_tol,
-// or P eps when rel_tol is 0); a zero or non-finite diagonal is a breakdown (*fail_out)
+// or P eps when rel_tol is 0); a zero or non-finite diagonal is a breakdown (*fail_out).  Not
+// launched when the producer of H wrote Lg itself (CholArgs.prepacked: the first step then sets
+// scal[0] and checks the diagonal).
 __global__ __launch_bounds__(256) void k_big_init(const double* __restrict__ H, int P, double* __restrict__ Lg,
                                                   double* scal, const int* status, int* fail_out, double rel_tol) {
   if (*status != kDevOk) return;
